@@ -1,0 +1,1098 @@
+/*
+ * dic_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain serial CPU reference for frequent itemset mining (Zymbler, "Parallel
+ * Algorithm for Frequent Itemset Mining on Intel Many-core Systems").  Only
+ * the test suite, the smoke check and the benchmark's CPU-baseline leg may
+ * use it.  It shares no code with the GPU library.
+ *
+ * What each function follows:
+ *   oracle_tau          -- Section 1: support is a fraction of transactions;
+ *                          the integer threshold is the smallest count that
+ *                          reaches it (reading: ceil with a near-integer guard).
+ *   oracle_dic          -- Section 4.2: Algorithm 2 (driver), FirstPass (full
+ *                          first pass, pairs of frequent items), Algorithm 3
+ *                          (CountSupport), Algorithm 4 (Prune), MakeCandidates
+ *                          (join of boxes by bitwise OR, no pseudocode in the
+ *                          paper) and Algorithm 5 (CheckFullPass), in that
+ *                          order at every stop; Section 3 for the four sets
+ *                          and the stop/rewind schedule.
+ *   oracle_apriori      -- Section 3: level-wise Apriori (join, a-priori
+ *                          prune, count), an independent cross-check.
+ *   oracle_bruteforce / oracle_tidlist -- the problem statement of Section 1
+ *                          written out (every itemset, or a depth-first walk
+ *                          that stops where support falls below threshold,
+ *                          which is exact because support is anti-monotone).
+ *
+ * Everything is integer except minsup, which becomes the integer threshold
+ * once.  No parallelism, no blocking, no layout tricks.
+ */
+#include "dic_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+struct or_result {
+    uint32_t W;
+    uint64_t size;
+    uint64_t *masks;  /* size * W */
+    uint32_t *counts; /* size */
+    or_stats stats;
+    or_stop *trace;
+    uint64_t trace_len;
+};
+
+/* ------------------------------------------------------------------------ */
+/* threshold                                                                 */
+/* ------------------------------------------------------------------------ */
+
+int oracle_tau(double minsup, uint64_t n, uint64_t *tau)
+{
+    if (!tau || n == 0 || !(minsup > 0.0)) /* NaN fails the comparison too */
+        return OR_E_INVAL;
+    double x = minsup * (double)n;
+    uint64_t t;
+    if (!(x < 9007199254740992.0)) { /* 2^53 and beyond, or +inf */
+        t = n + 1;
+    } else {
+        double r = nearbyint(x);
+        double scale = x > 1.0 ? x : 1.0;
+        if (fabs(x - r) <= 1e-9 * scale)
+            t = (uint64_t)r;
+        else
+            t = (uint64_t)ceil(x);
+    }
+    if (t > n + 1)
+        t = n + 1; /* nothing can reach it; keep the value bounded */
+    if (t < 1)
+        t = 1;
+    *tau = t;
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* itemset helpers                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* I is contained in T: BitMask(I) AND BitMask(T) = BitMask(I) (Section 4.1). */
+static int is_subset(const uint64_t *I, const uint64_t *T, uint32_t W)
+{
+    for (uint32_t w = 0; w < W; ++w)
+        if ((I[w] & T[w]) != I[w])
+            return 0;
+    return 1;
+}
+
+static uint32_t n_items(const uint64_t *I, uint32_t W)
+{
+    uint32_t k = 0;
+    for (uint32_t w = 0; w < W; ++w)
+        k += (uint32_t)__builtin_popcountll(I[w]);
+    return k;
+}
+
+static int has_item(const uint64_t *I, uint32_t p) { return (int)((I[p >> 6] >> (p & 63)) & 1u); }
+
+/* Canonical order: size ascending, then ascending item lists lexicographic. */
+static uint32_t canon_W;
+static const uint64_t *canon_masks;
+static int canon_cmp(const void *pa, const void *pb)
+{
+    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    const uint64_t *A = canon_masks + a * canon_W, *B = canon_masks + b * canon_W;
+    uint32_t ka = n_items(A, canon_W), kb = n_items(B, canon_W);
+    if (ka != kb)
+        return ka < kb ? -1 : 1;
+    /* walk both item lists in ascending order; first difference decides */
+    uint32_t wa = 0, wb = 0;
+    uint64_t xa = A[0], xb = B[0];
+    for (uint32_t i = 0; i < ka; ++i) {
+        while (xa == 0) xa = A[++wa];
+        while (xb == 0) xb = B[++wb];
+        uint32_t ia = wa * 64u + (uint32_t)__builtin_ctzll(xa);
+        uint32_t ib = wb * 64u + (uint32_t)__builtin_ctzll(xb);
+        if (ia != ib)
+            return ia < ib ? -1 : 1;
+        xa &= xa - 1;
+        xb &= xb - 1;
+    }
+    return 0;
+}
+
+/* Build a result from q itemsets (masks q*W, counts q), sorting canonically. */
+static int make_result(uint32_t W, uint64_t q, const uint64_t *masks, const uint32_t *counts,
+                       or_result **out)
+{
+    or_result *r = (or_result *)calloc(1, sizeof(*r));
+    if (!r)
+        return OR_E_NOMEM;
+    r->W = W;
+    r->size = q;
+    r->masks = (uint64_t *)malloc((q ? q : 1) * W * sizeof(uint64_t));
+    r->counts = (uint32_t *)malloc((q ? q : 1) * sizeof(uint32_t));
+    uint64_t *perm = (uint64_t *)malloc((q ? q : 1) * sizeof(uint64_t));
+    if (!r->masks || !r->counts || !perm) {
+        free(perm);
+        oracle_result_free(r);
+        return OR_E_NOMEM;
+    }
+    for (uint64_t i = 0; i < q; ++i)
+        perm[i] = i;
+    canon_W = W;
+    canon_masks = masks;
+    qsort(perm, q, sizeof(uint64_t), canon_cmp);
+    uint64_t kmax = 0;
+    for (uint64_t i = 0; i < q; ++i) {
+        memcpy(r->masks + i * W, masks + perm[i] * W, W * sizeof(uint64_t));
+        r->counts[i] = counts[perm[i]];
+        uint64_t k = n_items(masks + perm[i] * W, W);
+        if (k > kmax)
+            kmax = k;
+    }
+    free(perm);
+    r->stats.n_frequent = q;
+    r->stats.k_max = kmax;
+    *out = r;
+    return OR_OK;
+}
+
+static int check_db(const uint64_t *rows, uint64_t n, uint32_t m)
+{
+    if (!rows || n == 0 || m == 0 || n >= 0xFFFFFFFFull)
+        return OR_E_INVAL;
+    uint32_t W = (m + 63u) / 64u;
+    uint32_t tail = m & 63u;
+    if (tail) {
+        uint64_t pad = ~((1ull << tail) - 1ull);
+        for (uint64_t r = 0; r < n; ++r)
+            if (rows[r * W + W - 1] & pad)
+                return OR_E_INVAL;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* growable arrays                                                           */
+/* ------------------------------------------------------------------------ */
+
+static int grow(void **p, uint64_t *cap, uint64_t need, size_t elem)
+{
+    if (need <= *cap)
+        return 1;
+    uint64_t c = *cap ? *cap : 64;
+    while (c < need)
+        c *= 2;
+    void *q = realloc(*p, c * elem);
+    if (!q)
+        return 0;
+    *p = q;
+    *cap = c;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* KNOWN: every itemset ever created, with its current standing              */
+/* ------------------------------------------------------------------------ */
+
+enum { K_EMPTY = 0, K_CIRCLE = 1, K_BOX = 2, K_INFREQUENT = 3 };
+
+typedef struct {
+    uint32_t W;
+    uint64_t cap, used;
+    uint64_t *keys;
+    uint8_t *state;
+} known_map;
+
+static uint64_t fnv1a(const uint64_t *key, uint32_t W)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (uint32_t w = 0; w < W; ++w)
+        for (int b = 0; b < 8; ++b) {
+            h ^= (key[w] >> (8 * b)) & 0xFFu;
+            h *= 1099511628211ull;
+        }
+    return h;
+}
+
+static int known_init(known_map *k, uint32_t W, uint64_t cap)
+{
+    uint64_t c = 1024;
+    while (c < cap)
+        c *= 2;
+    k->W = W;
+    k->cap = c;
+    k->used = 0;
+    k->keys = (uint64_t *)calloc(c * W, sizeof(uint64_t));
+    k->state = (uint8_t *)calloc(c, 1);
+    return k->keys && k->state;
+}
+
+static void known_free(known_map *k)
+{
+    free(k->keys);
+    free(k->state);
+}
+
+static uint64_t known_slot(const known_map *k, const uint64_t *key)
+{
+    uint64_t s = fnv1a(key, k->W) & (k->cap - 1);
+    while (k->state[s] != K_EMPTY && memcmp(k->keys + s * k->W, key, k->W * sizeof(uint64_t)))
+        s = (s + 1) & (k->cap - 1);
+    return s;
+}
+
+static int known_get(const known_map *k, const uint64_t *key)
+{
+    return k->state[known_slot(k, key)];
+}
+
+static int known_set(known_map *k, const uint64_t *key, int st)
+{
+    if (2 * (k->used + 1) > k->cap) {
+        known_map bigger;
+        if (!known_init(&bigger, k->W, 2 * k->cap))
+            return 0;
+        for (uint64_t s = 0; s < k->cap; ++s)
+            if (k->state[s] != K_EMPTY) {
+                uint64_t t = known_slot(&bigger, k->keys + s * k->W);
+                memcpy(bigger.keys + t * k->W, k->keys + s * k->W, k->W * sizeof(uint64_t));
+                bigger.state[t] = k->state[s];
+                bigger.used++;
+            }
+        known_free(k);
+        *k = bigger;
+    }
+    uint64_t s = known_slot(k, key);
+    if (k->state[s] == K_EMPTY) {
+        memcpy(k->keys + s * k->W, key, k->W * sizeof(uint64_t));
+        k->used++;
+    }
+    k->state[s] = (uint8_t)st;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dynamic Itemset Counting                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* The itemset record of Section 4.1: mask, k, stop, supp, shape. */
+enum { SHAPE_NIL = 0, SHAPE_CIRCLE = 1, SHAPE_BOX = 2 };
+
+typedef struct {
+    uint64_t off; /* mask = arena[off .. off+W) */
+    uint32_t k;
+    uint64_t stop;
+    uint64_t supp;
+    int shape;
+} rec;
+
+typedef struct {
+    uint32_t W;
+    uint64_t *arena;
+    uint64_t arena_n, arena_cap;
+    rec *dashed;
+    uint64_t nd, capd;
+    rec *solid;
+    uint64_t ns, caps;
+    known_map known;
+} dic_state;
+
+static int new_mask(dic_state *S, const uint64_t *mask, uint64_t *off)
+{
+    if (!grow((void **)&S->arena, &S->arena_cap, S->arena_n + S->W, sizeof(uint64_t)))
+        return 0;
+    memcpy(S->arena + S->arena_n, mask, S->W * sizeof(uint64_t));
+    *off = S->arena_n;
+    S->arena_n += S->W;
+    return 1;
+}
+
+static int push_rec(rec **v, uint64_t *n, uint64_t *cap, rec r)
+{
+    if (!grow((void **)v, cap, *n + 1, sizeof(rec)))
+        return 0;
+    (*v)[(*n)++] = r;
+    return 1;
+}
+
+/* every maximal proper subset of C is a box (dashed or solid) */
+static int all_subsets_boxes(dic_state *S, const uint64_t *C, uint64_t *tmp)
+{
+    uint32_t W = S->W;
+    for (uint32_t w = 0; w < W; ++w) {
+        uint64_t x = C[w];
+        while (x) {
+            uint64_t low = x & (~x + 1);
+            memcpy(tmp, C, W * sizeof(uint64_t));
+            tmp[w] &= ~low;
+            if (known_get(&S->known, tmp) != K_BOX)
+                return 0;
+            x &= x - 1;
+        }
+    }
+    return 1;
+}
+
+/* Insert candidate C into DASHED as a dashed circle (supp 0, stop 0). */
+static int add_candidate(dic_state *S, const uint64_t *C, uint32_t k)
+{
+    rec r;
+    if (!new_mask(S, C, &r.off))
+        return 0;
+    r.k = k;
+    r.stop = 0;
+    r.supp = 0;
+    r.shape = SHAPE_CIRCLE;
+    if (!push_rec(&S->dashed, &S->nd, &S->capd, r))
+        return 0;
+    return known_set(&S->known, C, K_CIRCLE);
+}
+
+static void erase_nil(rec *v, uint64_t *n)
+{
+    uint64_t j = 0;
+    for (uint64_t i = 0; i < *n; ++i)
+        if (v[i].shape != SHAPE_NIL)
+            v[j++] = v[i];
+    *n = j;
+}
+
+static void dic_state_free(dic_state *S)
+{
+    free(S->arena);
+    free(S->dashed);
+    free(S->solid);
+    known_free(&S->known);
+}
+
+int oracle_dic(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, uint64_t M,
+               int candgen_mode, or_result **out)
+{
+    if (!out)
+        return OR_E_INVAL;
+    *out = NULL;
+    int rc = check_db(rows, n, m);
+    if (rc)
+        return rc;
+    if (M == 0 || (candgen_mode != 0 && candgen_mode != 1))
+        return OR_E_INVAL;
+    uint64_t tau;
+    if ((rc = oracle_tau(minsup, n, &tau)))
+        return rc;
+
+    const uint32_t W = (m + 63u) / 64u;
+    const uint64_t Mp = M < n ? M : n;         /* a block never exceeds the database */
+    const uint64_t stop_max = (n + Mp - 1) / Mp; /* Algorithm 2: ceil(n / M) */
+
+    dic_state S;
+    memset(&S, 0, sizeof(S));
+    S.W = W;
+    or_stop *trace = NULL;
+    uint64_t ntrace = 0, captrace = 0;
+    uint64_t *newb = NULL, nnew = 0, capnew = 0; /* arena offsets of new boxes */
+    uint32_t *L1 = NULL;
+    uint64_t nL1 = 0;
+    uint64_t *C = (uint64_t *)calloc(W, sizeof(uint64_t));
+    uint64_t *tmp = (uint64_t *)calloc(W, sizeof(uint64_t));
+    or_stats st;
+    memset(&st, 0, sizeof(st));
+    rc = OR_E_NOMEM;
+    if (!C || !tmp || !known_init(&S.known, W, 4096))
+        goto done;
+
+    /* Algorithm 2, initialisation: every 1-itemset goes to SOLID. */
+    for (uint32_t i = 0; i < m; ++i) {
+        memset(C, 0, W * sizeof(uint64_t));
+        C[i >> 6] = 1ull << (i & 63);
+        rec r;
+        if (!new_mask(&S, C, &r.off))
+            goto done;
+        r.k = 1;
+        r.stop = 0;
+        r.supp = 0;
+        r.shape = SHAPE_NIL;
+        if (!push_rec(&S.solid, &S.ns, &S.caps, r))
+            goto done;
+    }
+
+    /* FirstPass: one full pass over the database counts every 1-itemset. */
+    {
+        uint64_t *cnt = (uint64_t *)calloc(m, sizeof(uint64_t));
+        if (!cnt)
+            goto done;
+        for (uint64_t t = 0; t < n; ++t)
+            for (uint32_t i = 0; i < m; ++i)
+                if (has_item(rows + t * W, i))
+                    cnt[i]++;
+        L1 = (uint32_t *)malloc((m ? m : 1) * sizeof(uint32_t));
+        if (!L1) {
+            free(cnt);
+            goto done;
+        }
+        for (uint32_t i = 0; i < m; ++i) {
+            rec *r = &S.solid[i];
+            r->supp = cnt[i];
+            r->stop = stop_max;
+            r->shape = cnt[i] >= tau ? SHAPE_BOX : SHAPE_CIRCLE;
+            if (!known_set(&S.known, S.arena + r->off, r->shape == SHAPE_BOX ? K_BOX : K_CIRCLE)) {
+                free(cnt);
+                goto done;
+            }
+            if (r->shape == SHAPE_BOX)
+                L1[nL1++] = i;
+        }
+        free(cnt);
+        /* candidate 2-itemsets: bitwise OR of every pair of frequent items */
+        for (uint64_t a = 0; a < nL1; ++a)
+            for (uint64_t b = a + 1; b < nL1; ++b) {
+                memset(C, 0, W * sizeof(uint64_t));
+                C[L1[a] >> 6] |= 1ull << (L1[a] & 63);
+                C[L1[b] >> 6] |= 1ull << (L1[b] & 63);
+                if (!add_candidate(&S, C, 2))
+                    goto done;
+            }
+    }
+
+    /* Algorithm 2, main loop: one iteration per stop until DASHED is empty. */
+    uint64_t stop = 0;
+    while (S.nd > 0) {
+        /* scan the next block, rewinding after the last one */
+        stop = stop + 1;
+        if (stop > stop_max)
+            stop = 1;
+        uint64_t first = (stop - 1) * Mp;
+        uint64_t last = stop * Mp < n ? stop * Mp : n; /* exclusive */
+        or_stop tr;
+        memset(&tr, 0, sizeof(tr));
+        tr.stop = (uint32_t)stop;
+        tr.rows = (uint32_t)(last - first);
+        tr.live = S.nd;
+        st.stops++;
+        st.tests += S.nd * (last - first);
+        if (S.nd > st.peak_live)
+            st.peak_live = S.nd;
+
+        /* Algorithm 3, CountSupport: itemsets outer, transactions inner. */
+        for (uint64_t d = 0; d < S.nd; ++d) {
+            rec *I = &S.dashed[d];
+            I->stop = I->stop + 1;
+            const uint64_t *mask = S.arena + I->off;
+            for (uint64_t t = first; t < last; ++t)
+                if (is_subset(mask, rows + t * W, W))
+                    I->supp = I->supp + 1;
+        }
+
+        /* Algorithm 4, Prune: promote circles that reached the threshold;
+         * erase circles whose best possible support cannot reach it, together
+         * with every dashed-circle superset. */
+        nnew = 0;
+        for (uint64_t d = 0; d < S.nd; ++d) {
+            rec *I = &S.dashed[d];
+            if (I->shape != SHAPE_CIRCLE)
+                continue;
+            if (I->supp >= tau) {
+                I->shape = SHAPE_BOX;
+                tr.promoted++;
+                if (!known_set(&S.known, S.arena + I->off, K_BOX))
+                    goto done;
+                if (!grow((void **)&newb, &capnew, nnew + 1, sizeof(uint64_t)))
+                    goto done;
+                newb[nnew++] = I->off;
+            } else {
+                uint64_t supp_max = I->supp + Mp * (stop_max - I->stop);
+                if (supp_max < tau) {
+                    I->shape = SHAPE_NIL;
+                    tr.pruned++;
+                    if (!known_set(&S.known, S.arena + I->off, K_INFREQUENT))
+                        goto done;
+                    for (uint64_t e = 0; e < S.nd; ++e) {
+                        rec *J = &S.dashed[e];
+                        if (e != d && J->shape == SHAPE_CIRCLE &&
+                            is_subset(S.arena + I->off, S.arena + J->off, W)) {
+                            J->shape = SHAPE_NIL;
+                            st.superset_prunes++;
+                            tr.pruned++;
+                            if (!known_set(&S.known, S.arena + J->off, K_INFREQUENT))
+                                goto done;
+                        }
+                    }
+                }
+            }
+        }
+        erase_nil(S.dashed, &S.nd);
+
+        /* MakeCandidates: join of boxes by bitwise OR.  A candidate C is
+         * admitted when it is new and all its maximal proper subsets are
+         * boxes. */
+        if (candgen_mode == 0) {
+            for (uint64_t q = 0; q < nnew; ++q) {
+                uint32_t ks = 0;
+                for (uint64_t a = 0; a < nL1; ++a) {
+                    memcpy(C, S.arena + newb[q], W * sizeof(uint64_t));
+                    if (a == 0)
+                        ks = n_items(C, W);
+                    uint32_t i = L1[a];
+                    if (has_item(C, i))
+                        continue;
+                    C[i >> 6] |= 1ull << (i & 63);
+                    if (known_get(&S.known, C) != K_EMPTY)
+                        continue;
+                    if (!all_subsets_boxes(&S, C, tmp))
+                        continue;
+                    if (!add_candidate(&S, C, ks + 1))
+                        goto done;
+                    tr.generated++;
+                }
+            }
+        } else {
+            /* gather every box (solid first, then dashed) and OR all pairs */
+            uint64_t *boxes = NULL, nb = 0, capb = 0;
+            for (uint64_t i = 0; i < S.ns; ++i)
+                if (S.solid[i].shape == SHAPE_BOX) {
+                    if (!grow((void **)&boxes, &capb, nb + 1, sizeof(uint64_t))) {
+                        free(boxes);
+                        goto done;
+                    }
+                    boxes[nb++] = S.solid[i].off;
+                }
+            for (uint64_t i = 0; i < S.nd; ++i)
+                if (S.dashed[i].shape == SHAPE_BOX) {
+                    if (!grow((void **)&boxes, &capb, nb + 1, sizeof(uint64_t))) {
+                        free(boxes);
+                        goto done;
+                    }
+                    boxes[nb++] = S.dashed[i].off;
+                }
+            for (uint64_t a = 0; a < nb; ++a) {
+                uint32_t ka = n_items(S.arena + boxes[a], W);
+                for (uint64_t b = a + 1; b < nb; ++b) {
+                    const uint64_t *A = S.arena + boxes[a], *B = S.arena + boxes[b];
+                    if (n_items(B, W) != ka)
+                        continue;
+                    for (uint32_t w = 0; w < W; ++w)
+                        C[w] = A[w] | B[w];
+                    if (n_items(C, W) != ka + 1)
+                        continue;
+                    if (known_get(&S.known, C) != K_EMPTY)
+                        continue;
+                    if (!all_subsets_boxes(&S, C, tmp))
+                        continue;
+                    if (!add_candidate(&S, C, ka + 1)) {
+                        free(boxes);
+                        goto done;
+                    }
+                    tr.generated++;
+                }
+            }
+            free(boxes);
+        }
+
+        /* Algorithm 5, CheckFullPass: itemsets counted over a full pass
+         * become solid; a box if their support reached the threshold. */
+        for (uint64_t d = 0; d < S.nd; ++d) {
+            rec *I = &S.dashed[d];
+            if (I->stop == stop_max) {
+                if (I->supp >= tau) {
+                    if (I->shape == SHAPE_CIRCLE) {
+                        st.fullpass_promotions++;
+                        if (!known_set(&S.known, S.arena + I->off, K_BOX))
+                            goto done;
+                    }
+                    I->shape = SHAPE_BOX;
+                }
+                if (!push_rec(&S.solid, &S.ns, &S.caps, *I))
+                    goto done;
+                I->shape = SHAPE_NIL;
+                tr.solidified++;
+            }
+        }
+        erase_nil(S.dashed, &S.nd);
+
+        if (!grow((void **)&trace, &captrace, ntrace + 1, sizeof(or_stop)))
+            goto done;
+        trace[ntrace++] = tr;
+    }
+
+    /* L = the boxes in SOLID */
+    {
+        uint64_t q = 0;
+        for (uint64_t i = 0; i < S.ns; ++i)
+            q += S.solid[i].shape == SHAPE_BOX;
+        uint64_t *masks = (uint64_t *)malloc((q ? q : 1) * W * sizeof(uint64_t));
+        uint32_t *counts = (uint32_t *)malloc((q ? q : 1) * sizeof(uint32_t));
+        if (!masks || !counts) {
+            free(masks);
+            free(counts);
+            goto done;
+        }
+        q = 0;
+        for (uint64_t i = 0; i < S.ns; ++i)
+            if (S.solid[i].shape == SHAPE_BOX) {
+                memcpy(masks + q * W, S.arena + S.solid[i].off, W * sizeof(uint64_t));
+                counts[q] = (uint32_t)S.solid[i].supp;
+                q++;
+            }
+        or_result *r = NULL;
+        rc = make_result(W, q, masks, counts, &r);
+        free(masks);
+        free(counts);
+        if (rc)
+            goto done;
+        st.n_frequent = r->stats.n_frequent;
+        st.k_max = r->stats.k_max;
+        st.tau = tau;
+        st.block = Mp;
+        st.stop_max = stop_max;
+        st.known = S.known.used;
+        r->stats = st;
+        r->trace = trace;
+        r->trace_len = ntrace;
+        trace = NULL;
+        *out = r;
+        rc = OR_OK;
+    }
+
+done:
+    free(trace);
+    free(newb);
+    free(L1);
+    free(C);
+    free(tmp);
+    dic_state_free(&S);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Apriori (independent cross-check)                                         */
+/* ------------------------------------------------------------------------ */
+
+/* itemsets of one level as sorted item arrays, row-major [count][k] */
+typedef struct {
+    uint32_t k;
+    uint64_t count, cap;
+    uint32_t *items;
+    uint64_t *supp;
+} level;
+
+static int level_push(level *L, const uint32_t *items)
+{
+    if (L->count == L->cap) {
+        uint64_t c = L->cap ? 2 * L->cap : 256;
+        uint32_t *it = (uint32_t *)realloc(L->items, c * L->k * sizeof(uint32_t));
+        if (!it)
+            return 0;
+        L->items = it;
+        uint64_t *sp = (uint64_t *)realloc(L->supp, c * sizeof(uint64_t));
+        if (!sp)
+            return 0;
+        L->supp = sp;
+        L->cap = c;
+    }
+    memcpy(L->items + L->count * L->k, items, L->k * sizeof(uint32_t));
+    L->supp[L->count] = 0;
+    L->count++;
+    return 1;
+}
+
+static int lex_cmp(const uint32_t *a, const uint32_t *b, uint32_t k)
+{
+    for (uint32_t i = 0; i < k; ++i)
+        if (a[i] != b[i])
+            return a[i] < b[i] ? -1 : 1;
+    return 0;
+}
+
+static int level_contains(const level *L, const uint32_t *items)
+{
+    uint64_t lo = 0, hi = L->count;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) / 2;
+        int c = lex_cmp(L->items + mid * L->k, items, L->k);
+        if (c == 0)
+            return 1;
+        if (c < 0)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return 0;
+}
+
+int oracle_apriori(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, or_result **out)
+{
+    if (!out)
+        return OR_E_INVAL;
+    *out = NULL;
+    int rc = check_db(rows, n, m);
+    if (rc)
+        return rc;
+    uint64_t tau;
+    if ((rc = oracle_tau(minsup, n, &tau)))
+        return rc;
+    const uint32_t W = (m + 63u) / 64u;
+    rc = OR_E_NOMEM;
+
+    unsigned char *present = (unsigned char *)calloc(m, 1);
+    uint32_t *buf = (uint32_t *)malloc((m + 1) * sizeof(uint32_t));
+    uint64_t *all_masks = NULL, nall = 0, capm = 0;
+    uint32_t *all_counts = NULL;
+    uint64_t capc = 0;
+    level prev = {1, 0, 0, NULL, NULL}, cur = {0, 0, 0, NULL, NULL};
+    if (!present || !buf)
+        goto done;
+
+    /* level 1 */
+    {
+        uint64_t *cnt = (uint64_t *)calloc(m, sizeof(uint64_t));
+        if (!cnt)
+            goto done;
+        for (uint64_t t = 0; t < n; ++t)
+            for (uint32_t i = 0; i < m; ++i)
+                if ((rows[t * W + (i >> 6)] >> (i & 63)) & 1u)
+                    cnt[i]++;
+        for (uint32_t i = 0; i < m; ++i)
+            if (cnt[i] >= tau) {
+                if (!level_push(&prev, &i)) {
+                    free(cnt);
+                    goto done;
+                }
+                prev.supp[prev.count - 1] = cnt[i];
+            }
+        free(cnt);
+    }
+
+    for (;;) {
+        /* emit the frequent itemsets of this level */
+        for (uint64_t c = 0; c < prev.count; ++c) {
+            if (!grow((void **)&all_masks, &capm, (nall + 1) * W, sizeof(uint64_t)) ||
+                !grow((void **)&all_counts, &capc, nall + 1, sizeof(uint32_t)))
+                goto done;
+            uint64_t *mk = all_masks + nall * W;
+            memset(mk, 0, W * sizeof(uint64_t));
+            for (uint32_t j = 0; j < prev.k; ++j) {
+                uint32_t it = prev.items[c * prev.k + j];
+                mk[it >> 6] |= 1ull << (it & 63);
+            }
+            all_counts[nall++] = (uint32_t)prev.supp[c];
+        }
+        if (prev.count < 2)
+            break;
+        /* join: itemsets that share their first k-1 items */
+        uint32_t k = prev.k + 1;
+        cur.k = k;
+        cur.count = 0;
+        for (uint64_t a = 0; a < prev.count; ++a) {
+            const uint32_t *A = prev.items + a * prev.k;
+            for (uint64_t b = a + 1; b < prev.count; ++b) {
+                const uint32_t *B = prev.items + b * prev.k;
+                if (lex_cmp(A, B, prev.k - 1) != 0)
+                    break; /* sorted: the shared-prefix group has ended */
+                memcpy(buf, A, prev.k * sizeof(uint32_t));
+                buf[prev.k] = B[prev.k - 1];
+                /* a-priori prune: every (k-1)-subset must be frequent */
+                int ok = 1;
+                uint32_t sub[64 + 1];
+                uint32_t *s = k - 1 <= 64 ? sub : NULL;
+                uint32_t *heap = NULL;
+                if (!s) {
+                    heap = (uint32_t *)malloc((k - 1) * sizeof(uint32_t));
+                    if (!heap)
+                        goto done;
+                    s = heap;
+                }
+                for (uint32_t drop = 0; drop + 2 < k && ok; ++drop) {
+                    uint32_t q = 0;
+                    for (uint32_t j = 0; j < k; ++j)
+                        if (j != drop)
+                            s[q++] = buf[j];
+                    ok = level_contains(&prev, s);
+                }
+                free(heap);
+                if (ok && !level_push(&cur, buf))
+                    goto done;
+            }
+        }
+        if (cur.count == 0)
+            break;
+        /* count: for each transaction, mark its items and test every candidate */
+        for (uint64_t t = 0; t < n; ++t) {
+            for (uint32_t i = 0; i < m; ++i)
+                present[i] = (unsigned char)((rows[t * W + (i >> 6)] >> (i & 63)) & 1u);
+            for (uint64_t c = 0; c < cur.count; ++c) {
+                const uint32_t *it = cur.items + c * k;
+                uint32_t j = 0;
+                while (j < k && present[it[j]])
+                    ++j;
+                if (j == k)
+                    cur.supp[c]++;
+            }
+        }
+        /* keep the frequent ones (order is preserved: still lexicographic) */
+        level next = {k, 0, 0, NULL, NULL};
+        for (uint64_t c = 0; c < cur.count; ++c)
+            if (cur.supp[c] >= tau) {
+                if (!level_push(&next, cur.items + c * k)) {
+                    free(next.items);
+                    free(next.supp);
+                    goto done;
+                }
+                next.supp[next.count - 1] = cur.supp[c];
+            }
+        free(prev.items);
+        free(prev.supp);
+        prev = next;
+        if (prev.count == 0)
+            break;
+    }
+
+    {
+        or_result *r = NULL;
+        rc = make_result(W, nall, all_masks, all_counts, &r);
+        if (rc)
+            goto done;
+        r->stats.tau = tau;
+        *out = r;
+        rc = OR_OK;
+    }
+done:
+    free(present);
+    free(buf);
+    free(all_masks);
+    free(all_counts);
+    free(prev.items);
+    free(prev.supp);
+    free(cur.items);
+    free(cur.supp);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* exact enumeration                                                         */
+/* ------------------------------------------------------------------------ */
+
+int oracle_bruteforce(const uint64_t *rows, uint64_t n, uint32_t m, double minsup,
+                      or_result **out)
+{
+    if (!out)
+        return OR_E_INVAL;
+    *out = NULL;
+    int rc = check_db(rows, n, m);
+    if (rc)
+        return rc;
+    if (m > 20)
+        return OR_E_RANGE;
+    uint64_t tau;
+    if ((rc = oracle_tau(minsup, n, &tau)))
+        return rc;
+    uint64_t total = (1ull << m) - 1;
+    uint64_t *masks = (uint64_t *)malloc(total * sizeof(uint64_t));
+    uint32_t *counts = (uint32_t *)malloc(total * sizeof(uint32_t));
+    if (!masks || !counts) {
+        free(masks);
+        free(counts);
+        return OR_E_NOMEM;
+    }
+    uint64_t q = 0;
+    for (uint64_t s = 1; s <= total; ++s) {
+        uint64_t c = 0;
+        for (uint64_t t = 0; t < n; ++t)
+            if ((rows[t] & s) == s) /* m <= 20: one word per row */
+                c++;
+        if (c >= tau) {
+            masks[q] = s;
+            counts[q] = (uint32_t)c;
+            q++;
+        }
+    }
+    or_result *r = NULL;
+    rc = make_result(1, q, masks, counts, &r);
+    free(masks);
+    free(counts);
+    if (rc)
+        return rc;
+    r->stats.tau = tau;
+    *out = r;
+    return OR_OK;
+}
+
+typedef struct {
+    uint32_t m, W;
+    uint64_t tau;
+    uint32_t **tids; /* per item: ascending row ids containing it */
+    uint64_t *ntid;
+    uint64_t *masks, nout, capm;
+    uint32_t *counts;
+    uint64_t capc;
+    uint64_t *cur; /* current itemset mask */
+    int fail;
+} tid_walk;
+
+static void tid_dfs(tid_walk *T, const uint32_t *tl, uint64_t ntl, uint32_t start)
+{
+    for (uint32_t i = start; i < T->m && !T->fail; ++i) {
+        /* intersect the current row list with item i's */
+        uint32_t *nx = (uint32_t *)malloc((ntl ? ntl : 1) * sizeof(uint32_t));
+        if (!nx) {
+            T->fail = 1;
+            return;
+        }
+        uint64_t a = 0, b = 0, c = 0;
+        const uint32_t *L = T->tids[i];
+        while (a < ntl && b < T->ntid[i]) {
+            if (tl[a] == L[b]) {
+                nx[c++] = tl[a];
+                a++;
+                b++;
+            } else if (tl[a] < L[b]) {
+                a++;
+            } else {
+                b++;
+            }
+        }
+        if (c >= T->tau) {
+            T->cur[i >> 6] |= 1ull << (i & 63);
+            if (!grow((void **)&T->masks, &T->capm, (T->nout + 1) * T->W, sizeof(uint64_t)) ||
+                !grow((void **)&T->counts, &T->capc, T->nout + 1, sizeof(uint32_t))) {
+                T->fail = 1;
+                free(nx);
+                return;
+            }
+            memcpy(T->masks + T->nout * T->W, T->cur, T->W * sizeof(uint64_t));
+            T->counts[T->nout++] = (uint32_t)c;
+            tid_dfs(T, nx, c, i + 1);
+            T->cur[i >> 6] &= ~(1ull << (i & 63));
+        }
+        free(nx);
+    }
+}
+
+int oracle_tidlist(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, or_result **out)
+{
+    if (!out)
+        return OR_E_INVAL;
+    *out = NULL;
+    int rc = check_db(rows, n, m);
+    if (rc)
+        return rc;
+    tid_walk T;
+    memset(&T, 0, sizeof(T));
+    if ((rc = oracle_tau(minsup, n, &T.tau)))
+        return rc;
+    T.m = m;
+    T.W = (m + 63u) / 64u;
+    rc = OR_E_NOMEM;
+    uint32_t *all = NULL;
+    T.tids = (uint32_t **)calloc(m, sizeof(uint32_t *));
+    T.ntid = (uint64_t *)calloc(m, sizeof(uint64_t));
+    T.cur = (uint64_t *)calloc(T.W, sizeof(uint64_t));
+    if (!T.tids || !T.ntid || !T.cur)
+        goto done;
+    for (uint64_t t = 0; t < n; ++t)
+        for (uint32_t i = 0; i < m; ++i)
+            if ((rows[t * T.W + (i >> 6)] >> (i & 63)) & 1u)
+                T.ntid[i]++;
+    for (uint32_t i = 0; i < m; ++i) {
+        T.tids[i] = (uint32_t *)malloc((T.ntid[i] ? T.ntid[i] : 1) * sizeof(uint32_t));
+        if (!T.tids[i])
+            goto done;
+        T.ntid[i] = 0;
+    }
+    for (uint64_t t = 0; t < n; ++t)
+        for (uint32_t i = 0; i < m; ++i)
+            if ((rows[t * T.W + (i >> 6)] >> (i & 63)) & 1u)
+                T.tids[i][T.ntid[i]++] = (uint32_t)t;
+    all = (uint32_t *)malloc(n * sizeof(uint32_t));
+    if (!all)
+        goto done;
+    for (uint64_t t = 0; t < n; ++t)
+        all[t] = (uint32_t)t;
+    tid_dfs(&T, all, n, 0);
+    if (T.fail)
+        goto done;
+    {
+        or_result *r = NULL;
+        rc = make_result(T.W, T.nout, T.masks, T.counts, &r);
+        if (rc)
+            goto done;
+        r->stats.tau = T.tau;
+        *out = r;
+        rc = OR_OK;
+    }
+done:
+    free(all);
+    if (T.tids)
+        for (uint32_t i = 0; i < m; ++i)
+            free(T.tids[i]);
+    free(T.tids);
+    free(T.ntid);
+    free(T.cur);
+    free(T.masks);
+    free(T.counts);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* single-step references                                                    */
+/* ------------------------------------------------------------------------ */
+
+int oracle_item_counts(const uint64_t *rows, uint64_t n, uint32_t m, uint32_t *counts)
+{
+    int rc = check_db(rows, n, m);
+    if (rc || !counts)
+        return rc ? rc : OR_E_INVAL;
+    const uint32_t W = (m + 63u) / 64u;
+    for (uint32_t i = 0; i < m; ++i)
+        counts[i] = 0;
+    for (uint64_t t = 0; t < n; ++t)
+        for (uint32_t i = 0; i < m; ++i)
+            if (has_item(rows + t * W, i))
+                counts[i]++;
+    return OR_OK;
+}
+
+int oracle_count_block(const uint64_t *rows, uint64_t n, uint32_t m, const uint64_t *masks,
+                       uint64_t q, uint64_t first, uint64_t last, uint32_t *counts)
+{
+    int rc = check_db(rows, n, m);
+    if (rc || (!masks && q) || (!counts && q) || first > last || last > n)
+        return rc ? rc : OR_E_INVAL;
+    const uint32_t W = (m + 63u) / 64u;
+    for (uint64_t c = 0; c < q; ++c) {
+        uint32_t s = 0;
+        for (uint64_t t = first; t < last; ++t)
+            if (is_subset(masks + c * W, rows + t * W, W))
+                s++;
+        counts[c] = s;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* result accessors                                                          */
+/* ------------------------------------------------------------------------ */
+
+uint64_t oracle_result_size(const or_result *r) { return r ? r->size : 0; }
+uint32_t oracle_result_words(const or_result *r) { return r ? r->W : 0; }
+const uint64_t *oracle_result_masks(const or_result *r) { return r ? r->masks : NULL; }
+const uint32_t *oracle_result_counts(const or_result *r) { return r ? r->counts : NULL; }
+uint64_t oracle_result_trace_len(const or_result *r) { return r ? r->trace_len : 0; }
+const or_stop *oracle_result_trace(const or_result *r) { return r ? r->trace : NULL; }
+
+int oracle_result_stats(const or_result *r, or_stats *s)
+{
+    if (!r || !s)
+        return OR_E_INVAL;
+    *s = r->stats;
+    return OR_OK;
+}
+
+void oracle_result_free(or_result *r)
+{
+    if (!r)
+        return;
+    free(r->masks);
+    free(r->counts);
+    free(r->trace);
+    free(r);
+}
