@@ -487,6 +487,10 @@ int oracle_dic(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, uint
          * erase circles whose best possible support cannot reach it, together
          * with every dashed-circle superset. */
         nnew = 0;
+        uint32_t kmax_circle = 0; /* no circle of this size or less has a proper superset */
+        for (uint64_t d = 0; d < S.nd; ++d)
+            if (S.dashed[d].shape == SHAPE_CIRCLE && S.dashed[d].k > kmax_circle)
+                kmax_circle = S.dashed[d].k;
         for (uint64_t d = 0; d < S.nd; ++d) {
             rec *I = &S.dashed[d];
             if (I->shape != SHAPE_CIRCLE)
@@ -506,9 +510,10 @@ int oracle_dic(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, uint
                     tr.pruned++;
                     if (!known_set(&S.known, S.arena + I->off, K_INFREQUENT))
                         goto done;
-                    for (uint64_t e = 0; e < S.nd; ++e) {
+                    for (uint64_t e = 0; I->k < kmax_circle && e < S.nd; ++e) {
                         rec *J = &S.dashed[e];
-                        if (e != d && J->shape == SHAPE_CIRCLE &&
+                        /* only a strictly larger itemset can be a proper superset */
+                        if (e != d && J->shape == SHAPE_CIRCLE && J->k > I->k &&
                             is_subset(S.arena + I->off, S.arena + J->off, W)) {
                             J->shape = SHAPE_NIL;
                             st.superset_prunes++;
