@@ -1,0 +1,202 @@
+/*
+ * dic.h -- frequent itemset mining by Dynamic Itemset Counting on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Zymbler, "Parallel Algorithm for Frequent Itemset Mining on Intel
+ * Many-core Systems".  Given a transaction database D = (T_1..T_n) over items
+ * 0..m-1 and a minimum support fraction minsup, the library returns every
+ * itemset contained in at least tau transactions together with its exact
+ * count (the problem statement of Section 1).  It gets there the way the
+ * paper's ParallelDIC does (Algorithm 2): a full first pass finds the
+ * frequent items and seeds all their pairs as candidates; then the database
+ * is scanned in blocks of M transactions, rewinding after the last block,
+ * and at every stop each live candidate's support is counted over the block
+ * (Algorithm 3), candidates that reached tau are promoted and hopeless ones
+ * pruned (Algorithm 4), supersets of new frequent itemsets whose maximal
+ * subsets are all frequent are added (MakeCandidates), and candidates that
+ * have seen every transaction once become final (Algorithm 5).  Every step
+ * runs in HIP kernels on the GPU; counts are exact 32-bit integers.
+ *
+ * Threshold: tau = max(1, ceil(minsup * n)), except that when minsup * n is
+ * within 1e-9 (relative, at least absolute 1e-9) of an integer that integer
+ * is used, and when minsup * n exceeds n the threshold is n + 1 (nothing is
+ * frequent).  minsup must be > 0 and not NaN.
+ *
+ * Bit layout (Section 4.1, one 64-bit word generalised to W words): a row
+ * is W = ceil(m / 64) uint64 words; item p is bit (p & 63) of word (p >> 6);
+ * bits at or above m must be zero.  A transaction T contains an itemset I
+ * exactly when (T[w] & I[w]) == I[w] for every word w.
+ *
+ * Limits: 1 <= m <= 4096 items, 1 <= n < 2^32 - 1 transactions.
+ *
+ * Errors: every call returns 0 on success or a negative DIC_E_* code and
+ * sets a thread-local message readable with dic_last_error().  No C++
+ * exception crosses this interface.  On error every out-pointer is set to
+ * NULL (or left untouched where documented) and nothing is leaked.
+ *
+ * Threads: calls on different databases may run concurrently from different
+ * host threads.  Calls on the same database are serialised internally.
+ */
+#ifndef DIC_H
+#define DIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define DIC_API __attribute__((visibility("default")))
+#else
+#define DIC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DIC_OK 0
+#define DIC_E_INVAL (-1)    /* a bad argument                                   */
+#define DIC_E_NOMEM (-2)    /* device or host allocation failed                 */
+#define DIC_E_CAPACITY (-3) /* request can never fit the server's memory budget */
+#define DIC_E_BUSY (-4)     /* database still referenced by queued/running work */
+#define DIC_E_PENDING (-5)  /* result not ready yet                             */
+#define DIC_E_DEVICE (-6)   /* a HIP runtime error                              */
+#define DIC_E_TIMEOUT (-7)  /* wait timed out                                   */
+#define DIC_E_NOTFOUND (-8) /* unknown ticket                                   */
+
+typedef struct dic_db dic_db;
+typedef struct dic_result dic_result;
+typedef struct dic_server dic_server;
+
+/* Per-stop record of one mining run (the loop body of Algorithm 2). */
+typedef struct dic_stop_trace {
+    uint32_t stop;       /* block index 1..stop_max counted at this stop      */
+    uint32_t rows;       /* transactions in that block                         */
+    uint32_t live;       /* candidates counted (|DASHED| at CountSupport)      */
+    uint32_t promoted;   /* dashed circles that reached tau (Prune)            */
+    uint32_t pruned;     /* dashed circles erased by the upper bound (Prune)   */
+    uint32_t generated;  /* new candidates (MakeCandidates)                    */
+    uint32_t solidified; /* candidates that finished a full pass (CheckFullPass) */
+    uint32_t reserved;
+} dic_stop_trace;
+
+typedef struct dic_stats {
+    uint64_t tau;        /* integer support threshold                          */
+    uint64_t block;      /* M' = min(M, n)                                     */
+    uint64_t stop_max;   /* ceil(n / M')                                       */
+    uint64_t stops;      /* stops executed                                     */
+    uint64_t tests;      /* subset tests: sum over stops of live * rows        */
+    uint64_t peak_live;  /* largest live candidate set                         */
+    uint64_t n_frequent; /* |L|                                                */
+    uint64_t k_max;      /* size of the largest frequent itemset               */
+    uint64_t known;      /* itemsets ever created (1-itemsets included)        */
+    uint64_t restarts;   /* runs repeated after growing the candidate capacity */
+    double mine_ms;      /* wall time of the mining call                       */
+} dic_stats;
+
+/*
+ * Copy a database to the device.  rows: host pointer to n*W uint64 words,
+ * row-major (layout above).  The library copies the data; the caller keeps
+ * ownership of rows.  DIC_E_INVAL if rows is NULL, n == 0, n >= 2^32-1,
+ * m == 0, m > 4096, or any bit at or above m is set.  *out is NULL on error.
+ */
+DIC_API int dic_load_db(const uint64_t *rows, uint64_t n, uint32_t m, dic_db **out);
+
+/*
+ * Same, from a database already in device memory (rows is a device pointer
+ * to n*W words, e.g. a framework tensor).  The data is copied device to
+ * device on the library's stream; the padding-bit check runs on the GPU.
+ */
+DIC_API int dic_load_db_device(const uint64_t *rows, uint64_t n, uint32_t m, dic_db **out);
+
+/*
+ * Build a database from item lists in CSR form: transaction t holds
+ * items[offsets[t] .. offsets[t+1]) (host pointers; offsets has n+1
+ * entries, offsets[0] == 0, non-decreasing).  Duplicate items are
+ * harmless.  The bit rows are packed on the GPU.  DIC_E_INVAL if an item
+ * is >= m or the offsets are malformed.
+ */
+DIC_API int dic_load_db_lists(const uint32_t *items, const uint64_t *offsets, uint64_t n, uint32_t m,
+                      dic_db **out);
+
+/* n, m of a loaded database (NULL-safe: 0). */
+DIC_API uint64_t dic_db_rows(const dic_db *db);
+DIC_API uint32_t dic_db_items(const dic_db *db);
+
+/*
+ * Free a database.  NULL gives DIC_OK.  DIC_E_BUSY (and nothing is freed)
+ * while a server request that references it is queued or running.
+ */
+DIC_API int dic_free_db(dic_db *db);
+
+/*
+ * Mine one database: every itemset with support >= tau and its exact count.
+ * minsup > 0 (values above 1 give an empty result), M >= 1 (clamped to n).
+ * Synchronous.  *out is owned by the caller (dic_result_free).
+ */
+DIC_API int dic_mine(dic_db *db, double minsup, uint64_t M, dic_result **out);
+
+/*
+ * Mine many databases at once: one launch per kernel per stop covers every
+ * database still running.  outs[i] receives database i's result, identical
+ * to what dic_mine would return; status[i] (may be NULL) its own code.
+ * Returns DIC_OK if every element succeeded, else the first failing
+ * element's code (failed elements have outs[i] == NULL).
+ */
+DIC_API int dic_batch(dic_db *const *dbs, const double *minsup, const uint64_t *M, uint32_t count,
+              dic_result **outs, int *status);
+
+/* Result accessors; pointers stay valid until dic_result_free. */
+DIC_API uint64_t dic_result_size(const dic_result *r);
+DIC_API uint32_t dic_result_words(const dic_result *r);
+/* size*W words, canonical order: size ascending, then item lists ascending */
+DIC_API const uint64_t *dic_result_masks(const dic_result *r);
+DIC_API const uint32_t *dic_result_counts(const dic_result *r);
+DIC_API int dic_result_stats(const dic_result *r, dic_stats *s);
+/* per-stop records, *n_stops entries (NULL-safe) */
+DIC_API const dic_stop_trace *dic_result_trace(const dic_result *r, uint64_t *n_stops);
+DIC_API void dic_result_free(dic_result *r);
+
+/*
+ * Serving: a request loop that keeps databases and candidate tables on the
+ * device and runs admitted requests together (continuous batching: a
+ * request that arrives while others are running joins at the next stop
+ * once its memory fits the budget).
+ */
+typedef struct dic_serve_opts {
+    uint32_t max_active;   /* requests mined together at most (0: 64)        */
+    uint32_t reserved;
+} dic_serve_opts;
+
+DIC_API int dic_serve_create(uint64_t hbm_budget_bytes, const dic_serve_opts *opts, dic_server **out);
+/* Queue a request.  DIC_E_CAPACITY at once if its footprint estimate can
+ * never fit the budget.  *ticket identifies it for poll/wait. */
+DIC_API int dic_serve_submit(dic_server *srv, dic_db *db, double minsup, uint64_t M, uint64_t *ticket);
+/* DIC_E_PENDING while queued or running; otherwise hands over the result
+ * (or the request's error code) and forgets the ticket. */
+DIC_API int dic_serve_poll(dic_server *srv, uint64_t ticket, dic_result **out);
+/* Like poll but blocks up to timeout_ms (negative: forever). */
+DIC_API int dic_serve_wait(dic_server *srv, uint64_t ticket, int64_t timeout_ms, dic_result **out);
+/* Latency percentiles (submit to completion, ms) and completed requests/s. */
+DIC_API int dic_serve_stats(dic_server *srv, double *p50_ms, double *p99_ms, double *throughput_rps);
+/* Waits for running work, drops queued requests, frees the server. */
+DIC_API int dic_serve_destroy(dic_server *srv);
+
+/*
+ * Route the library's device allocations and work: alloc(size, stream)
+ * returns device memory or NULL, free(ptr, stream) releases it, stream is a
+ * hipStream_t (NULL: the library's own stream).  Pass NULL functions to
+ * return to hipMalloc/hipFree.  Call before loading databases.
+ */
+DIC_API int dic_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(void *, void *),
+                      void *stream);
+
+/* Counting layout: 0 row-major bitmaps (default), 1 vertical item bitsets. */
+DIC_API int dic_set_option(const char *name, int64_t value);
+
+/* Thread-local message for the last error on this thread ("" if none). */
+DIC_API const char *dic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

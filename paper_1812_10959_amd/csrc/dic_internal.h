@@ -1,0 +1,161 @@
+// Internal declarations of the GPU library: device-visible job records, the
+// per-stop work plan, kernel launchers and the host engine.  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dic.h"
+
+namespace dic {
+
+// ---------------------------------------------------------------------------
+// Itemset standing.  DIC keeps four sets (Section 3): dashed/solid x
+// circle/box; pruned itemsets (Algorithm 4) stay known so they are never
+// generated again.
+// ---------------------------------------------------------------------------
+enum : uint32_t {
+    ST_DASHED_CIRCLE = 0,
+    ST_DASHED_BOX = 1,
+    ST_PRUNED = 2,
+    ST_SOLID_CIRCLE = 3,
+    ST_SOLID_BOX = 4,
+};
+
+constexpr uint32_t NO_EPOCH = 0xFFFFFFFFu;
+constexpr unsigned long long SLOT_EMPTY = ~0ull;
+constexpr uint32_t MAX_ITEMS = 4096;  // W <= 64, so a 64-bit map covers the words
+constexpr int WG = 256;               // threads per workgroup in every kernel
+constexpr int CW = 16;                // candidates per wave in the count kernel
+constexpr int CAND_PER_WG = CW * (WG / 64);
+constexpr int LDS_DWORDS = 8192;      // count kernel row tile (32 KiB)
+constexpr int MAX_GROUPS = 16;        // 64-row groups per row tile (1024 rows)
+
+__host__ __device__ inline uint32_t row_tile_rows(uint32_t W)
+{
+    // rows staged per tile: 2W dword planes of r rows each
+    uint32_t r = (uint32_t)(LDS_DWORDS / (2u * W));
+    r = (r / 64u) * 64u;
+    if (r > 64u * MAX_GROUPS)
+        r = 64u * MAX_GROUPS;
+    return r < 64u ? 64u : r;
+}
+
+// Mutable state of one mining run, updated only by kernels during a run.
+struct JobState {
+    uint32_t done;      // DASHED became empty
+    uint32_t overflow;  // candidate pool capacity exceeded
+    uint32_t stop;      // current block index 1..stop_max (0 before the first)
+    uint32_t epoch;     // stops executed so far
+    uint32_t K;         // live candidates counted at this stop
+    uint32_t k_next;    // live candidates appended for the next stop
+    uint32_t n_new;     // boxes promoted at this stop
+    uint32_t pool_n;    // itemsets in the pool (>= cap means overflow)
+    uint32_t nL1;       // frequent items
+    uint32_t max_rem;   // stops the next live set certainly still needs
+    uint32_t parity;    // live list in use: live[parity]
+    uint32_t first;     // block [first, last) of this stop
+    uint32_t last;
+    uint32_t n_ct;      // count plan: candidate groups
+    uint32_t n_ri;      //             row items
+    uint32_t rpi;       //             rows per row item
+    uint32_t peak_K;
+    uint32_t asserts;   // invariant violations (must stay 0)
+    unsigned long long tests;
+    uint32_t pad[12];
+};
+
+// Read-only description of one mining run (device copy in a job table).
+struct Job {
+    const uint64_t *rows;  // n * W, row-major
+    uint32_t n, m, W, Mp;
+    uint32_t stop_max, tau;
+    uint32_t cap;    // pool capacity (itemsets)
+    uint32_t hmask;  // hash slots - 1
+    uint64_t *pmask;  // cap * W
+    unsigned long long *phash;  // Zobrist hash of each itemset
+    uint64_t *pnz;    // bitmap of nonzero words
+    uint32_t *psupp, *pstop, *pstate, *ppromo, *pk;
+    unsigned long long *slots;  // open addressing: idx<<32 | fp24<<8 | k8
+    uint32_t *live0, *live1;    // cap each
+    uint32_t *newbox;           // cap
+    uint32_t *l1;               // m
+    uint32_t *item_cnt;         // m
+    dic_stop_trace *trace;
+    uint32_t trace_cap;
+    uint32_t pad0;
+    JobState *st;
+    uint64_t *out_mask;   // collect: cap * W
+    uint32_t *out_cnt;    // cap
+    uint32_t *out_n;      // 1
+};
+
+// Work plan of one step across all jobs (prefix sums, njobs + 1 entries).
+struct Plan {
+    uint32_t njobs;
+    uint32_t pad;
+    uint32_t *pre_count;
+    uint32_t *pre_epi;
+    unsigned long long *pre_cg;
+    unsigned long long *pre_fp;  // first pass row chunks
+    const unsigned long long *zobrist;  // MAX_ITEMS random words
+};
+
+// kernel launchers (dic_kernels.hip)
+void launch_first_pass(const Job *jobs, const Plan *plan, unsigned long long total_chunks,
+                       hipStream_t s);
+void launch_l1_and_pairs_prepare(const Job *jobs, const Plan *plan, uint32_t njobs, hipStream_t s);
+void launch_init_pairs(const Job *jobs, const Plan *plan, unsigned long long total, hipStream_t s);
+void launch_step(const Job *jobs, const Plan *plan, uint32_t njobs, hipStream_t s);
+void launch_collect(const Job *jobs, const Plan *plan, uint32_t njobs, hipStream_t s);
+void launch_pack_lists(const uint32_t *items, const uint64_t *offsets, uint64_t n, uint32_t W,
+                       uint64_t *rows, hipStream_t s);
+void launch_check_padding(const uint64_t *rows, uint64_t n, uint32_t m, uint32_t *bad,
+                          hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// host side (dic_engine.hip / dic_api.hip)
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+
+void *dev_alloc(size_t bytes);
+void dev_free(void *p);
+hipStream_t lib_stream();
+
+struct MineRequest {
+    const uint64_t *rows;  // device
+    uint32_t n, m;
+    double minsup;
+    uint64_t M;
+};
+
+struct MineOutput {
+    int status = 0;
+    std::vector<uint64_t> masks;
+    std::vector<uint32_t> counts;
+    std::vector<dic_stop_trace> trace;
+    dic_stats stats{};
+};
+
+// Compute tau from minsup; returns false on invalid minsup.
+bool threshold(double minsup, uint64_t n, uint64_t *tau);
+
+// Mine every request together (one launch per kernel per stop).
+int run_jobs(const std::vector<MineRequest> &reqs, std::vector<MineOutput> &outs,
+             hipStream_t stream);
+
+// Device bytes a request needs with a given candidate capacity.
+uint64_t job_bytes(uint32_t n, uint32_t m, uint32_t cap, uint32_t trace_cap);
+
+}  // namespace dic
+
+struct dic_result {
+    uint32_t W;
+    std::vector<uint64_t> masks;
+    std::vector<uint32_t> counts;
+    std::vector<dic_stop_trace> trace;
+    dic_stats stats;
+};

@@ -1,0 +1,751 @@
+// HIP kernels for Dynamic Itemset Counting on gfx950.
+//
+// Every kernel works on a table of jobs (one job = one database being mined)
+// so that the single-database path and the batched path are the same code:
+// a step launches each kernel once for all jobs, and each workgroup or wave
+// locates its job by binary search over per-job prefix sums of work.
+//
+// Per stop (the loop body of Algorithm 2, Section 4.2):
+//   k_begin     advance the block with rewind, size this stop's work
+//   k_count     CountSupport (Algorithm 3): live candidates x block rows
+//   k_epilogue  Prune (Algorithm 4) and CheckFullPass (Algorithm 5),
+//               compaction of the live list
+//   k_plan_cg   size MakeCandidates' work
+//   k_candgen   MakeCandidates: extend new boxes by frequent items
+// Before the loop: k_first_pass and k_l1 (FirstPass: item supports, the
+// frequent items), k_init_pairs (pairs of frequent items as candidates).
+// After it: k_collect gathers the solid boxes.
+#include "dic_internal.h"
+
+namespace dic {
+
+namespace {
+
+constexpr uint32_t FP_ROWS = 4096;       // first pass rows per workgroup item
+constexpr uint32_t COUNT_TARGET = 2048;  // count work items aimed at per job
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ unsigned long long lanemask_lt()
+{
+    uint32_t l = lane_id();
+    return l ? (~0ull >> (64u - l)) : 0ull;
+}
+
+// Largest j with pre[j] <= x, given pre[0] <= x < pre[njobs].
+template <typename T>
+__device__ __forceinline__ uint32_t find_job(const T *pre, uint32_t njobs, T x)
+{
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1u) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Wave-aggregated counter increment: one atomic per wave when every lane
+// targets the same counter, per-lane atomics otherwise.  All lanes call.
+__device__ __forceinline__ uint32_t wave_append(uint32_t *ctr, bool pred, bool uniform)
+{
+    if (uniform) {
+        unsigned long long b = __ballot(pred);
+        uint32_t base = 0;
+        if (b) {
+            int leader = __ffsll((long long)b) - 1;
+            if ((int)lane_id() == leader)
+                base = atomicAdd(ctr, (uint32_t)__popcll(b));
+            base = (uint32_t)__shfl((int)base, leader);
+        }
+        return base + (uint32_t)__popcll(b & lanemask_lt());
+    }
+    return pred ? atomicAdd(ctr, 1u) : 0u;
+}
+
+__device__ __forceinline__ void wave_max(uint32_t *ctr, uint32_t v, bool uniform)
+{
+    if (uniform) {
+        for (int off = 32; off > 0; off >>= 1) {
+            uint32_t o = (uint32_t)__shfl_xor((int)v, off);
+            v = o > v ? o : v;
+        }
+        if (lane_id() == 0 && v)
+            atomicMax(ctr, v);
+    } else if (v) {
+        atomicMax(ctr, v);
+    }
+}
+
+__device__ __forceinline__ dic_stop_trace *trace_of(const Job *J, const JobState *st)
+{
+    uint32_t e = st->epoch;
+    return (e >= 1 && e - 1 < J->trace_cap) ? J->trace + (e - 1) : nullptr;
+}
+
+// Hash slot key: pool index in the high half, a 24-bit fingerprint and the
+// itemset size (mod 256) in the low half.  Lookups of k-itemsets never match
+// a slot of a (k+1)-itemset being inserted concurrently.
+__device__ __forceinline__ uint32_t slot_tag(unsigned long long h, uint32_t k)
+{
+    return (uint32_t)(((h >> 40) & 0xFFFFFFull) << 8) | (k & 0xFFu);
+}
+
+__device__ __forceinline__ void hash_insert(const Job *J, unsigned long long h, uint32_t k,
+                                            uint32_t idx)
+{
+    unsigned long long v = ((unsigned long long)idx << 32) | slot_tag(h, k);
+    uint32_t s = (uint32_t)h & J->hmask;
+    for (;;) {
+        unsigned long long old = atomicCAS(J->slots + s, SLOT_EMPTY, v);
+        if (old == SLOT_EMPTY)
+            return;
+        s = (s + 1u) & J->hmask;
+    }
+}
+
+// Pool index of the itemset (S | {i}) \ {x} with hash h and size k, or NONE.
+__device__ __forceinline__ uint32_t hash_find_sub(const Job *J, unsigned long long h, uint32_t k,
+                                                  const uint64_t *S, uint32_t i, uint32_t x)
+{
+    const uint32_t tag = slot_tag(h, k);
+    const uint32_t W = J->W;
+    uint32_t s = (uint32_t)h & J->hmask;
+    for (;;) {
+        unsigned long long v =
+            __hip_atomic_load(J->slots + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v == SLOT_EMPTY)
+            return NONE;
+        if ((uint32_t)v == tag) {
+            uint32_t idx = (uint32_t)(v >> 32);
+            const uint64_t *P = J->pmask + (uint64_t)idx * W;
+            bool eq = true;
+            for (uint32_t w = 0; w < W && eq; ++w) {
+                uint64_t e = S[w];
+                if (w == (i >> 6))
+                    e |= 1ull << (i & 63u);
+                if (w == (x >> 6))
+                    e &= ~(1ull << (x & 63u));
+                eq = P[w] == e;
+            }
+            if (eq)
+                return idx;
+        }
+        s = (s + 1u) & J->hmask;
+    }
+}
+
+// Inclusive block scan of one value per thread (WG threads); *total gets
+// the sum over the block.  sh must hold WG elements.
+template <typename T>
+__device__ T block_scan_incl(T v, T *sh, T *total)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (uint32_t off = 1; off < WG; off <<= 1) {
+        T add = threadIdx.x >= off ? sh[threadIdx.x - off] : (T)0;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    T r = sh[threadIdx.x];
+    *total = sh[WG - 1];
+    __syncthreads();
+    return r;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// FirstPass: support of every item over all rows (column popcount).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_first_pass(const Job *__restrict__ jobs,
+                                                   const Plan *__restrict__ plan,
+                                                   unsigned long long total)
+{
+    __shared__ uint32_t hist[MAX_ITEMS];
+    for (unsigned long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const uint32_t j = find_job(plan->pre_fp, plan->njobs, it);
+        const Job *J = jobs + j;
+        const uint32_t W = J->W, m = J->m;
+        const uint64_t chunk = it - plan->pre_fp[j];
+        const uint64_t r0 = chunk * FP_ROWS;
+        const uint64_t r1 = r0 + FP_ROWS < J->n ? r0 + FP_ROWS : J->n;
+        for (uint32_t i = threadIdx.x; i < m; i += WG)
+            hist[i] = 0;
+        __syncthreads();
+        const uint64_t *rows = J->rows;
+        for (uint64_t e = r0 * W + threadIdx.x; e < r1 * W; e += WG) {
+            uint64_t x = rows[e];
+            const uint32_t base = (uint32_t)(e % W) * 64u;
+            while (x) {
+                atomicAdd(&hist[base + (uint32_t)__builtin_ctzll(x)], 1u);
+                x &= x - 1;
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < m; i += WG)
+            if (hist[i])
+                atomicAdd(&J->item_cnt[i], hist[i]);
+        __syncthreads();
+    }
+}
+
+// Frequent items (ascending) and the size of the pair candidate set.
+// One workgroup per job.
+__global__ __launch_bounds__(WG) void k_l1(const Job *__restrict__ jobs)
+{
+    __shared__ uint32_t sh[WG];
+    const Job *J = jobs + blockIdx.x;
+    JobState *st = J->st;
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < J->m; b += WG) {
+        const uint32_t i = b + threadIdx.x;
+        const uint32_t f = (i < J->m && J->item_cnt[i] >= J->tau) ? 1u : 0u;
+        uint32_t tot;
+        const uint32_t incl = block_scan_incl<uint32_t>(f, sh, &tot);
+        if (f)
+            J->l1[carry + incl - 1u] = i;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t nL1 = carry;
+        const uint64_t nC2 = (uint64_t)nL1 * (nL1 ? nL1 - 1u : 0u) / 2u;
+        st->nL1 = nL1;
+        st->k_next = (uint32_t)nC2;
+        st->pool_n = (uint32_t)nC2;
+        st->max_rem = nC2 ? J->stop_max : 0u;
+    }
+}
+
+// Candidate 2-itemsets: bitwise OR of every pair of frequent items, written
+// as pool entries 0..nC2-1 and as the first live list.
+__global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
+                                                   const Plan *__restrict__ plan,
+                                                   unsigned long long total)
+{
+    const unsigned long long stride = (unsigned long long)gridDim.x * WG;
+    for (unsigned long long x = (unsigned long long)blockIdx.x * WG + threadIdx.x; x < total;
+         x += stride) {
+        const uint32_t j = find_job(plan->pre_cg, plan->njobs, x);
+        const Job *J = jobs + j;
+        const uint32_t nL1 = J->st->nL1;
+        const unsigned long long local = x - plan->pre_cg[j];
+        const uint32_t a = (uint32_t)(local / nL1), b = (uint32_t)(local % nL1);
+        if (a >= b)
+            continue;
+        const uint32_t p = a * nL1 - a * (a + 1u) / 2u + (b - a - 1u);
+        const uint32_t ia = J->l1[a], ib = J->l1[b];
+        const uint32_t W = J->W;
+        uint64_t *mk = J->pmask + (uint64_t)p * W;
+        for (uint32_t w = 0; w < W; ++w)
+            mk[w] = 0;
+        mk[ia >> 6] |= 1ull << (ia & 63u);
+        mk[ib >> 6] |= 1ull << (ib & 63u);
+        const unsigned long long h = plan->zobrist[ia] ^ plan->zobrist[ib];
+        J->phash[p] = h;
+        J->pnz[p] = (1ull << (ia >> 6)) | (1ull << (ib >> 6));
+        J->pk[p] = 2;
+        J->psupp[p] = 0;
+        J->pstop[p] = 0;
+        J->pstate[p] = ST_DASHED_CIRCLE;
+        J->ppromo[p] = NO_EPOCH;
+        J->live1[p] = p;  // parity starts at 0, so the first stop reads live1
+        __threadfence();
+        hash_insert(J, h, 2, p);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One stop.
+// ---------------------------------------------------------------------------
+
+// Advance every job's block (Algorithm 2: stop <- stop + 1, rewinding past
+// stop_max), swap live lists, record the trace entry and plan the count and
+// epilogue work.  One workgroup.
+__global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan *plan)
+{
+    __shared__ uint32_t sh[WG];
+    const uint32_t njobs = plan->njobs;
+    uint32_t carry_c = 0, carry_e = 0;
+    if (threadIdx.x == 0) {
+        plan->pre_count[0] = 0;
+        plan->pre_epi[0] = 0;
+    }
+    for (uint32_t b = 0; b < njobs; b += WG) {
+        const uint32_t j = b + threadIdx.x;
+        uint32_t items = 0, K = 0;
+        if (j < njobs) {
+            const Job *J = jobs + j;
+            JobState *st = J->st;
+            if (!st->done && !st->overflow) {
+                if (st->k_next == 0) {
+                    st->done = 1;
+                    st->K = 0;
+                } else {
+                    K = st->k_next;
+                    st->K = K;
+                    st->k_next = 0;
+                    st->n_new = 0;
+                    st->parity ^= 1u;
+                    st->max_rem = 0;
+                    const uint32_t stop = st->stop % J->stop_max + 1u;
+                    st->stop = stop;
+                    st->epoch += 1u;
+                    const uint64_t first = (uint64_t)(stop - 1u) * J->Mp;
+                    const uint64_t end = (uint64_t)stop * J->Mp;
+                    const uint64_t last = end < J->n ? end : J->n;
+                    st->first = (uint32_t)first;
+                    st->last = (uint32_t)last;
+                    const uint32_t rows = (uint32_t)(last - first);
+                    st->tests += (unsigned long long)K * rows;
+                    if (K > st->peak_K)
+                        st->peak_K = K;
+                    if (st->epoch - 1u < J->trace_cap) {
+                        dic_stop_trace t;
+                        t.stop = stop;
+                        t.rows = rows;
+                        t.live = K;
+                        t.promoted = t.pruned = t.generated = t.solidified = t.reserved = 0;
+                        J->trace[st->epoch - 1u] = t;
+                    }
+                    const uint32_t rt = row_tile_rows(J->W);
+                    const uint32_t n_ct = (K + CAND_PER_WG - 1u) / CAND_PER_WG;
+                    const uint32_t tiles = (rows + rt - 1u) / rt;
+                    uint32_t want = (COUNT_TARGET + n_ct - 1u) / n_ct;
+                    if (want < 1u)
+                        want = 1u;
+                    if (want > tiles)
+                        want = tiles;
+                    const uint32_t rpi = ((tiles + want - 1u) / want) * rt;
+                    const uint32_t n_ri = (rows + rpi - 1u) / rpi;
+                    st->n_ct = n_ct;
+                    st->rpi = rpi;
+                    st->n_ri = n_ri;
+                    items = n_ct * n_ri;
+                }
+            }
+        }
+        uint32_t tc, te;
+        const uint32_t ic = block_scan_incl<uint32_t>(items, sh, &tc);
+        const uint32_t ie = block_scan_incl<uint32_t>(K, sh, &te);
+        if (j < njobs) {
+            plan->pre_count[j + 1] = carry_c + ic;
+            plan->pre_epi[j + 1] = carry_e + ie;
+        }
+        carry_c += tc;
+        carry_e += te;
+    }
+}
+
+// CountSupport (Algorithm 3).  Work item = (row range, group of CAND_PER_WG
+// candidates).  The workgroup stages the complemented rows of a tile in LDS
+// as 32-bit planes (plane d holds dword d of every row), each wave takes CW
+// candidates, and for every candidate each lane holds one row per 64-row
+// group: acc = OR over the candidate's nonzero dwords of (c_d AND NOT t_d);
+// the row contains the candidate iff acc == 0.  The 64 answers of a group
+// are counted with a wave ballot and a popcount.
+__global__ __launch_bounds__(WG) void k_count(const Job *__restrict__ jobs,
+                                              const Plan *__restrict__ plan)
+{
+    __shared__ uint32_t tile[LDS_DWORDS];
+    const uint32_t total = plan->pre_count[plan->njobs];
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = lane_id();
+    for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const uint32_t j = find_job(plan->pre_count, plan->njobs, it);
+        const Job *J = jobs + j;
+        const JobState *st = J->st;
+        const uint32_t local = it - plan->pre_count[j];
+        const uint32_t n_ct = st->n_ct;
+        const uint32_t ri = local / n_ct;
+        const uint32_t ct = local - ri * n_ct;
+        const uint32_t W = J->W;
+        const uint32_t rt = row_tile_rows(W);
+        const uint32_t r_begin = st->first + ri * st->rpi;
+        const uint32_t r_lim = r_begin + st->rpi;
+        const uint32_t r_end = r_lim < st->last ? r_lim : st->last;
+        const uint32_t K = st->K;
+        const uint32_t *live = st->parity ? J->live1 : J->live0;
+        const uint32_t c0 = ct * CAND_PER_WG + wave * CW;
+
+        uint32_t pidx[CW];
+        uint32_t cnt[CW];
+#pragma unroll
+        for (int q = 0; q < CW; ++q) {
+            pidx[q] = (c0 + (uint32_t)q < K) ? live[c0 + q] : NONE;
+            cnt[q] = 0;
+        }
+
+        for (uint64_t s0 = r_begin; s0 < r_end; s0 += rt) {
+            const uint32_t nr = (uint32_t)((r_end - s0) < rt ? (r_end - s0) : rt);
+            __syncthreads();
+            for (uint32_t r = threadIdx.x; r < rt; r += WG) {
+                if (r < nr) {
+                    const uint64_t *src = J->rows + (uint64_t)(s0 + r) * W;
+                    for (uint32_t w = 0; w < W; ++w) {
+                        const uint64_t v = ~src[w];
+                        tile[(2u * w) * rt + r] = (uint32_t)v;
+                        tile[(2u * w + 1u) * rt + r] = (uint32_t)(v >> 32);
+                    }
+                } else {
+                    for (uint32_t w = 0; w < 2u * W; ++w)
+                        tile[w * rt + r] = ~0u;  // never contains a nonempty itemset
+                }
+            }
+            __syncthreads();
+            const uint32_t G = (nr + 63u) >> 6;
+#pragma unroll
+            for (int q = 0; q < CW; ++q) {
+                const uint32_t p = pidx[q];
+                if (p == NONE)
+                    break;
+                uint32_t acc[MAX_GROUPS];
+#pragma unroll
+                for (int g = 0; g < MAX_GROUPS; ++g)
+                    acc[g] = 0;
+                uint64_t nz = J->pnz[p];
+                const uint64_t *cm = J->pmask + (uint64_t)p * W;
+                while (nz) {
+                    const uint32_t wd = (uint32_t)__builtin_ctzll(nz);
+                    nz &= nz - 1;
+                    const uint64_t v = cm[wd];
+                    const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+                    if (lo) {
+                        const uint32_t *pl = tile + (2u * wd) * rt + lane;
+#pragma unroll
+                        for (int g = 0; g < MAX_GROUPS; ++g)
+                            if ((uint32_t)g < G)
+                                acc[g] |= lo & pl[g * 64];
+                    }
+                    if (hi) {
+                        const uint32_t *pl = tile + (2u * wd + 1u) * rt + lane;
+#pragma unroll
+                        for (int g = 0; g < MAX_GROUPS; ++g)
+                            if ((uint32_t)g < G)
+                                acc[g] |= hi & pl[g * 64];
+                    }
+                }
+                uint32_t s = 0;
+#pragma unroll
+                for (int g = 0; g < MAX_GROUPS; ++g)
+                    if ((uint32_t)g < G)
+                        s += (uint32_t)__popcll(__ballot(acc[g] == 0u));
+                cnt[q] += s;
+            }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < CW; ++q)
+                if (pidx[q] != NONE && cnt[q])
+                    atomicAdd(J->psupp + pidx[q], cnt[q]);
+        }
+    }
+}
+
+// Prune (Algorithm 4) and CheckFullPass (Algorithm 5) for every live
+// candidate, plus the compaction of survivors into the next live list.
+// Candidates are counted for stop_I += 1 here (Algorithm 3's first line).
+__global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
+                                                 const Plan *__restrict__ plan)
+{
+    const uint32_t total = plan->pre_epi[plan->njobs];
+    const uint32_t lane = lane_id();
+    const uint32_t gw = (blockIdx.x * WG + threadIdx.x) >> 6;
+    const uint32_t nw = (gridDim.x * WG) >> 6;
+    for (uint32_t base = gw * 64u; base < total; base += nw * 64u) {
+        const uint32_t x = base + lane;
+        const bool valid = x < total;
+        const uint32_t j0 = find_job(plan->pre_epi, plan->njobs, base);
+        const uint32_t j = valid ? find_job(plan->pre_epi, plan->njobs, x) : j0;
+        const bool uniform = __ballot(j != j0) == 0ull;
+        const Job *J = jobs + j;
+        JobState *st = J->st;
+        bool promoted = false, pruned = false, solid = false, keep = false;
+        uint32_t p = 0, sc = 0;
+        if (valid) {
+            const uint32_t c = x - plan->pre_epi[j];
+            p = (st->parity ? J->live1 : J->live0)[c];
+            sc = J->pstop[p] + 1u;
+            J->pstop[p] = sc;
+            uint32_t state = J->pstate[p];
+            const uint32_t supp = J->psupp[p];
+            if (state == ST_DASHED_CIRCLE) {
+                if (supp >= J->tau) {
+                    state = ST_DASHED_BOX;
+                    J->ppromo[p] = st->epoch;
+                    promoted = true;
+                } else if ((uint64_t)supp + (uint64_t)J->Mp * (uint64_t)(J->stop_max - sc) <
+                           (uint64_t)J->tau) {
+                    state = ST_PRUNED;
+                    pruned = true;
+                }
+            }
+            if (!pruned) {
+                if (sc == J->stop_max) {
+                    solid = true;
+                    state = state == ST_DASHED_BOX ? ST_SOLID_BOX : ST_SOLID_CIRCLE;
+                } else {
+                    keep = true;
+                }
+            }
+            J->pstate[p] = state;
+        }
+        uint32_t *next = st->parity ? J->live0 : J->live1;
+        const uint32_t pos = wave_append(&st->k_next, keep, uniform);
+        if (keep)
+            next[pos] = p;
+        const uint32_t npos = wave_append(&st->n_new, promoted, uniform);
+        if (promoted)
+            J->newbox[npos] = p;
+        wave_max(&st->max_rem, keep ? J->stop_max - sc : 0u, uniform);
+        dic_stop_trace *tr = trace_of(J, st);
+        if (uniform) {
+            if (tr) {
+                wave_append(&tr->promoted, promoted, true);
+                wave_append(&tr->pruned, pruned, true);
+                wave_append(&tr->solidified, solid, true);
+            }
+        } else if (tr) {
+            if (promoted)
+                atomicAdd(&tr->promoted, 1u);
+            if (pruned)
+                atomicAdd(&tr->pruned, 1u);
+            if (solid)
+                atomicAdd(&tr->solidified, 1u);
+        }
+    }
+}
+
+// Size MakeCandidates' work: (new boxes) x (frequent items) per job.
+__global__ __launch_bounds__(WG) void k_plan_cg(const Job *__restrict__ jobs, Plan *plan)
+{
+    __shared__ unsigned long long sh[WG];
+    const uint32_t njobs = plan->njobs;
+    unsigned long long carry = 0;
+    if (threadIdx.x == 0)
+        plan->pre_cg[0] = 0;
+    for (uint32_t b = 0; b < njobs; b += WG) {
+        const uint32_t j = b + threadIdx.x;
+        unsigned long long v = 0;
+        if (j < njobs) {
+            const JobState *st = jobs[j].st;
+            if (!st->done && !st->overflow)
+                v = (unsigned long long)st->n_new * st->nL1;
+        }
+        unsigned long long tot;
+        const unsigned long long incl = block_scan_incl<unsigned long long>(v, sh, &tot);
+        if (j < njobs)
+            plan->pre_cg[j + 1] = carry + incl;
+        carry += tot;
+    }
+}
+
+// MakeCandidates: for each itemset S promoted at this stop and each frequent
+// item i not in S, C = S | {i} is admitted when every maximal proper subset
+// of C is a box.  C is produced by exactly one of its newly promoted subsets
+// C \ {i}: the one with the largest i, so no candidate is generated twice
+// and no set of already-known itemsets is needed (an itemset whose subsets
+// were all boxes before this stop was generated at an earlier stop).
+__global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
+                                                const Plan *__restrict__ plan)
+{
+    const unsigned long long total = plan->pre_cg[plan->njobs];
+    const uint32_t lane = lane_id();
+    const unsigned long long gw = ((unsigned long long)blockIdx.x * WG + threadIdx.x) >> 6;
+    const unsigned long long nw = ((unsigned long long)gridDim.x * WG) >> 6;
+    const unsigned long long *z = plan->zobrist;
+    for (unsigned long long base = gw * 64ull; base < total; base += nw * 64ull) {
+        const unsigned long long x = base + lane;
+        const bool valid = x < total;
+        const uint32_t j0 = find_job(plan->pre_cg, plan->njobs, base);
+        const uint32_t j = valid ? find_job(plan->pre_cg, plan->njobs, x) : j0;
+        const bool uniform = __ballot(j != j0) == 0ull;
+        const Job *J = jobs + j;
+        JobState *st = J->st;
+        const uint32_t W = J->W;
+        bool gen = false;
+        uint32_t p = 0, i = 0, k = 0;
+        unsigned long long hC = 0;
+        if (valid) {
+            const uint32_t nL1 = st->nL1;
+            const unsigned long long local = x - plan->pre_cg[j];
+            const uint32_t q = (uint32_t)(local / nL1), a = (uint32_t)(local % nL1);
+            p = J->newbox[q];
+            i = J->l1[a];
+            const uint64_t *S = J->pmask + (uint64_t)p * W;
+            if (!((S[i >> 6] >> (i & 63u)) & 1ull)) {
+                k = J->pk[p];
+                hC = J->phash[p] ^ z[i];
+                gen = true;
+                uint64_t nzw = J->pnz[p];
+                while (gen && nzw) {
+                    const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
+                    nzw &= nzw - 1;
+                    uint64_t bits = S[wd];
+                    while (gen && bits) {
+                        const uint32_t xj = wd * 64u + (uint32_t)__builtin_ctzll(bits);
+                        bits &= bits - 1;
+                        const uint32_t sub = hash_find_sub(J, hC ^ z[xj], k, S, i, xj);
+                        if (sub == NONE) {
+                            gen = false;
+                        } else {
+                            const uint32_t s2 = J->pstate[sub];
+                            if (s2 != ST_DASHED_BOX && s2 != ST_SOLID_BOX)
+                                gen = false;
+                            else if (xj > i && J->ppromo[sub] == st->epoch)
+                                gen = false;  // a subset dropping a larger item generates C
+                        }
+                    }
+                }
+            }
+        }
+        const uint32_t np = wave_append(&st->pool_n, gen, uniform);
+        const bool stored = gen && np < J->cap;
+        if (gen && !stored)
+            st->overflow = 1u;
+        if (stored) {
+            const uint64_t *S = J->pmask + (uint64_t)p * W;
+            uint64_t *C = J->pmask + (uint64_t)np * W;
+            for (uint32_t w = 0; w < W; ++w)
+                C[w] = S[w];
+            C[i >> 6] |= 1ull << (i & 63u);
+            J->phash[np] = hC;
+            J->pnz[np] = J->pnz[p] | (1ull << (i >> 6));
+            J->pk[np] = k + 1u;
+            J->psupp[np] = 0;
+            J->pstop[np] = 0;
+            J->pstate[np] = ST_DASHED_CIRCLE;
+            J->ppromo[np] = NO_EPOCH;
+            __threadfence();
+            hash_insert(J, hC, k + 1u, np);
+        }
+        uint32_t *next = st->parity ? J->live0 : J->live1;
+        const uint32_t pos = wave_append(&st->k_next, stored, uniform);
+        if (stored)
+            next[pos] = np;
+        wave_max(&st->max_rem, stored ? J->stop_max : 0u, uniform);
+        dic_stop_trace *tr = trace_of(J, st);
+        if (uniform) {
+            if (tr)
+                wave_append(&tr->generated, stored, true);
+        } else if (tr && stored) {
+            atomicAdd(&tr->generated, 1u);
+        }
+    }
+}
+
+// Gather solid boxes (the output L without its 1-itemsets).
+__global__ __launch_bounds__(WG) void k_collect(const Job *__restrict__ jobs)
+{
+    const Job *J = jobs + blockIdx.y;
+    const uint32_t pool_n = J->st->pool_n < J->cap ? J->st->pool_n : J->cap;
+    const uint32_t W = J->W;
+    for (uint32_t b = blockIdx.x * WG; b < pool_n; b += gridDim.x * WG) {
+        const uint32_t p = b + threadIdx.x;
+        const bool box = p < pool_n && J->pstate[p] == ST_SOLID_BOX;
+        const uint32_t pos = wave_append(J->out_n, box, true);
+        if (box) {
+            for (uint32_t w = 0; w < W; ++w)
+                J->out_mask[(uint64_t)pos * W + w] = J->pmask[(uint64_t)p * W + w];
+            J->out_cnt[pos] = J->psupp[p];
+        }
+    }
+}
+
+// Item lists (CSR) to bit rows, one thread per row.
+__global__ __launch_bounds__(WG) void k_pack_lists(const uint32_t *__restrict__ items,
+                                                   const uint64_t *__restrict__ offsets,
+                                                   uint64_t n, uint32_t W, uint64_t *rows)
+{
+    for (uint64_t r = (uint64_t)blockIdx.x * WG + threadIdx.x; r < n;
+         r += (uint64_t)gridDim.x * WG) {
+        uint64_t *row = rows + r * W;
+        for (uint32_t w = 0; w < W; ++w)
+            row[w] = 0;
+        for (uint64_t e = offsets[r]; e < offsets[r + 1]; ++e) {
+            const uint32_t it = items[e];
+            row[it >> 6] |= 1ull << (it & 63u);
+        }
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_check_padding(const uint64_t *__restrict__ rows,
+                                                      uint64_t n, uint32_t m, uint32_t *bad)
+{
+    const uint32_t W = (m + 63u) / 64u;
+    const uint64_t pad = ~((1ull << (m & 63u)) - 1ull);
+    for (uint64_t r = (uint64_t)blockIdx.x * WG + threadIdx.x; r < n;
+         r += (uint64_t)gridDim.x * WG)
+        if (rows[r * W + W - 1] & pad)
+            atomicOr(bad, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+constexpr uint32_t GRID_COUNT = 2048;
+constexpr uint32_t GRID_EPI = 512;
+constexpr uint32_t GRID_CG = 1024;
+
+uint32_t grid_for(unsigned long long work, uint32_t per, uint32_t cap)
+{
+    unsigned long long g = (work + per - 1) / per;
+    if (g < 1)
+        g = 1;
+    return (uint32_t)(g < cap ? g : cap);
+}
+}  // namespace
+
+void launch_first_pass(const Job *jobs, const Plan *plan, unsigned long long total_chunks,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_first_pass, dim3(grid_for(total_chunks, 1, 4096)), dim3(WG), 0, s, jobs,
+                       plan, total_chunks);
+}
+
+void launch_l1_and_pairs_prepare(const Job *jobs, const Plan *, uint32_t njobs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_l1, dim3(njobs), dim3(WG), 0, s, jobs);
+}
+
+void launch_init_pairs(const Job *jobs, const Plan *plan, unsigned long long total, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_pairs, dim3(grid_for(total, WG, 8192)), dim3(WG), 0, s, jobs, plan,
+                       total);
+}
+
+void launch_step(const Job *jobs, const Plan *plan, uint32_t, hipStream_t s)
+{
+    Plan *pl = const_cast<Plan *>(plan);
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(WG), 0, s, jobs, pl);
+    hipLaunchKernelGGL(k_count, dim3(GRID_COUNT), dim3(WG), 0, s, jobs, plan);
+    hipLaunchKernelGGL(k_epilogue, dim3(GRID_EPI), dim3(WG), 0, s, jobs, plan);
+    hipLaunchKernelGGL(k_plan_cg, dim3(1), dim3(WG), 0, s, jobs, pl);
+    hipLaunchKernelGGL(k_candgen, dim3(GRID_CG), dim3(WG), 0, s, jobs, plan);
+}
+
+void launch_collect(const Job *jobs, const Plan *, uint32_t njobs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_collect, dim3(64, njobs), dim3(WG), 0, s, jobs);
+}
+
+void launch_pack_lists(const uint32_t *items, const uint64_t *offsets, uint64_t n, uint32_t W,
+                       uint64_t *rows, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack_lists, dim3(grid_for(n, WG, 16384)), dim3(WG), 0, s, items, offsets,
+                       n, W, rows);
+}
+
+void launch_check_padding(const uint64_t *rows, uint64_t n, uint32_t m, uint32_t *bad,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_padding, dim3(grid_for(n, WG, 16384)), dim3(WG), 0, s, rows, n, m,
+                       bad);
+}
+
+}  // namespace dic
