@@ -1,0 +1,317 @@
+#!/usr/bin/env python3
+"""Benchmark: frequent itemset mining by Dynamic Itemset Counting on one MI355X.
+
+A step is one full mining call (first pass, then every stop: count, prune /
+promote, candidate generation, full-pass check and compaction, then
+collection) over the sparse Quest-style database of n = 1,000,000
+transactions and m = 1,000 items (minsup 0.5 %, M = 10,000), resident in HBM
+before timing starts.  ``value`` is subset tests per second over the whole
+step: (sum over stops of live candidates x block rows, plus the m*n item tests
+of the first pass) / step time.
+
+Also reported on the same line: the count kernel's roofline (HIP-event time
+of every CountSupport launch, algorithmic work per launch), the CPU oracle on
+a bounded sample, the other single-database workloads, batched vs plain
+mining of 256 databases, and latency percentiles of a served Poisson request
+stream.  Progress goes to stderr; the JSON line to stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "G subset-tests/s & % HBM roofline, batched vs plain; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit integer VALU lane operations
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline workload only (for profiler runs)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--cpu-rows", type=int, default=40_000)
+    return ap.parse_args()
+
+
+def mine_rate(stats, n, m):
+    return (stats["tests"] + n * m)
+
+
+def count_roofline(results, W):
+    """Algorithmic work of every CountSupport launch, summed over results.
+
+    Per stop: bytes = block rows x 8W (the block is read once) + live x 8W
+    (candidate masks); lane-ops = (nonzero 32-bit words of the live masks +
+    one compare per candidate) x block rows."""
+    byt = ops = 0
+    ms = 0.0
+    launches = 0
+    for r in results:
+        rows = r.trace[:, 1].astype(np.float64)
+        live = r.trace[:, 2].astype(np.float64)
+        words = r.words.astype(np.float64)
+        byt += float((rows * 8 * W + live * 8 * W).sum())
+        ops += float(((words + live) * rows).sum())
+        ms += r.stats["count_ms"]
+        launches += r.stats["count_launches"]
+    return byt, ops, ms, launches
+
+
+def headline(dic, args):
+    import synth
+    log("generating the sparse workload (n=1,000,000, m=1,000) ...")
+    t0 = time.time()
+    c = synth.config(2)
+    log(f"  generated in {time.time() - t0:.1f}s")
+    rows, m = c["rows"], c["m"]
+    n, W = rows.shape
+    db = dic.dic_load_db(rows, m)
+    dic.dic_set_option("profile", 1)
+    import torch
+    for i in range(args.warmup):
+        r = dic.dic_mine(db, c["minsup"], c["M"])
+        log(f"  warmup {i}: {r.stats['mine_ms']:.1f} ms, |L|={r.stats['n_frequent']}, "
+            f"stops={r.stats['stops']}")
+    torch.cuda.synchronize()
+    res = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res.append(dic.dic_mine(db, c["minsup"], c["M"]))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for r in res[1:]:
+        assert np.array_equal(r.masks, res[0].masks) and np.array_equal(r.counts, res[0].counts)
+    st = res[0].stats
+    tests = mine_rate(st, n, m)
+    value = tests * args.steps / dt / 1e9
+    byt, ops, cms, launches = count_roofline(res, W)
+    log(f"  timed {args.steps} steps: {dt / args.steps * 1e3:.2f} ms/step, {value:.1f} G tests/s, "
+        f"count kernel {cms / args.steps:.2f} ms/step over {launches // args.steps} launches")
+    out = {
+        "value": value, "ms_per_step": dt / args.steps * 1e3, "stats": st,
+        "workload": c, "db": db, "rows": rows,
+        "count": {"ms_per_step": cms / args.steps, "launches_per_step": launches / args.steps,
+                  "bytes_per_step": byt / args.steps, "ops_per_step": ops / args.steps,
+                  "tests_per_step": st["tests"]},
+    }
+    achieved_tops = ops / (cms * 1e-3) / 1e12 if cms else 0.0
+    achieved_gbs = byt / (cms * 1e-3) / 1e9 if cms else 0.0
+    out["roofline"] = {
+        "kernel": "k_count", "bound": "alu", "achieved": achieved_tops, "peak": ALU_PEAK_TOPS,
+        "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved_tops / ALU_PEAK_TOPS,
+        "traffic": None,
+        "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved_gbs / HBM_PEAK_GBS},
+        "count_tests_per_s": st["tests"] / (cms / args.steps * 1e-3) if cms else 0.0,
+        "avg_launch_us": cms / launches * 1e3 if launches else 0.0,
+    }
+    return out
+
+
+def cpu_baseline(c, rows_full, n_rows):
+    import oracle
+    rows = np.ascontiguousarray(rows_full[:n_rows])
+    log(f"CPU oracle on the first {n_rows} rows ...")
+    t0 = time.perf_counter()
+    r = oracle.dic(rows, c["m"], c["minsup"], c["M"])
+    dt = time.perf_counter() - t0
+    tests = r.stats["tests"] + n_rows * c["m"]
+    log(f"  oracle {dt:.1f}s, {tests / dt / 1e9:.3f} G tests/s")
+    return {"value": tests / dt / 1e9, "unit": "G subset-tests/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_rows} rows of the n=1,000,000 m=1,000 workload, same minsup and "
+                      f"M; serial C oracle, {dt:.1f} s, {r.stats['tests']} block tests + "
+                      f"{n_rows * c['m']} first-pass tests",
+            "cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def other_configs(dic):
+    import synth
+    out = {}
+    for idx in (1, 3):
+        c = synth.config(idx)
+        rows, m = c["rows"], c["m"]
+        n = rows.shape[0]
+        db = dic.dic_load_db(rows, m)
+        dic.dic_mine(db, c["minsup"], c["M"])
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            r = dic.dic_mine(db, c["minsup"], c["M"])
+        dt = (time.perf_counter() - t0) / reps
+        st = r.stats
+        out[c["name"]] = {
+            "n": n, "m": m, "minsup": c["minsup"], "M": c["M"], "ms": dt * 1e3,
+            "G_tests_per_s": mine_rate(st, n, m) / dt / 1e9,
+            "count_G_tests_per_s": st["tests"] / (st["count_ms"] * 1e-3) / 1e9
+            if st["count_ms"] else None,
+            "n_frequent": st["n_frequent"], "k_max": st["k_max"], "stops": st["stops"],
+            "tests": st["tests"], "peak_live": st["peak_live"]}
+        log(f"  {c['name']}: {dt * 1e3:.2f} ms, {out[c['name']]['G_tests_per_s']:.1f} G tests/s")
+    return out
+
+
+def _gen_batch(args_):
+    import synth
+    count, seed = args_
+    return synth.batch_config(count, seed=seed)
+
+
+def batch_vs_plain(dic, count):
+    import synth
+    log(f"generating {count} databases ...")
+    t0 = time.time()
+    dbs_spec = synth.batch_config(count)
+    log(f"  generated in {time.time() - t0:.1f}s")
+    dbs = [dic.dic_load_db(d["rows"], d["m"]) for d in dbs_spec]
+    ms = [d["minsup"] for d in dbs_spec]
+    Ms = [d["M"] for d in dbs_spec]
+    tests_first = sum(d["rows"].shape[0] * d["m"] for d in dbs_spec)
+    # warm both paths once
+    dic.dic_batch(dbs[:8], ms[:8], Ms[:8])
+    for i in range(4):
+        dic.dic_mine(dbs[i], ms[i], Ms[i])
+    t0 = time.perf_counter()
+    plain = [dic.dic_mine(db, a, b) for db, a, b in zip(dbs, ms, Ms)]
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batched = dic.dic_batch(dbs, ms, Ms)
+    t_batch = time.perf_counter() - t0
+    same = all(np.array_equal(p.masks, b.masks) and np.array_equal(p.counts, b.counts)
+               for p, b in zip(plain, batched))
+    tests = sum(r.stats["tests"] for r in plain) + tests_first
+    out = {"databases": count, "plain_s": t_plain, "batched_s": t_batch,
+           "plain_G_tests_per_s": tests / t_plain / 1e9,
+           "batched_G_tests_per_s": tests / t_batch / 1e9,
+           "speedup": t_plain / t_batch, "identical_results": bool(same),
+           "total_tests": tests,
+           "n_frequent_total": int(sum(r.stats["n_frequent"] for r in plain))}
+    log(f"  plain {t_plain:.2f}s, batched {t_batch:.2f}s, x{t_plain / t_batch:.2f}, "
+        f"identical={same}")
+    return out
+
+
+def serving(dic, seconds, rate, big_c2=None):
+    import synth
+    log(f"serving: Poisson {rate}/s for {seconds}s over mixed databases ...")
+    pool = []
+    if big_c2 is not None:
+        c2 = dict(big_c2)
+        c2["minsup_range"] = (0.005, 0.05)
+        pool.append(c2)
+    else:
+        c2 = synth.config(2)
+        c2["minsup_range"] = (0.005, 0.05)
+        pool.append(c2)
+    c3 = synth.config(3)
+    c3["minsup_range"] = (0.25, 0.30)
+    pool.append(c3)
+    for d in synth.batch_config(16, seed=synth.CONFIG_SEED_BASE + 5):
+        d["minsup_range"] = (0.01, 0.05)
+        pool.append(d)
+    dbs = [dic.dic_load_db(p["rows"], p["m"]) for p in pool]
+    stream = synth.serve_stream([p["rows"].shape[0] for p in pool], rate=rate,
+                                duration_s=seconds, minsup_ranges=[p["minsup_range"] for p in pool])
+    srv = dic.dic_serve_create(200 << 30, max_active=64)
+    tickets = []
+    t_start = time.perf_counter()
+    for (t_arr, j, minsup) in stream:
+        now = time.perf_counter() - t_start
+        if t_arr > now:
+            time.sleep(t_arr - now)
+        M = pool[j]["M"] if j < 2 else max(1, pool[j]["rows"].shape[0] // 20)
+        tickets.append((dic.dic_serve_submit(srv, dbs[j], minsup, M), j, minsup, M))
+    log(f"  submitted {len(tickets)} requests; waiting ...")
+    results = []
+    for (t, j, minsup, M) in tickets:
+        results.append((dic.dic_serve_wait(srv, t), j, minsup, M))
+    wall = time.perf_counter() - t_start
+    p50, p99, rps = dic.dic_serve_stats(srv)
+    dic.dic_serve_destroy(srv)
+    # spot-check that served results equal solo mining
+    rng = np.random.default_rng(0)
+    ok = True
+    for k in rng.choice(len(results), size=min(8, len(results)), replace=False):
+        r, j, minsup, M = results[k]
+        solo = dic.dic_mine(dbs[j], minsup, M)
+        ok &= np.array_equal(r.masks, solo.masks) and np.array_equal(r.counts, solo.counts)
+    tests = sum(r.stats["tests"] + pool[j]["rows"].shape[0] * pool[j]["m"]
+                for r, j, _, _ in results)
+    out = {"rate_req_per_s": rate, "seconds": seconds, "requests": len(results),
+           "p50_ms": p50, "p99_ms": p99, "throughput_req_per_s": rps,
+           "G_tests_per_s": tests / wall / 1e9, "budget_bytes": 200 << 30,
+           "spot_check_identical": bool(ok)}
+    log(f"  p50 {p50:.1f} ms, p99 {p99:.1f} ms, {rps:.1f} req/s, spot-check identical={ok}")
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the mining path "
+              "is single-GPU in this build", file=sys.stderr)
+        sys.exit(2)
+    import paper_1812_10959_amd as dic
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    h = headline(dic, args)
+    c = h["workload"]
+    line = {
+        "metric": METRIC, "value": round(h["value"], 3), "unit": "G subset-tests/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(h["ms_per_step"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "quest_zipf_n1M_m1000", "n": int(h["rows"].shape[0]), "m": c["m"],
+                   "minsup": c["minsup"], "M": c["M"], "seed": c["meta"]["seed"],
+                   "path": "dic_mine (plain, one database)"},
+        "roofline": h["roofline"],
+        "stats": {k: h["stats"][k] for k in ("tau", "stops", "tests", "peak_live", "n_frequent",
+                                              "k_max", "known", "restarts")},
+        "count_kernel": h["count"],
+    }
+    if not args.only_headline:
+        if not args.no_cpu:
+            line["cpu_baseline"] = cpu_baseline(c, h["rows"], args.cpu_rows)
+        log("other single-database workloads ...")
+        line["workloads"] = other_configs(dic)
+        if not args.no_batch:
+            line["batched_vs_plain"] = batch_vs_plain(dic, args.batch_count)
+        if not args.no_serve:
+            line["serving"] = serving(dic, args.serve_seconds, args.serve_rate, big_c2=c)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

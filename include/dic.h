@@ -76,7 +76,8 @@ typedef struct dic_stop_trace {
     uint32_t pruned;     /* dashed circles erased by the upper bound (Prune)   */
     uint32_t generated;  /* new candidates (MakeCandidates)                    */
     uint32_t solidified; /* candidates that finished a full pass (CheckFullPass) */
-    uint32_t reserved;
+    uint32_t words;      /* nonzero 32-bit words over the live candidates' masks:
+                            the AND work per transaction at this stop      */
 } dic_stop_trace;
 
 typedef struct dic_stats {
@@ -90,7 +91,10 @@ typedef struct dic_stats {
     uint64_t k_max;      /* size of the largest frequent itemset               */
     uint64_t known;      /* itemsets ever created (1-itemsets included)        */
     uint64_t restarts;   /* runs repeated after growing the candidate capacity */
-    double mine_ms;      /* wall time of the mining call                       */
+    double mine_ms;      /* wall time from submission to result                */
+    double count_ms;     /* CountSupport kernel time (HIP events; 0 unless the
+                            "profile" option is on)                           */
+    uint64_t count_launches; /* CountSupport launches timed into count_ms      */
 } dic_stats;
 
 /*
@@ -190,7 +194,11 @@ DIC_API int dic_serve_destroy(dic_server *srv);
 DIC_API int dic_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(void *, void *),
                       void *stream);
 
-/* Counting layout: 0 row-major bitmaps (default), 1 vertical item bitsets. */
+/*
+ * Library options (process-wide):
+ *   "profile"  0/1: time every CountSupport launch with HIP events recorded
+ *              on the stream it runs on; reported as dic_stats.count_ms.
+ */
 DIC_API int dic_set_option(const char *name, int64_t value);
 
 /* Thread-local message for the last error on this thread ("" if none). */

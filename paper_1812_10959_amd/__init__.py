@@ -63,13 +63,14 @@ class DicError(RuntimeError):
 
 class dic_stop_trace(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint32) for f in (
-        "stop", "rows", "live", "promoted", "pruned", "generated", "solidified", "reserved")]
+        "stop", "rows", "live", "promoted", "pruned", "generated", "solidified", "words")]
 
 
 class dic_stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in (
         "tau", "block", "stop_max", "stops", "tests", "peak_live", "n_frequent", "k_max",
-        "known", "restarts")] + [("mine_ms", ctypes.c_double)]
+        "known", "restarts")] + [("mine_ms", ctypes.c_double), ("count_ms", ctypes.c_double),
+                                 ("count_launches", ctypes.c_uint64)]
 
 
 class dic_serve_opts(ctypes.Structure):
@@ -203,6 +204,7 @@ class Result:
     counts: np.ndarray             # uint32[|L|]
     stats: dict = field(default_factory=dict)
     trace: np.ndarray | None = None  # uint32[stops, 7] in TRACE_FIELDS order
+    words: np.ndarray | None = None  # uint32[stops]: nonzero 32-bit words of the live masks
 
 
 def _take_result(h: int) -> Result:
@@ -222,16 +224,17 @@ def _take_result(h: int) -> Result:
             counts = np.zeros(0, np.uint32)
         st = dic_stats()
         _check(_lib.dic_result_stats(h, ctypes.byref(st)), "dic_result_stats")
-        stats = {f: (float(getattr(st, f)) if f == "mine_ms" else int(getattr(st, f)))
+        stats = {f: (float(getattr(st, f)) if f.endswith("_ms") else int(getattr(st, f)))
                  for f, _ in dic_stats._fields_}
         ns = _u64()
         tp = _lib.dic_result_trace(h, ctypes.byref(ns))
-        trace = None
+        trace = words = None
         if ns.value:
             raw = np.ctypeslib.as_array(ctypes.cast(tp, ctypes.POINTER(ctypes.c_uint32)),
                                         shape=(ns.value * 8,)).reshape(ns.value, 8)
             trace = raw[:, :7].copy()
-        return Result(masks, counts, stats, trace)
+            words = raw[:, 7].copy()
+        return Result(masks, counts, stats, trace, words)
     finally:
         _lib.dic_result_free(h)
 

@@ -20,6 +20,12 @@ struct dic_db {
 
 namespace dic {
 
+const uint64_t *db_rows(dic_db *db) { return db->rows; }
+uint64_t db_n(dic_db *db) { return db->n; }
+uint32_t db_m(dic_db *db) { return db->m; }
+uint32_t db_W(dic_db *db) { return db->W; }
+void db_ref(dic_db *db, int delta) { db->refs += delta; }
+
 namespace {
 
 thread_local std::string t_err;
@@ -160,8 +166,11 @@ int dic_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(void *, vo
 
 int dic_set_option(const char *name, int64_t value)
 {
-    (void)value;
-    set_error(std::string("dic_set_option: unknown option ") + (name ? name : "(null)"));
+    if (name && std::strcmp(name, "profile") == 0 && (value == 0 || value == 1)) {
+        set_profiling((int)value);
+        return DIC_OK;
+    }
+    set_error(std::string("dic_set_option: unknown option or value ") + (name ? name : "(null)"));
     return DIC_E_INVAL;
 }
 

@@ -1,16 +1,19 @@
-// Host engine: drives the per-stop kernels for a table of jobs.
+// Host engine: drives the per-stop kernels for a changing set of jobs.
 //
-// A run has three phases:
-//   1. FirstPass on every job (item supports, frequent items), one readback
-//      to learn each job's frequent-item count and size its candidate pool;
-//   2. the stop loop: the host enqueues S stops at a time without looking at
-//      the device (every kernel reads its job's state from device memory and
-//      does nothing once the job is done), then reads back the small job
-//      states once; S is the number of stops the live candidates still
-//      certainly need, so no enqueued stop is idle;
-//   3. collection of the solid boxes and the canonical sort.
-// A job whose candidate pool overflowed is rerun with four times the room.
+// Life of a job:
+//   add      -> FirstPass (item supports, frequent items) for the new jobs,
+//               one readback to size each candidate pool, then the pair
+//               candidates are written on the device;
+//   advance  -> the host enqueues S stops for every unfinished job without
+//               looking at the device (each kernel reads its job's state from
+//               device memory and does nothing for a finished job), then reads
+//               the small job states back once.  S is at most the number of
+//               stops the live candidates certainly still need, so enqueued
+//               stops are not idle;
+//   harvest  -> solid boxes are gathered, sorted canonically and returned;
+//               a job whose pool overflowed is rerun with four times the room.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -32,9 +35,9 @@ namespace {
         }                                                                                \
     } while (0)
 
-constexpr uint32_t FP_ROWS = 4096;  // must match the first-pass kernel
+constexpr uint32_t FP_ROWS = 4096;  // rows per first-pass work item (kernel side too)
 constexpr uint32_t TRACE_INIT = 512;
-constexpr uint32_t MAX_STEPS_PER_SYNC = 1024;
+constexpr uint32_t MAX_RESTARTS = 6;
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -83,35 +86,14 @@ const unsigned long long *zobrist(hipStream_t s)
     return g_zob[dev];
 }
 
-// A device buffer carved into aligned pieces.
 struct Carver {
     size_t off = 0;
-    size_t take(size_t bytes) {
+    size_t take(size_t bytes)
+    {
         size_t o = off;
         off = align_up(off + bytes, 256);
         return o;
     }
-};
-
-struct DevBuf {
-    void *p = nullptr;
-    DevBuf() = default;
-    DevBuf(const DevBuf &) = delete;
-    DevBuf &operator=(const DevBuf &) = delete;
-    ~DevBuf() { if (p) dev_free(p); }
-    bool alloc(size_t bytes) { p = dev_alloc(bytes ? bytes : 256); return p != nullptr; }
-    char *at(size_t off) const { return (char *)p + off; }
-};
-
-struct JobPlanHost {
-    uint32_t W, Mp, stop_max, tau;
-    uint64_t n;
-    uint32_t m;
-    uint32_t cap = 0;
-    uint32_t nL1 = 0;
-    uint32_t trace_cap = TRACE_INIT;
-    size_t a_cnt, a_l1;
-    void *trace_buf = nullptr;
 };
 
 bool canon_less(const uint64_t *A, const uint64_t *B, uint32_t W, uint32_t ka, uint32_t kb)
@@ -128,7 +110,49 @@ bool canon_less(const uint64_t *A, const uint64_t *B, uint32_t W, uint32_t ka, u
     return false;
 }
 
+uint64_t pool_cap_for(uint32_t nL1, uint32_t mult)
+{
+    const uint64_t nC2 = (uint64_t)nL1 * (nL1 ? nL1 - 1u : 0u) / 2u;
+    return std::max<uint64_t>(16384, 4 * nC2 + 16384) * mult;
+}
+
+// Layout of a job's candidate pool buffer.
+struct PoolLayout {
+    size_t mask, hash, nz, supp, stop, state, promo, k, slots, live0, live1, newbox, omask, ocnt;
+    size_t bytes;
+    uint64_t hslots;
+    PoolLayout(uint64_t cap, uint32_t W)
+    {
+        hslots = next_pow2(2 * cap);
+        Carver c;
+        mask = c.take(cap * W * 8);
+        hash = c.take(cap * 8);
+        nz = c.take(cap * 8);
+        supp = c.take(cap * 4);
+        stop = c.take(cap * 4);
+        state = c.take(cap * 4);
+        promo = c.take(cap * 4);
+        k = c.take(cap * 4);
+        slots = c.take(hslots * 8);
+        live0 = c.take(cap * 4);
+        live1 = c.take(cap * 4);
+        newbox = c.take(cap * 4);
+        omask = c.take(cap * W * 8);
+        ocnt = c.take(cap * 4);
+        bytes = c.off;
+    }
+};
+
+std::atomic<int> g_profile{0};
+
 }  // namespace
+
+bool profiling() { return g_profile.load() != 0; }
+void set_profiling(int on) { g_profile.store(on); }
+
+// ---------------------------------------------------------------------------
+// threshold and sizes
+// ---------------------------------------------------------------------------
 
 bool threshold(double minsup, uint64_t n, uint64_t *tau)
 {
@@ -151,279 +175,451 @@ bool threshold(double minsup, uint64_t n, uint64_t *tau)
     return true;
 }
 
-uint64_t job_bytes(uint32_t n, uint32_t m, uint32_t cap, uint32_t trace_cap)
+uint64_t job_bytes(uint32_t m, uint64_t cap, uint32_t trace_cap)
 {
-    (void)n;
-    const uint64_t W = (m + 63u) / 64u;
-    const uint64_t H = next_pow2(2ull * cap);
-    uint64_t b = 0;
-    b += sizeof(JobState) + 2ull * m * 4 + (uint64_t)trace_cap * sizeof(dic_stop_trace) + 1024;
-    b += (uint64_t)cap * W * 8 * 2;         // pool masks + collected masks
-    b += (uint64_t)cap * (8 + 8 + 5 * 4);   // hash, nonzero map, u32 fields
-    b += (uint64_t)cap * 4 * 4;             // live0, live1, newbox, collected counts
-    b += H * 8;                             // slots
-    return b + 16 * 256;
+    const uint32_t W = (m + 63u) / 64u;
+    return PoolLayout(cap, W).bytes + 2ull * m * 4 + 512 +
+           (uint64_t)trace_cap * sizeof(dic_stop_trace);
 }
 
-static int run_once(const std::vector<MineRequest> &reqs, std::vector<MineOutput> &outs,
-                    const std::vector<uint32_t> &cap_mult, std::vector<char> &overflowed,
-                    hipStream_t s)
+uint64_t job_bytes_bound(uint32_t m) { return job_bytes(m, pool_cap_for(m, 1), TRACE_INIT); }
+
+// ---------------------------------------------------------------------------
+// per-job host record
+// ---------------------------------------------------------------------------
+
+struct ActiveJob {
+    uint64_t id = 0;
+    MineRequest req{};
+    uint32_t W = 0, Mp = 0, stop_max = 0, tau = 0;
+    uint32_t mult = 1, restarts = 0;
+    uint32_t cap = 0, nL1 = 0, trace_cap = TRACE_INIT;
+    int slot = -1;
+    void *small = nullptr;  // item counts, frequent items
+    void *pool = nullptr;   // candidate pool
+    void *trace = nullptr;
+    Job job{};
+    bool in_loop = false;   // pairs written, taking part in stops
+    double count_ms = 0;
+    uint64_t count_launches = 0;
+    std::chrono::steady_clock::time_point t0;
+
+    void release()
+    {
+        dev_free(small);
+        dev_free(pool);
+        dev_free(trace);
+        small = pool = trace = nullptr;
+    }
+    ~ActiveJob() { release(); }
+};
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+
+Engine::Engine(hipStream_t s, uint32_t max_jobs) : s_(s), max_jobs_(std::max(1u, max_jobs))
 {
-    const uint32_t njobs = (uint32_t)reqs.size();
-    std::vector<JobPlanHost> H(njobs);
-    const unsigned long long *zob = zobrist(s);
+    for (int i = (int)max_jobs_ - 1; i >= 0; --i)
+        free_slots_.push_back(i);
+    st_.resize(max_jobs_);
+}
+
+Engine::~Engine()
+{
+    (void)hipStreamSynchronize(s_);
+    for (ActiveJob *j : jobs_)
+        delete j;
+    dev_free(slab_);
+    dev_free(table_);
+    dev_free(table_aux_);
+    dev_free(plan_buf_);
+    for (hipEvent_t e : events_)
+        (void)hipEventDestroy(e);
+}
+
+bool Engine::running() const
+{
+    for (ActiveJob *j : jobs_) {
+        const JobState &s = st_[j->slot];
+        if (j->in_loop && !s.done && !s.overflow && s.k_next > 0)
+            return true;
+    }
+    return false;
+}
+
+uint64_t Engine::job_bytes_of(uint64_t id) const
+{
+    for (ActiveJob *j : jobs_)
+        if (j->id == id)
+            return job_bytes(j->req.m, j->cap ? j->cap : pool_cap_for(j->req.m, j->mult),
+                             j->trace_cap);
+    return 0;
+}
+
+int Engine::read_states()
+{
+    int hi = -1;
+    for (ActiveJob *j : jobs_)
+        hi = std::max(hi, j->slot);
+    if (hi >= 0)
+        HIP_TRY(hipMemcpyAsync(st_.data(), slab_, sizeof(JobState) * (hi + 1),
+                               hipMemcpyDeviceToHost, s_));
+    HIP_TRY(hipStreamSynchronize(s_));
+    return DIC_OK;
+}
+
+int Engine::add(const std::vector<MineRequest> &reqs, const std::vector<uint64_t> &ids)
+{
+    if (reqs.size() > free_slots_.size()) {
+        set_error("too many jobs for this engine");
+        return DIC_E_INVAL;
+    }
+    std::vector<ActiveJob *> fresh;
+    const auto now = std::chrono::steady_clock::now();
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        ActiveJob *a = new ActiveJob;
+        a->id = ids[i];
+        a->req = reqs[i];
+        a->t0 = now;
+        fresh.push_back(a);
+    }
+    return add_internal(fresh);
+}
+
+int Engine::add_internal(std::vector<ActiveJob *> &fresh)
+{
+    const int rc = add_impl(fresh);
+    if (rc) {
+        // drop the jobs of a failed add; the caller reports them
+        for (ActiveJob *a : fresh) {
+            auto it = std::find(jobs_.begin(), jobs_.end(), a);
+            if (it != jobs_.end())
+                jobs_.erase(it);
+            if (a->slot >= 0)
+                free_slots_.push_back(a->slot);
+            delete a;
+        }
+        fresh.clear();
+        (void)hipStreamSynchronize(s_);
+    }
+    return rc;
+}
+
+int Engine::add_impl(std::vector<ActiveJob *> &fresh)
+{
+    if (fresh.empty())
+        return DIC_OK;
+    const unsigned long long *zob = zobrist(s_);
     if (!zob) {
         set_error("could not create the itemset hash table on the device");
         return DIC_E_DEVICE;
     }
-
-    // ---- stage A: states, item counts, frequent items, traces, plan
-    Carver ca;
-    const size_t a_jobs = ca.take(sizeof(Job) * njobs);
-    const size_t a_plan = ca.take(sizeof(Plan));
-    const size_t a_pre_count = ca.take(4ull * (njobs + 1));
-    const size_t a_pre_epi = ca.take(4ull * (njobs + 1));
-    const size_t a_pre_cg = ca.take(8ull * (njobs + 1));
-    const size_t a_pre_fp = ca.take(8ull * (njobs + 1));
-    const size_t a_states = ca.take(sizeof(JobState) * njobs);
-    const size_t a_outn = ca.take(4ull * njobs);
-    for (uint32_t j = 0; j < njobs; ++j) {
-        const MineRequest &r = reqs[j];
-        JobPlanHost &h = H[j];
-        uint64_t tau;
-        threshold(r.minsup, r.n, &tau);  // validated by the caller
-        h.n = r.n;
-        h.m = r.m;
-        h.W = (r.m + 63u) / 64u;
-        h.Mp = (uint32_t)std::min<uint64_t>(r.M, r.n);
-        h.stop_max = (uint32_t)((r.n + h.Mp - 1) / h.Mp);
-        h.tau = (uint32_t)tau;
-        h.a_cnt = ca.take(4ull * r.m);
-        h.a_l1 = ca.take(4ull * r.m);
-    }
-    DevBuf A;
-    if (!A.alloc(ca.off)) {
-        set_error("device allocation failed (job states)");
-        return DIC_E_NOMEM;
-    }
-    HIP_TRY(hipMemsetAsync(A.p, 0, ca.off, s));
-
-    std::vector<Job> jobs(njobs);
-    std::vector<DevBuf> traces(njobs);
-    for (uint32_t j = 0; j < njobs; ++j) {
-        JobPlanHost &h = H[j];
-        Job &J = jobs[j];
-        std::memset(&J, 0, sizeof(Job));
-        J.rows = reqs[j].rows;
-        J.n = (uint32_t)h.n;
-        J.m = h.m;
-        J.W = h.W;
-        J.Mp = h.Mp;
-        J.stop_max = h.stop_max;
-        J.tau = h.tau;
-        J.st = (JobState *)A.at(a_states) + j;
-        J.item_cnt = (uint32_t *)A.at(h.a_cnt);
-        J.l1 = (uint32_t *)A.at(h.a_l1);
-        J.out_n = (uint32_t *)A.at(a_outn) + j;
-        if (!traces[j].alloc(sizeof(dic_stop_trace) * h.trace_cap)) {
-            set_error("device allocation failed (trace)");
+    // one-time device buffers
+    if (!slab_) {
+        slab_ = dev_alloc(sizeof(JobState) * max_jobs_ + 4ull * max_jobs_);
+        table_ = dev_alloc(sizeof(Job) * max_jobs_);
+        table_aux_ = dev_alloc(sizeof(Job) * max_jobs_);
+        Carver c;
+        const size_t p0 = c.take(sizeof(Plan)), p1 = c.take(sizeof(Plan));
+        const size_t a0 = c.take(4ull * (max_jobs_ + 1)), a1 = c.take(4ull * (max_jobs_ + 1));
+        const size_t a2 = c.take(8ull * (max_jobs_ + 1)), a3 = c.take(8ull * (max_jobs_ + 1));
+        const size_t b0 = c.take(4ull * (max_jobs_ + 1)), b1 = c.take(4ull * (max_jobs_ + 1));
+        const size_t b2 = c.take(8ull * (max_jobs_ + 1)), b3 = c.take(8ull * (max_jobs_ + 1));
+        plan_buf_ = dev_alloc(c.off);
+        if (!slab_ || !table_ || !table_aux_ || !plan_buf_) {
+            set_error("device allocation failed (engine tables)");
             return DIC_E_NOMEM;
         }
-        J.trace = (dic_stop_trace *)traces[j].p;
-        J.trace_cap = h.trace_cap;
+        char *pb = (char *)plan_buf_;
+        d_plan_step_ = (Plan *)(pb + p0);
+        d_plan_aux_ = (Plan *)(pb + p1);
+        plan_step_.pre_count = (uint32_t *)(pb + a0);
+        plan_step_.pre_epi = (uint32_t *)(pb + a1);
+        plan_step_.pre_cg = (unsigned long long *)(pb + a2);
+        plan_step_.pre_fp = (unsigned long long *)(pb + a3);
+        plan_aux_.pre_count = (uint32_t *)(pb + b0);
+        plan_aux_.pre_epi = (uint32_t *)(pb + b1);
+        plan_aux_.pre_cg = (unsigned long long *)(pb + b2);
+        plan_aux_.pre_fp = (unsigned long long *)(pb + b3);
+        plan_step_.zobrist = plan_aux_.zobrist = zob;
+        HIP_TRY(hipMemsetAsync(slab_, 0, sizeof(JobState) * max_jobs_ + 4ull * max_jobs_, s_));
     }
-    Job *d_jobs = (Job *)A.at(a_jobs);
-    Plan *d_plan = (Plan *)A.at(a_plan);
-    Plan plan{};
-    plan.njobs = njobs;
-    plan.pre_count = (uint32_t *)A.at(a_pre_count);
-    plan.pre_epi = (uint32_t *)A.at(a_pre_epi);
-    plan.pre_cg = (unsigned long long *)A.at(a_pre_cg);
-    plan.pre_fp = (unsigned long long *)A.at(a_pre_fp);
-    plan.zobrist = zob;
+    JobState *states = (JobState *)slab_;
+    uint32_t *outn = (uint32_t *)(states + max_jobs_);
 
-    std::vector<unsigned long long> pre(njobs + 1, 0);
-    for (uint32_t j = 0; j < njobs; ++j)
-        pre[j + 1] = pre[j] + (H[j].n + FP_ROWS - 1) / FP_ROWS;
-    HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(Job) * njobs, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_plan, &plan, sizeof(Plan), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(plan.pre_fp, pre.data(), 8ull * (njobs + 1), hipMemcpyHostToDevice, s));
-    launch_first_pass(d_jobs, d_plan, pre[njobs], s);
-    launch_l1_and_pairs_prepare(d_jobs, d_plan, njobs, s);
-    HIP_TRY(hipGetLastError());
-
-    std::vector<JobState> st(njobs);
-    auto read_states = [&]() -> int {
-        HIP_TRY(hipMemcpyAsync(st.data(), A.at(a_states), sizeof(JobState) * njobs,
-                               hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        return DIC_OK;
-    };
-    int rc = read_states();
+    // ---- per-job small buffers and records
+    const uint32_t nf = (uint32_t)fresh.size();
+    int rc = DIC_OK;
+    for (ActiveJob *a : fresh) {
+        const MineRequest &r = a->req;
+        uint64_t tau = 0;
+        threshold(r.minsup, r.n, &tau);  // validated by the caller
+        a->W = (r.m + 63u) / 64u;
+        a->Mp = (uint32_t)std::min<uint64_t>(r.M, r.n);
+        a->stop_max = (uint32_t)((r.n + a->Mp - 1) / a->Mp);
+        a->tau = (uint32_t)tau;
+        jobs_.push_back(a);  // owned by the engine from here on
+        if (free_slots_.empty()) {
+            set_error("too many jobs for this engine");
+            return DIC_E_INVAL;
+        }
+        a->slot = free_slots_.back();
+        free_slots_.pop_back();
+        a->small = dev_alloc(8ull * r.m + 256);
+        a->trace = dev_alloc(sizeof(dic_stop_trace) * a->trace_cap);
+        if (!a->small || !a->trace) {
+            rc = DIC_E_NOMEM;
+            set_error("device allocation failed (job records)");
+        }
+    }
     if (rc)
         return rc;
+    aux_host_.assign(nf, Job{});
+    for (uint32_t i = 0; i < nf; ++i) {
+        ActiveJob *a = fresh[i];
+        Job &J = a->job;
+        std::memset(&J, 0, sizeof(Job));
+        J.rows = a->req.rows;
+        J.n = a->req.n;
+        J.m = a->req.m;
+        J.W = a->W;
+        J.Mp = a->Mp;
+        J.stop_max = a->stop_max;
+        J.tau = a->tau;
+        J.item_cnt = (uint32_t *)a->small;
+        J.l1 = (uint32_t *)((char *)a->small + align_up(4ull * a->req.m, 256));
+        J.st = states + a->slot;
+        J.out_n = outn + a->slot;
+        J.trace = (dic_stop_trace *)a->trace;
+        J.trace_cap = a->trace_cap;
+        HIP_TRY(hipMemsetAsync(J.st, 0, sizeof(JobState), s_));
+        HIP_TRY(hipMemsetAsync(J.item_cnt, 0, 4ull * a->req.m, s_));
+        aux_host_[i] = J;
+    }
 
-    // ---- stage B: candidate pools sized from the pair count
-    Carver cb;
-    std::vector<size_t> b_off(njobs);
-    std::vector<uint64_t> hslots(njobs);
-    for (uint32_t j = 0; j < njobs; ++j) {
-        JobPlanHost &h = H[j];
-        h.nL1 = st[j].nL1;
-        const uint64_t nC2 = (uint64_t)h.nL1 * (h.nL1 ? h.nL1 - 1 : 0) / 2;
-        uint64_t cap = std::max<uint64_t>(16384, 4 * nC2 + 16384) * cap_mult[j];
+    // ---- FirstPass for the new jobs
+    pre_host_.assign(nf + 1, 0);
+    for (uint32_t i = 0; i < nf; ++i)
+        pre_host_[i + 1] = pre_host_[i] + (fresh[i]->req.n + FP_ROWS - 1) / FP_ROWS;
+    plan_aux_.njobs = nf;
+    HIP_TRY(hipMemcpyAsync(table_aux_, aux_host_.data(), sizeof(Job) * nf,
+                           hipMemcpyHostToDevice, s_));
+    HIP_TRY(hipMemcpyAsync(d_plan_aux_, &plan_aux_, sizeof(Plan), hipMemcpyHostToDevice, s_));
+    HIP_TRY(hipMemcpyAsync(plan_aux_.pre_fp, pre_host_.data(), 8ull * (nf + 1),
+                           hipMemcpyHostToDevice, s_));
+    launch_first_pass((const Job *)table_aux_, d_plan_aux_, pre_host_[nf], s_);
+    launch_l1_and_pairs_prepare((const Job *)table_aux_, d_plan_aux_, nf, s_);
+    HIP_TRY(hipGetLastError());
+    if ((rc = read_states()))
+        return rc;
+
+    // ---- candidate pools sized from the frequent-item count
+    for (uint32_t i = 0; i < nf; ++i) {
+        ActiveJob *a = fresh[i];
+        Job &J = a->job;
+        a->nL1 = st_[a->slot].nL1;
+        const uint64_t cap = pool_cap_for(a->nL1, a->mult);
         if (cap > 0x7FFFFFFFull) {
             set_error("candidate pool would exceed 2^31 itemsets");
             return DIC_E_NOMEM;
         }
-        h.cap = (uint32_t)cap;
-        hslots[j] = next_pow2(2 * cap);
-        b_off[j] = cb.off;
-        cb.take(cap * h.W * 8);   // pmask
-        cb.take(cap * 8);         // phash
-        cb.take(cap * 8);         // pnz
-        for (int f = 0; f < 5; ++f)
-            cb.take(cap * 4);     // psupp pstop pstate ppromo pk
-        cb.take(hslots[j] * 8);   // slots
-        for (int f = 0; f < 3; ++f)
-            cb.take(cap * 4);     // live0 live1 newbox
-        cb.take(cap * h.W * 8);   // out_mask
-        cb.take(cap * 4);         // out_cnt
+        a->cap = (uint32_t)cap;
+        PoolLayout L(cap, a->W);
+        a->pool = dev_alloc(L.bytes);
+        if (!a->pool) {
+            set_error("device allocation failed (candidate pool)");
+            return DIC_E_NOMEM;
+        }
+        char *b = (char *)a->pool;
+        J.cap = a->cap;
+        J.hmask = (uint32_t)(L.hslots - 1);
+        J.pmask = (uint64_t *)(b + L.mask);
+        J.phash = (unsigned long long *)(b + L.hash);
+        J.pnz = (uint64_t *)(b + L.nz);
+        J.psupp = (uint32_t *)(b + L.supp);
+        J.pstop = (uint32_t *)(b + L.stop);
+        J.pstate = (uint32_t *)(b + L.state);
+        J.ppromo = (uint32_t *)(b + L.promo);
+        J.pk = (uint32_t *)(b + L.k);
+        J.slots = (unsigned long long *)(b + L.slots);
+        J.live0 = (uint32_t *)(b + L.live0);
+        J.live1 = (uint32_t *)(b + L.live1);
+        J.newbox = (uint32_t *)(b + L.newbox);
+        J.out_mask = (uint64_t *)(b + L.omask);
+        J.out_cnt = (uint32_t *)(b + L.ocnt);
+        HIP_TRY(hipMemsetAsync(J.slots, 0xFF, L.hslots * 8, s_));
+        aux_host_[i] = J;
     }
-    DevBuf B;
-    if (!B.alloc(cb.off)) {
-        set_error("device allocation failed (candidate pools)");
-        return DIC_E_NOMEM;
-    }
-    for (uint32_t j = 0; j < njobs; ++j) {
-        JobPlanHost &h = H[j];
-        Job &J = jobs[j];
-        Carver c;
-        c.off = b_off[j];
-        const uint64_t cap = h.cap;
-        J.cap = h.cap;
-        J.hmask = (uint32_t)(hslots[j] - 1);
-        J.pmask = (uint64_t *)B.at(c.take(cap * h.W * 8));
-        J.phash = (unsigned long long *)B.at(c.take(cap * 8));
-        J.pnz = (uint64_t *)B.at(c.take(cap * 8));
-        J.psupp = (uint32_t *)B.at(c.take(cap * 4));
-        J.pstop = (uint32_t *)B.at(c.take(cap * 4));
-        J.pstate = (uint32_t *)B.at(c.take(cap * 4));
-        J.ppromo = (uint32_t *)B.at(c.take(cap * 4));
-        J.pk = (uint32_t *)B.at(c.take(cap * 4));
-        J.slots = (unsigned long long *)B.at(c.take(hslots[j] * 8));
-        J.live0 = (uint32_t *)B.at(c.take(cap * 4));
-        J.live1 = (uint32_t *)B.at(c.take(cap * 4));
-        J.newbox = (uint32_t *)B.at(c.take(cap * 4));
-        J.out_mask = (uint64_t *)B.at(c.take(cap * h.W * 8));
-        J.out_cnt = (uint32_t *)B.at(c.take(cap * 4));
-        HIP_TRY(hipMemsetAsync(J.slots, 0xFF, hslots[j] * 8, s));
-    }
-    HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(Job) * njobs, hipMemcpyHostToDevice, s));
-    for (uint32_t j = 0; j < njobs; ++j)
-        pre[j + 1] = pre[j] + (unsigned long long)H[j].nL1 * H[j].nL1;
-    HIP_TRY(hipMemcpyAsync(plan.pre_cg, pre.data(), 8ull * (njobs + 1), hipMemcpyHostToDevice, s));
-    if (pre[njobs])
-        launch_init_pairs(d_jobs, d_plan, pre[njobs], s);
+    for (uint32_t i = 0; i < nf; ++i)
+        pre_host_[i + 1] = pre_host_[i] + (unsigned long long)fresh[i]->nL1 * fresh[i]->nL1;
+    HIP_TRY(hipMemcpyAsync(table_aux_, aux_host_.data(), sizeof(Job) * nf,
+                           hipMemcpyHostToDevice, s_));
+    HIP_TRY(hipMemcpyAsync(plan_aux_.pre_cg, pre_host_.data(), 8ull * (nf + 1),
+                           hipMemcpyHostToDevice, s_));
+    if (pre_host_[nf])
+        launch_init_pairs((const Job *)table_aux_, d_plan_aux_, pre_host_[nf], s_);
     HIP_TRY(hipGetLastError());
+    // the host buffers above must outlive the copies: settle before returning
+    HIP_TRY(hipStreamSynchronize(s_));
+    for (ActiveJob *a : fresh)
+        a->in_loop = true;
+    table_dirty_ = true;
+    return DIC_OK;
+}
 
-    // ---- stop loop
-    uint32_t steps = 0;
-    for (uint32_t j = 0; j < njobs; ++j)
-        steps = std::max(steps, st[j].max_rem);
-    for (;;) {
-        bool running = false;
-        for (uint32_t j = 0; j < njobs; ++j)
-            running |= !st[j].done && !st[j].overflow && st[j].k_next > 0;
-        if (!running)
-            break;
-        uint32_t S = std::min(std::max(steps, 1u), MAX_STEPS_PER_SYNC);
-        // every stop writes one trace entry: make room for S more
-        bool table_dirty = false;
-        for (uint32_t j = 0; j < njobs; ++j) {
-            if (st[j].epoch + S <= H[j].trace_cap)
-                continue;
-            uint32_t nc = H[j].trace_cap;
-            while (nc < st[j].epoch + S)
-                nc *= 2;
-            DevBuf nb;
-            if (!nb.alloc(sizeof(dic_stop_trace) * nc)) {
-                set_error("device allocation failed (trace)");
-                return DIC_E_NOMEM;
+int Engine::upload_table()
+{
+    table_host_.clear();
+    for (ActiveJob *a : jobs_)
+        if (a->in_loop)
+            table_host_.push_back(a->job);
+    plan_step_.njobs = (uint32_t)table_host_.size();
+    if (!table_host_.empty())
+        HIP_TRY(hipMemcpyAsync(table_, table_host_.data(), sizeof(Job) * table_host_.size(),
+                               hipMemcpyHostToDevice, s_));
+    HIP_TRY(hipMemcpyAsync(d_plan_step_, &plan_step_, sizeof(Plan), hipMemcpyHostToDevice, s_));
+    table_dirty_ = false;
+    return DIC_OK;
+}
+
+int Engine::ensure_trace(uint32_t steps)
+{
+    for (ActiveJob *a : jobs_) {
+        if (!a->in_loop)
+            continue;
+        const uint32_t epoch = st_[a->slot].epoch;
+        if (epoch + steps <= a->trace_cap)
+            continue;
+        uint32_t nc = a->trace_cap;
+        while (nc < epoch + steps)
+            nc *= 2;
+        void *nb = dev_alloc(sizeof(dic_stop_trace) * nc);
+        if (!nb) {
+            set_error("device allocation failed (trace)");
+            return DIC_E_NOMEM;
+        }
+        HIP_TRY(hipMemcpyAsync(nb, a->trace, sizeof(dic_stop_trace) * a->trace_cap,
+                               hipMemcpyDeviceToDevice, s_));
+        HIP_TRY(hipStreamSynchronize(s_));
+        dev_free(a->trace);
+        a->trace = nb;
+        a->trace_cap = nc;
+        a->job.trace = (dic_stop_trace *)nb;
+        a->job.trace_cap = nc;
+        table_dirty_ = true;
+    }
+    return DIC_OK;
+}
+
+int Engine::advance(uint32_t max_steps)
+{
+    if (!running())
+        return DIC_OK;
+    uint32_t S = 1;
+    for (ActiveJob *a : jobs_) {
+        const JobState &s = st_[a->slot];
+        if (a->in_loop && !s.done && !s.overflow && s.k_next > 0)
+            S = std::max(S, s.max_rem);
+    }
+    S = std::min(S, std::max(1u, max_steps));
+    int rc = ensure_trace(S);
+    if (rc)
+        return rc;
+    if (table_dirty_ && (rc = upload_table()))
+        return rc;
+    const bool prof = profiling();
+    if (prof) {
+        while (events_.size() < 2 * S) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            events_.push_back(e);
+        }
+    }
+    for (uint32_t k = 0; k < S; ++k)
+        launch_step((const Job *)table_, d_plan_step_, s_, prof ? events_[2 * k] : nullptr,
+                    prof ? events_[2 * k + 1] : nullptr);
+    HIP_TRY(hipGetLastError());
+    if ((rc = read_states()))
+        return rc;
+    if (prof) {
+        double ms = 0;
+        for (uint32_t k = 0; k < S; ++k) {
+            float t = 0;
+            HIP_TRY(hipEventElapsedTime(&t, events_[2 * k], events_[2 * k + 1]));
+            ms += t;
+        }
+        for (ActiveJob *a : jobs_)
+            if (a->in_loop) {
+                a->count_ms += ms;
+                a->count_launches += S;
             }
-            HIP_TRY(hipMemcpyAsync(nb.p, traces[j].p, sizeof(dic_stop_trace) * H[j].trace_cap,
-                                   hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            std::swap(nb.p, traces[j].p);
-            H[j].trace_cap = nc;
-            jobs[j].trace = (dic_stop_trace *)traces[j].p;
-            jobs[j].trace_cap = nc;
-            table_dirty = true;
-        }
-        if (table_dirty)
-            HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(Job) * njobs, hipMemcpyHostToDevice,
-                                   s));
-        for (uint32_t k = 0; k < S; ++k)
-            launch_step(d_jobs, d_plan, njobs, s);
-        HIP_TRY(hipGetLastError());
-        if ((rc = read_states()))
-            return rc;
-        steps = 0;
-        for (uint32_t j = 0; j < njobs; ++j)
-            if (!st[j].done && !st[j].overflow && st[j].k_next > 0)
-                steps = std::max(steps, st[j].max_rem);
     }
+    return DIC_OK;
+}
 
-    // ---- collect
-    launch_collect(d_jobs, d_plan, njobs, s);
+int Engine::collect(std::vector<ActiveJob *> &fin,
+                    std::vector<std::pair<uint64_t, MineOutput>> &out)
+{
+    const uint32_t nf = (uint32_t)fin.size();
+    JobState *states = (JobState *)slab_;
+    uint32_t *outn_d = (uint32_t *)(states + max_jobs_);
+    aux_host_.assign(nf, Job{});
+    for (uint32_t i = 0; i < nf; ++i) {
+        aux_host_[i] = fin[i]->job;
+        HIP_TRY(hipMemsetAsync(outn_d + fin[i]->slot, 0, 4, s_));
+    }
+    HIP_TRY(hipMemcpyAsync(table_aux_, aux_host_.data(), sizeof(Job) * nf, hipMemcpyHostToDevice,
+                           s_));
+    launch_collect((const Job *)table_aux_, d_plan_aux_, nf, s_);
     HIP_TRY(hipGetLastError());
-    std::vector<uint32_t> outn(njobs);
-    HIP_TRY(hipMemcpyAsync(outn.data(), A.at(a_outn), 4ull * njobs, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    std::vector<std::vector<uint64_t>> om(njobs);
-    std::vector<std::vector<uint32_t>> oc(njobs), icnt(njobs);
-    for (uint32_t j = 0; j < njobs; ++j) {
-        MineOutput &o = outs[j];
-        overflowed[j] = st[j].overflow != 0;
-        if (overflowed[j])
-            continue;
-        const uint32_t W = H[j].W;
-        om[j].resize((size_t)outn[j] * W);
-        oc[j].resize(outn[j]);
-        icnt[j].resize(H[j].m);
-        if (outn[j]) {
-            HIP_TRY(hipMemcpyAsync(om[j].data(), jobs[j].out_mask, 8ull * outn[j] * W,
-                                   hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(oc[j].data(), jobs[j].out_cnt, 4ull * outn[j],
-                                   hipMemcpyDeviceToHost, s));
-        }
-        HIP_TRY(hipMemcpyAsync(icnt[j].data(), jobs[j].item_cnt, 4ull * H[j].m,
-                               hipMemcpyDeviceToHost, s));
-        const uint32_t ntr = std::min(st[j].epoch, H[j].trace_cap);
-        o.trace.resize(ntr);
-        if (ntr)
-            HIP_TRY(hipMemcpyAsync(o.trace.data(), jobs[j].trace, sizeof(dic_stop_trace) * ntr,
-                                   hipMemcpyDeviceToHost, s));
-    }
-    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<uint32_t> outn(max_jobs_);
+    HIP_TRY(hipMemcpyAsync(outn.data(), outn_d, 4ull * max_jobs_, hipMemcpyDeviceToHost, s_));
+    HIP_TRY(hipStreamSynchronize(s_));
 
-    for (uint32_t j = 0; j < njobs; ++j) {
-        if (overflowed[j])
-            continue;
-        MineOutput &o = outs[j];
-        const uint32_t W = H[j].W;
+    std::vector<std::vector<uint64_t>> om(nf);
+    std::vector<std::vector<uint32_t>> oc(nf), icnt(nf);
+    std::vector<MineOutput> res(nf);
+    for (uint32_t i = 0; i < nf; ++i) {
+        ActiveJob *a = fin[i];
+        const uint32_t q = outn[a->slot];
+        om[i].resize((size_t)q * a->W);
+        oc[i].resize(q);
+        icnt[i].resize(a->req.m);
+        if (q) {
+            HIP_TRY(hipMemcpyAsync(om[i].data(), a->job.out_mask, 8ull * q * a->W,
+                                   hipMemcpyDeviceToHost, s_));
+            HIP_TRY(hipMemcpyAsync(oc[i].data(), a->job.out_cnt, 4ull * q, hipMemcpyDeviceToHost,
+                                   s_));
+        }
+        HIP_TRY(hipMemcpyAsync(icnt[i].data(), a->job.item_cnt, 4ull * a->req.m,
+                               hipMemcpyDeviceToHost, s_));
+        const uint32_t ntr = std::min(st_[a->slot].epoch, a->trace_cap);
+        res[i].trace.resize(ntr);
+        if (ntr)
+            HIP_TRY(hipMemcpyAsync(res[i].trace.data(), a->trace, sizeof(dic_stop_trace) * ntr,
+                                   hipMemcpyDeviceToHost, s_));
+    }
+    HIP_TRY(hipStreamSynchronize(s_));
+    const auto now = std::chrono::steady_clock::now();
+
+    for (uint32_t i = 0; i < nf; ++i) {
+        ActiveJob *a = fin[i];
+        const JobState &s = st_[a->slot];
+        MineOutput &o = res[i];
+        const uint32_t W = a->W;
         // L = frequent items followed by the collected solid boxes
         std::vector<uint64_t> masks;
         std::vector<uint32_t> counts;
-        for (uint32_t i = 0; i < H[j].m; ++i)
-            if (icnt[j][i] >= H[j].tau) {
-                size_t b = masks.size();
+        for (uint32_t it = 0; it < a->req.m; ++it)
+            if (icnt[i][it] >= a->tau) {
+                const size_t b = masks.size();
                 masks.resize(b + W, 0);
-                masks[b + (i >> 6)] = 1ull << (i & 63);
-                counts.push_back(icnt[j][i]);
+                masks[b + (it >> 6)] = 1ull << (it & 63);
+                counts.push_back(icnt[i][it]);
             }
-        masks.insert(masks.end(), om[j].begin(), om[j].end());
-        counts.insert(counts.end(), oc[j].begin(), oc[j].end());
+        masks.insert(masks.end(), om[i].begin(), om[i].end());
+        counts.insert(counts.end(), oc[i].begin(), oc[i].end());
         const size_t q = counts.size();
         std::vector<uint32_t> k(q), idx(q);
         for (size_t t = 0; t < q; ++t) {
@@ -433,8 +629,8 @@ static int run_once(const std::vector<MineRequest> &reqs, std::vector<MineOutput
             k[t] = c;
         }
         std::iota(idx.begin(), idx.end(), 0u);
-        std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
-            return canon_less(&masks[(size_t)a * W], &masks[(size_t)b * W], W, k[a], k[b]);
+        std::sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) {
+            return canon_less(&masks[(size_t)x * W], &masks[(size_t)y * W], W, k[x], k[y]);
         });
         o.masks.resize(q * W);
         o.counts.resize(q);
@@ -445,69 +641,132 @@ static int run_once(const std::vector<MineRequest> &reqs, std::vector<MineOutput
             kmax = std::max<uint64_t>(kmax, k[idx[t]]);
         }
         dic_stats &S = o.stats;
-        S.tau = H[j].tau;
-        S.block = H[j].Mp;
-        S.stop_max = H[j].stop_max;
-        S.stops = st[j].epoch;
-        S.tests = st[j].tests;
-        S.peak_live = st[j].peak_K;
+        S.tau = a->tau;
+        S.block = a->Mp;
+        S.stop_max = a->stop_max;
+        S.stops = s.epoch;
+        S.tests = s.tests;
+        S.peak_live = s.peak_K;
         S.n_frequent = q;
         S.k_max = kmax;
-        S.known = (uint64_t)H[j].m + std::min(st[j].pool_n, H[j].cap);
-        o.status = st[j].asserts ? DIC_E_DEVICE : DIC_OK;
+        S.known = (uint64_t)a->req.m + std::min(s.pool_n, a->cap);
+        S.restarts = a->restarts;
+        S.mine_ms = std::chrono::duration<double, std::milli>(now - a->t0).count();
+        S.count_ms = a->count_ms;
+        S.count_launches = a->count_launches;
+        o.status = s.asserts ? DIC_E_DEVICE : DIC_OK;
+        out.emplace_back(a->id, std::move(o));
     }
     return DIC_OK;
 }
 
+int Engine::harvest(std::vector<std::pair<uint64_t, MineOutput>> &done)
+{
+    std::vector<ActiveJob *> fin, over, keep;
+    for (ActiveJob *a : jobs_) {
+        const JobState &s = st_[a->slot];
+        if (!a->in_loop) {
+            keep.push_back(a);
+        } else if (s.overflow) {
+            over.push_back(a);
+        } else if (s.done || s.k_next == 0) {
+            fin.push_back(a);
+        } else {
+            keep.push_back(a);
+        }
+    }
+    if (fin.empty() && over.empty())
+        return DIC_OK;
+    int rc = DIC_OK;
+    if (!fin.empty())
+        rc = collect(fin, done);
+    for (ActiveJob *a : fin) {
+        free_slots_.push_back(a->slot);
+        delete a;
+    }
+    jobs_.swap(keep);
+    table_dirty_ = true;
+    if (rc) {
+        for (ActiveJob *a : over)
+            delete a;
+        return rc;
+    }
+    // rerun overflowed jobs with four times the candidate room
+    std::vector<ActiveJob *> again;
+    for (ActiveJob *a : over) {
+        free_slots_.push_back(a->slot);
+        if (a->restarts >= MAX_RESTARTS) {
+            MineOutput o;
+            o.status = DIC_E_NOMEM;
+            set_error("candidate pool kept overflowing");
+            done.emplace_back(a->id, std::move(o));
+            delete a;
+            continue;
+        }
+        ActiveJob *b = new ActiveJob;
+        b->id = a->id;
+        b->req = a->req;
+        b->t0 = a->t0;
+        b->mult = a->mult * 4;
+        b->restarts = a->restarts + 1;
+        b->count_ms = a->count_ms;
+        b->count_launches = a->count_launches;
+        delete a;
+        again.push_back(b);
+    }
+    std::vector<uint64_t> again_ids;
+    for (ActiveJob *b : again)
+        again_ids.push_back(b->id);
+    const int arc = add_internal(again);
+    if (arc)
+        for (uint64_t id : again_ids) {
+            MineOutput o;
+            o.status = arc;
+            done.emplace_back(id, std::move(o));
+        }
+    return DIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// run a fixed set of jobs to completion
+// ---------------------------------------------------------------------------
+
 int run_jobs(const std::vector<MineRequest> &reqs, std::vector<MineOutput> &outs,
              hipStream_t stream)
 {
-    const auto t0 = std::chrono::steady_clock::now();
     outs.assign(reqs.size(), MineOutput{});
-    std::vector<uint32_t> idx(reqs.size());
-    std::iota(idx.begin(), idx.end(), 0u);
-    std::vector<uint32_t> mult(reqs.size(), 1u);
-    std::vector<uint32_t> restarts(reqs.size(), 0u);
-    for (int attempt = 0; !idx.empty(); ++attempt) {
-        if (attempt > 6) {
-            set_error("candidate pool kept overflowing");
-            for (uint32_t i : idx)
-                outs[i].status = DIC_E_NOMEM;
+    if (reqs.empty())
+        return DIC_OK;
+    const uint32_t cap = (uint32_t)std::min<size_t>(reqs.size(), 4096);
+    Engine eng(stream, cap);
+    std::vector<uint64_t> ids(reqs.size());
+    std::iota(ids.begin(), ids.end(), 0ull);
+    size_t next = 0;
+    std::vector<std::pair<uint64_t, MineOutput>> done;
+    int rc = DIC_OK;
+    while (next < reqs.size() || eng.size() > 0) {
+        // keep the engine full: add as many pending jobs as it has room for
+        const size_t room = cap - eng.size();
+        if (next < reqs.size() && room > 0) {
+            const size_t take = std::min(room, reqs.size() - next);
+            std::vector<MineRequest> r(reqs.begin() + next, reqs.begin() + next + take);
+            std::vector<uint64_t> id(ids.begin() + next, ids.begin() + next + take);
+            if ((rc = eng.add(r, id)))
+                break;
+            next += take;
+        }
+        if ((rc = eng.advance(1024)))
             break;
-        }
-        std::vector<MineRequest> sub;
-        std::vector<uint32_t> m;
-        for (uint32_t i : idx) {
-            sub.push_back(reqs[i]);
-            m.push_back(mult[i]);
-        }
-        std::vector<MineOutput> so(sub.size());
-        std::vector<char> ov(sub.size(), 0);
-        int rc = run_once(sub, so, m, ov, stream);
-        if (rc) {
-            for (uint32_t i : idx)
-                outs[i].status = rc;
-            return rc;
-        }
-        std::vector<uint32_t> again;
-        for (size_t t = 0; t < idx.size(); ++t) {
-            const uint32_t i = idx[t];
-            if (ov[t]) {
-                mult[i] *= 4;
-                restarts[i]++;
-                again.push_back(i);
-            } else {
-                outs[i] = std::move(so[t]);
-            }
-        }
-        idx.swap(again);
+        if ((rc = eng.harvest(done)))
+            break;
     }
-    const double ms =
-        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    for (size_t i = 0; i < outs.size(); ++i) {
-        outs[i].stats.restarts = restarts[i];
-        outs[i].stats.mine_ms = ms;
+    if (rc) {
+        for (auto &o : outs)
+            o.status = rc;
+        return rc;
     }
+    for (auto &d : done)
+        outs[d.first] = std::move(d.second);
     return DIC_OK;
 }
 

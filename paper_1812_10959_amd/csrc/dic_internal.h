@@ -109,7 +109,10 @@ void launch_first_pass(const Job *jobs, const Plan *plan, unsigned long long tot
                        hipStream_t s);
 void launch_l1_and_pairs_prepare(const Job *jobs, const Plan *plan, uint32_t njobs, hipStream_t s);
 void launch_init_pairs(const Job *jobs, const Plan *plan, unsigned long long total, hipStream_t s);
-void launch_step(const Job *jobs, const Plan *plan, uint32_t njobs, hipStream_t s);
+// One stop for every job in the table; when given, the two events bracket
+// the CountSupport launch on stream s.
+void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, hipEvent_t before = nullptr,
+                 hipEvent_t after = nullptr);
 void launch_collect(const Job *jobs, const Plan *plan, uint32_t njobs, hipStream_t s);
 void launch_pack_lists(const uint32_t *items, const uint64_t *offsets, uint64_t n, uint32_t W,
                        uint64_t *rows, hipStream_t s);
@@ -147,8 +150,61 @@ bool threshold(double minsup, uint64_t n, uint64_t *tau);
 int run_jobs(const std::vector<MineRequest> &reqs, std::vector<MineOutput> &outs,
              hipStream_t stream);
 
-// Device bytes a request needs with a given candidate capacity.
-uint64_t job_bytes(uint32_t n, uint32_t m, uint32_t cap, uint32_t trace_cap);
+// Device bytes of a job's working memory for a given candidate capacity.
+uint64_t job_bytes(uint32_t m, uint64_t cap, uint32_t trace_cap);
+// Upper bound of a job's working memory before its first pass (every item
+// frequent), used for admission.
+uint64_t job_bytes_bound(uint32_t m);
+
+bool profiling();
+void set_profiling(int on);
+
+struct ActiveJob;
+
+// A set of jobs mined together on one stream.  Jobs can be added between
+// step chunks (their first pass runs at once); every advance() runs up to
+// max_steps stops for all unfinished jobs with one launch per kernel per
+// stop; harvest() hands back finished jobs and releases their memory.  A
+// job whose candidate pool overflowed is restarted with four times the room.
+// Not thread-safe: one owner thread.
+class Engine {
+  public:
+    Engine(hipStream_t s, uint32_t max_jobs);
+    ~Engine();
+    Engine(const Engine &) = delete;
+    Engine &operator=(const Engine &) = delete;
+
+    int add(const std::vector<MineRequest> &reqs, const std::vector<uint64_t> &ids);
+    int advance(uint32_t max_steps);
+    int harvest(std::vector<std::pair<uint64_t, MineOutput>> &done);
+    size_t size() const { return jobs_.size(); }
+    bool running() const;
+    uint64_t job_bytes_of(uint64_t id) const;
+
+  private:
+    int add_internal(std::vector<ActiveJob *> &fresh);
+    int add_impl(std::vector<ActiveJob *> &fresh);
+    int read_states();
+    int upload_table();
+    int ensure_trace(uint32_t steps);
+    int collect(std::vector<ActiveJob *> &fin, std::vector<std::pair<uint64_t, MineOutput>> &out);
+
+    hipStream_t s_;
+    uint32_t max_jobs_;
+    std::vector<ActiveJob *> jobs_;
+    std::vector<int> free_slots_;
+    void *slab_ = nullptr;       // JobState[max_jobs] + out_n[max_jobs]
+    void *table_ = nullptr;      // Job[max_jobs] for the step kernels
+    void *table_aux_ = nullptr;  // Job[max_jobs] for first pass / collection
+    void *plan_buf_ = nullptr;   // two Plans and their prefix arrays
+    Plan *d_plan_step_ = nullptr, *d_plan_aux_ = nullptr;
+    Plan plan_step_{}, plan_aux_{};
+    std::vector<JobState> st_;   // host copy of the slab
+    std::vector<Job> table_host_, aux_host_;
+    std::vector<unsigned long long> pre_host_;
+    bool table_dirty_ = true;
+    std::vector<hipEvent_t> events_;
+};
 
 }  // namespace dic
 

@@ -66,6 +66,19 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *ctr, bool pred, bool u
     return pred ? atomicAdd(ctr, 1u) : 0u;
 }
 
+// Wave-aggregated add of a per-lane value (all lanes call).
+__device__ __forceinline__ void wave_add(uint32_t *ctr, uint32_t v, bool uniform)
+{
+    if (uniform) {
+        for (int off = 32; off > 0; off >>= 1)
+            v += (uint32_t)__shfl_xor((int)v, off);
+        if (lane_id() == 0 && v)
+            atomicAdd(ctr, v);
+    } else if (v) {
+        atomicAdd(ctr, v);
+    }
+}
+
 __device__ __forceinline__ void wave_max(uint32_t *ctr, uint32_t v, bool uniform)
 {
     if (uniform) {
@@ -309,7 +322,7 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
                         t.stop = stop;
                         t.rows = rows;
                         t.live = K;
-                        t.promoted = t.pruned = t.generated = t.solidified = t.reserved = 0;
+                        t.promoted = t.pruned = t.generated = t.solidified = t.words = 0;
                         J->trace[st->epoch - 1u] = t;
                     }
                     const uint32_t rt = row_tile_rows(J->W);
@@ -465,10 +478,18 @@ __global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
         const Job *J = jobs + j;
         JobState *st = J->st;
         bool promoted = false, pruned = false, solid = false, keep = false;
-        uint32_t p = 0, sc = 0;
+        uint32_t p = 0, sc = 0, words = 0;
         if (valid) {
             const uint32_t c = x - plan->pre_epi[j];
             p = (st->parity ? J->live1 : J->live0)[c];
+            // nonzero 32-bit words of this candidate: its AND work per row
+            uint64_t nzw = J->pnz[p];
+            const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+            while (nzw) {
+                const uint64_t v = cm[__builtin_ctzll(nzw)];
+                nzw &= nzw - 1;
+                words += ((uint32_t)v != 0u) + ((uint32_t)(v >> 32) != 0u);
+            }
             sc = J->pstop[p] + 1u;
             J->pstop[p] = sc;
             uint32_t state = J->pstate[p];
@@ -505,11 +526,14 @@ __global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
         dic_stop_trace *tr = trace_of(J, st);
         if (uniform) {
             if (tr) {
+                wave_add(&tr->words, words, true);
                 wave_append(&tr->promoted, promoted, true);
                 wave_append(&tr->pruned, pruned, true);
                 wave_append(&tr->solidified, solid, true);
             }
         } else if (tr) {
+            if (words)
+                atomicAdd(&tr->words, words);
             if (promoted)
                 atomicAdd(&tr->promoted, 1u);
             if (pruned)
@@ -719,11 +743,16 @@ void launch_init_pairs(const Job *jobs, const Plan *plan, unsigned long long tot
                        total);
 }
 
-void launch_step(const Job *jobs, const Plan *plan, uint32_t, hipStream_t s)
+void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, hipEvent_t before,
+                 hipEvent_t after)
 {
     Plan *pl = const_cast<Plan *>(plan);
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(WG), 0, s, jobs, pl);
+    if (before)
+        (void)hipEventRecord(before, s);
     hipLaunchKernelGGL(k_count, dim3(GRID_COUNT), dim3(WG), 0, s, jobs, plan);
+    if (after)
+        (void)hipEventRecord(after, s);
     hipLaunchKernelGGL(k_epilogue, dim3(GRID_EPI), dim3(WG), 0, s, jobs, plan);
     hipLaunchKernelGGL(k_plan_cg, dim3(1), dim3(WG), 0, s, jobs, pl);
     hipLaunchKernelGGL(k_candgen, dim3(GRID_CG), dim3(WG), 0, s, jobs, plan);

@@ -1,11 +1,358 @@
-// Serving entry points (placeholder until the continuous-batching scheduler lands).
+// Serving: a request loop over resident databases with continuous batching.
+//
+// One worker thread owns an Engine (its own stream).  Requests queue in
+// arrival order; the worker admits the head of the queue whenever a slot is
+// free and the request's memory bound fits the remaining budget, runs the
+// admitted requests' first passes, and then advances every admitted request
+// together a few stops at a time (one launch per kernel per stop for all of
+// them), so requests that arrive while others are running join at the next
+// stop chunk.  Finished requests free their slot and budget at once.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
 #include "dic_internal.h"
+
 using namespace dic;
-extern "C" {
-int dic_serve_create(uint64_t, const dic_serve_opts *, dic_server **out) { if (out) *out = nullptr; set_error("serving not available"); return DIC_E_INVAL; }
-int dic_serve_submit(dic_server *, dic_db *, double, uint64_t, uint64_t *) { return DIC_E_INVAL; }
-int dic_serve_poll(dic_server *, uint64_t, dic_result **) { return DIC_E_INVAL; }
-int dic_serve_wait(dic_server *, uint64_t, int64_t, dic_result **) { return DIC_E_INVAL; }
-int dic_serve_stats(dic_server *, double *, double *, double *) { return DIC_E_INVAL; }
-int dic_serve_destroy(dic_server *) { return DIC_OK; }
+
+namespace dic {
+// accessors implemented next to the database object
+const uint64_t *db_rows(dic_db *db);
+uint64_t db_n(dic_db *db);
+uint32_t db_m(dic_db *db);
+uint32_t db_W(dic_db *db);
+void db_ref(dic_db *db, int delta);
+}  // namespace dic
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+// Stops advanced between admission checks: small enough that an arriving
+// request waits at most a few stops, large enough to amortise a readback.
+constexpr uint32_t SERVE_STEPS = 8;
+
+struct Req {
+    uint64_t ticket;
+    dic_db *db;
+    double minsup;
+    uint64_t M;
+    uint64_t bytes;  // budget charged while admitted
+    clk::time_point submit;
+    bool admitted = false, done = false;
+    int status = DIC_OK;
+    MineOutput out;
+};
+
+}  // namespace
+
+struct dic_server {
+    uint64_t budget = 0;
+    uint32_t max_active = 64;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> queue;
+    std::map<uint64_t, std::unique_ptr<Req>> reqs;
+    uint64_t next_ticket = 1;
+    uint64_t used = 0;
+    uint32_t active = 0;
+    bool stopping = false;
+    std::vector<double> lat_ms;
+    bool any = false;
+    clk::time_point first_submit, last_done;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::thread worker;
+};
+
+namespace {
+
+void finish(dic_server *S, Req *r, int status, MineOutput &&o)
+{
+    // called with S->mu held
+    r->status = status;
+    r->out = std::move(o);
+    r->done = true;
+    S->used -= r->bytes;
+    S->active--;
+    db_ref(r->db, -1);
+    const auto now = clk::now();
+    S->lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->submit).count());
+    S->last_done = now;
 }
+
+void worker_main(dic_server *S)
+{
+    (void)hipSetDevice(S->device);
+    Engine eng(S->stream, S->max_active);
+    std::vector<std::pair<uint64_t, MineOutput>> done;
+    for (;;) {
+        std::vector<MineRequest> add;
+        std::vector<uint64_t> ids;
+        {
+            std::unique_lock<std::mutex> g(S->mu);
+            for (;;) {
+                // admit from the head of the queue while slots and budget allow
+                while (!S->queue.empty() && S->active < S->max_active) {
+                    Req *r = S->reqs[S->queue.front()].get();
+                    if (S->used + r->bytes > S->budget)
+                        break;
+                    S->queue.pop_front();
+                    r->admitted = true;
+                    S->used += r->bytes;
+                    S->active++;
+                    add.push_back({db_rows(r->db), (uint32_t)db_n(r->db), db_m(r->db), r->minsup,
+                                   r->M});
+                    ids.push_back(r->ticket);
+                }
+                if (!add.empty() || eng.size() > 0)
+                    break;
+                if (S->stopping)
+                    return;
+                S->cv_work.wait(g);
+            }
+        }
+        int rc = DIC_OK;
+        if (!add.empty()) {
+            rc = eng.add(add, ids);
+            if (rc) {
+                std::lock_guard<std::mutex> g(S->mu);
+                for (uint64_t t : ids) {
+                    MineOutput o;
+                    finish(S, S->reqs[t].get(), rc, std::move(o));
+                }
+                S->cv_done.notify_all();
+            }
+        }
+        if (eng.size() > 0) {
+            rc = eng.advance(SERVE_STEPS);
+            done.clear();
+            if (!rc)
+                rc = eng.harvest(done);
+            std::lock_guard<std::mutex> g(S->mu);
+            for (auto &d : done)
+                finish(S, S->reqs[d.first].get(), d.second.status, std::move(d.second));
+            if (!done.empty())
+                S->cv_done.notify_all();
+            if (rc) {
+                // a device error: fail everything still in the engine and stop
+                // using it; queued requests fail the same way, later submits too
+                S->stopping = true;
+                for (auto &kv : S->reqs)
+                    if (!kv.second->done && kv.second->admitted) {
+                        MineOutput o;
+                        finish(S, kv.second.get(), rc, std::move(o));
+                    }
+                for (uint64_t t : S->queue) {
+                    Req *r = S->reqs[t].get();
+                    r->status = rc;
+                    r->done = true;
+                    db_ref(r->db, -1);
+                }
+                S->queue.clear();
+                S->cv_done.notify_all();
+                return;
+            }
+        }
+    }
+}
+
+int take(dic_server *S, uint64_t ticket, dic_result **out, std::unique_lock<std::mutex> &g)
+{
+    (void)g;
+    auto it = S->reqs.find(ticket);
+    Req *r = it->second.get();
+    int rc = r->status;
+    if (!rc) {
+        dic_result *res = new (std::nothrow) dic_result;
+        if (!res) {
+            rc = DIC_E_NOMEM;
+        } else {
+            res->W = db_W(r->db);
+            res->masks = std::move(r->out.masks);
+            res->counts = std::move(r->out.counts);
+            res->trace = std::move(r->out.trace);
+            res->stats = r->out.stats;
+            *out = res;
+        }
+    } else {
+        set_error("request failed");
+    }
+    S->reqs.erase(it);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dic_serve_create(uint64_t hbm_budget_bytes, const dic_serve_opts *opts, dic_server **out)
+{
+    if (!out) {
+        set_error("dic_serve_create: out is NULL");
+        return DIC_E_INVAL;
+    }
+    *out = nullptr;
+    if (hbm_budget_bytes == 0) {
+        set_error("dic_serve_create: budget must be > 0");
+        return DIC_E_INVAL;
+    }
+    dic_server *S = new (std::nothrow) dic_server;
+    if (!S) {
+        set_error("host allocation failed");
+        return DIC_E_NOMEM;
+    }
+    S->budget = hbm_budget_bytes;
+    if (opts && opts->max_active)
+        S->max_active = std::min<uint32_t>(opts->max_active, 4096);
+    if (hipGetDevice(&S->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        delete S;
+        set_error("dic_serve_create: could not create a stream");
+        return DIC_E_DEVICE;
+    }
+    S->worker = std::thread(worker_main, S);
+    *out = S;
+    return DIC_OK;
+}
+
+int dic_serve_submit(dic_server *S, dic_db *db, double minsup, uint64_t M, uint64_t *ticket)
+{
+    if (!S || !db || !ticket || !(minsup > 0.0) || M == 0) {
+        set_error("dic_serve_submit: bad argument");
+        return DIC_E_INVAL;
+    }
+    const uint64_t bytes = job_bytes_bound(db_m(db));
+    std::lock_guard<std::mutex> g(S->mu);
+    if (S->stopping) {
+        set_error("dic_serve_submit: server is shutting down");
+        return DIC_E_INVAL;
+    }
+    if (bytes > S->budget) {
+        set_error("dic_serve_submit: the request's memory bound exceeds the budget");
+        return DIC_E_CAPACITY;
+    }
+    auto r = std::make_unique<Req>();
+    r->ticket = S->next_ticket++;
+    r->db = db;
+    r->minsup = minsup;
+    r->M = M;
+    r->bytes = bytes;
+    r->submit = clk::now();
+    if (!S->any) {
+        S->any = true;
+        S->first_submit = r->submit;
+    }
+    db_ref(db, +1);
+    *ticket = r->ticket;
+    S->queue.push_back(r->ticket);
+    S->reqs[r->ticket] = std::move(r);
+    S->cv_work.notify_one();
+    return DIC_OK;
+}
+
+int dic_serve_poll(dic_server *S, uint64_t ticket, dic_result **out)
+{
+    if (!S || !out) {
+        set_error("dic_serve_poll: bad argument");
+        return DIC_E_INVAL;
+    }
+    *out = nullptr;
+    std::unique_lock<std::mutex> g(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) {
+        set_error("dic_serve_poll: unknown ticket");
+        return DIC_E_NOTFOUND;
+    }
+    if (!it->second->done)
+        return DIC_E_PENDING;
+    return take(S, ticket, out, g);
+}
+
+int dic_serve_wait(dic_server *S, uint64_t ticket, int64_t timeout_ms, dic_result **out)
+{
+    if (!S || !out) {
+        set_error("dic_serve_wait: bad argument");
+        return DIC_E_INVAL;
+    }
+    *out = nullptr;
+    std::unique_lock<std::mutex> g(S->mu);
+    auto ready = [&] {
+        auto it = S->reqs.find(ticket);
+        return it == S->reqs.end() || it->second->done;
+    };
+    if (timeout_ms < 0) {
+        S->cv_done.wait(g, ready);
+    } else if (!S->cv_done.wait_for(g, std::chrono::milliseconds(timeout_ms), ready)) {
+        set_error("dic_serve_wait: timed out");
+        return DIC_E_TIMEOUT;
+    }
+    if (S->reqs.find(ticket) == S->reqs.end()) {
+        set_error("dic_serve_wait: unknown ticket");
+        return DIC_E_NOTFOUND;
+    }
+    return take(S, ticket, out, g);
+}
+
+int dic_serve_stats(dic_server *S, double *p50_ms, double *p99_ms, double *throughput_rps)
+{
+    if (!S) {
+        set_error("dic_serve_stats: server is NULL");
+        return DIC_E_INVAL;
+    }
+    std::lock_guard<std::mutex> g(S->mu);
+    std::vector<double> v = S->lat_ms;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) -> double {
+        if (v.empty())
+            return 0.0;
+        // nearest rank
+        size_t r = (size_t)std::ceil(p / 100.0 * (double)v.size());
+        r = std::max<size_t>(1, std::min(r, v.size()));
+        return v[r - 1];
+    };
+    if (p50_ms)
+        *p50_ms = pct(50);
+    if (p99_ms)
+        *p99_ms = pct(99);
+    if (throughput_rps) {
+        double secs = v.empty() ? 0.0
+                                : std::chrono::duration<double>(S->last_done - S->first_submit)
+                                      .count();
+        *throughput_rps = secs > 0 ? (double)v.size() / secs : 0.0;
+    }
+    return DIC_OK;
+}
+
+int dic_serve_destroy(dic_server *S)
+{
+    if (!S)
+        return DIC_OK;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->stopping = true;
+        // queued requests are dropped; running ones finish
+        for (uint64_t t : S->queue) {
+            Req *r = S->reqs[t].get();
+            r->status = DIC_E_INVAL;
+            r->done = true;
+            db_ref(r->db, -1);
+        }
+        S->queue.clear();
+        S->cv_work.notify_all();
+    }
+    if (S->worker.joinable())
+        S->worker.join();
+    (void)hipStreamDestroy(S->stream);
+    delete S;
+    return DIC_OK;
+}
+
+}  // extern "C"
