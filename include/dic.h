@@ -78,6 +78,8 @@ typedef struct dic_stop_trace {
     uint32_t solidified; /* candidates that finished a full pass (CheckFullPass) */
     uint32_t words;      /* nonzero 32-bit words over the live candidates' masks:
                             the AND work per transaction at this stop      */
+    uint32_t items;      /* items over the live candidates (sum of sizes)   */
+    uint32_t reserved;
 } dic_stop_trace;
 
 typedef struct dic_stats {
@@ -198,6 +200,11 @@ DIC_API int dic_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(vo
  * Library options (process-wide):
  *   "profile"  0/1: time every CountSupport launch with HIP events recorded
  *              on the stream it runs on; reported as dic_stats.count_ms.
+ *   "layout"   counting layout of runs started from now on: 1 (default)
+ *              per-item bitsets over 64-row words (a candidate's support in
+ *              a word is the popcount of the AND of its items' words), 0 the
+ *              row bitmaps themselves (one AND/compare per row and nonzero
+ *              word).  Both give identical results.
  */
 DIC_API int dic_set_option(const char *name, int64_t value);
 

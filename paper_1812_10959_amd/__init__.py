@@ -63,7 +63,8 @@ class DicError(RuntimeError):
 
 class dic_stop_trace(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint32) for f in (
-        "stop", "rows", "live", "promoted", "pruned", "generated", "solidified", "words")]
+        "stop", "rows", "live", "promoted", "pruned", "generated", "solidified", "words", "items",
+        "reserved")]
 
 
 class dic_stats(ctypes.Structure):
@@ -205,6 +206,7 @@ class Result:
     stats: dict = field(default_factory=dict)
     trace: np.ndarray | None = None  # uint32[stops, 7] in TRACE_FIELDS order
     words: np.ndarray | None = None  # uint32[stops]: nonzero 32-bit words of the live masks
+    items: np.ndarray | None = None  # uint32[stops]: items over the live candidates
 
 
 def _take_result(h: int) -> Result:
@@ -228,13 +230,14 @@ def _take_result(h: int) -> Result:
                  for f, _ in dic_stats._fields_}
         ns = _u64()
         tp = _lib.dic_result_trace(h, ctypes.byref(ns))
-        trace = words = None
+        trace = words = items = None
         if ns.value:
             raw = np.ctypeslib.as_array(ctypes.cast(tp, ctypes.POINTER(ctypes.c_uint32)),
-                                        shape=(ns.value * 8,)).reshape(ns.value, 8)
+                                        shape=(ns.value * 10,)).reshape(ns.value, 10)
             trace = raw[:, :7].copy()
             words = raw[:, 7].copy()
-        return Result(masks, counts, stats, trace, words)
+            items = raw[:, 8].copy()
+        return Result(masks, counts, stats, trace, words, items)
     finally:
         _lib.dic_result_free(h)
 

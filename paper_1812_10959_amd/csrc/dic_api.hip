@@ -11,9 +11,10 @@
 #include "dic_internal.h"
 
 struct dic_db {
-    uint64_t *rows = nullptr;  // device, n * W
+    uint64_t *rows = nullptr;  // device, n * W, row-major
+    uint64_t *vert = nullptr;  // device, m * nw: per-item bitsets over 64-row words
     uint64_t n = 0;
-    uint32_t m = 0, W = 0;
+    uint32_t m = 0, W = 0, nw = 0;
     std::mutex mu;             // one mining call at a time on this database
     std::atomic<int> refs{0};  // server requests queued or running on it
 };
@@ -21,6 +22,7 @@ struct dic_db {
 namespace dic {
 
 const uint64_t *db_rows(dic_db *db) { return db->rows; }
+const uint64_t *db_vert(dic_db *db) { return db->vert; }
 uint64_t db_n(dic_db *db) { return db->n; }
 uint32_t db_m(dic_db *db) { return db->m; }
 uint32_t db_W(dic_db *db) { return db->W; }
@@ -170,6 +172,10 @@ int dic_set_option(const char *name, int64_t value)
         set_profiling((int)value);
         return DIC_OK;
     }
+    if (name && std::strcmp(name, "layout") == 0 && (value == 0 || value == 1)) {
+        set_count_layout(value ? LAYOUT_VERTICAL : LAYOUT_ROWS);
+        return DIC_OK;
+    }
     set_error(std::string("dic_set_option: unknown option or value ") + (name ? name : "(null)"));
     return DIC_E_INVAL;
 }
@@ -197,8 +203,12 @@ static int new_db(uint64_t n, uint32_t m, dic_db **out)
     db->n = n;
     db->m = m;
     db->W = (m + 63u) / 64u;
+    db->nw = (uint32_t)((n + 63u) / 64u);
     db->rows = (uint64_t *)dev_alloc(8ull * n * db->W);
-    if (!db->rows) {
+    db->vert = (uint64_t *)dev_alloc(8ull * m * db->nw);
+    if (!db->rows || !db->vert) {
+        dev_free(db->rows);
+        dev_free(db->vert);
         delete db;
         set_error("device allocation failed for the database");
         return DIC_E_NOMEM;
@@ -210,7 +220,15 @@ static int new_db(uint64_t n, uint32_t m, dic_db **out)
 static void delete_db(dic_db *db)
 {
     dev_free(db->rows);
+    dev_free(db->vert);
     delete db;
+}
+
+// The per-item bitset copy of a database whose rows are on the device
+// (the layout counted by default); enqueued on s.
+static void build_vertical(dic_db *db, hipStream_t s)
+{
+    launch_transpose(db->rows, db->n, db->m, db->vert, db->nw, s);
 }
 
 int dic_load_db(const uint64_t *rows, uint64_t n, uint32_t m, dic_db **out)
@@ -240,8 +258,10 @@ int dic_load_db(const uint64_t *rows, uint64_t n, uint32_t m, dic_db **out)
     if ((rc = new_db(n, m, &db)))
         return rc;
     hipStream_t s = lib_stream();
-    if (hipMemcpyAsync(db->rows, rows, 8ull * n * W, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
+    bool ok = hipMemcpyAsync(db->rows, rows, 8ull * n * W, hipMemcpyHostToDevice, s) == hipSuccess;
+    if (ok)
+        build_vertical(db, s);
+    if (!ok || hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
         set_error("dic_load_db: copy to device failed");
         delete_db(db);
         return DIC_E_DEVICE;
@@ -275,6 +295,8 @@ int dic_load_db_device(const uint64_t *rows, uint64_t n, uint32_t m, dic_db **ou
                   hipSuccess;
     if (ok && (m & 63u))
         launch_check_padding(db->rows, n, m, bad, s);
+    if (ok)
+        build_vertical(db, s);
     ok = ok && hipGetLastError() == hipSuccess &&
          hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s) == hipSuccess &&
          hipStreamSynchronize(s) == hipSuccess;
@@ -333,8 +355,10 @@ int dic_load_db_lists(const uint32_t *items, const uint64_t *offsets, uint64_t n
               (nnz == 0 ||
                hipMemcpyAsync(d_items, items, 4 * nnz, hipMemcpyHostToDevice, s) == hipSuccess) &&
               hipMemcpyAsync(d_off, offsets, 8 * (n + 1), hipMemcpyHostToDevice, s) == hipSuccess;
-    if (ok)
+    if (ok) {
         launch_pack_lists(d_items, d_off, n, db->W, db->rows, s);
+        build_vertical(db, s);
+    }
     ok = ok && hipGetLastError() == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
     dev_free(d_items);
     dev_free(d_off);
@@ -409,7 +433,7 @@ int dic_mine(dic_db *db, double minsup, uint64_t M, dic_result **out)
     if (rc)
         return rc;
     std::lock_guard<std::mutex> g(db->mu);
-    std::vector<MineRequest> reqs{{db->rows, (uint32_t)db->n, db->m, minsup, M}};
+    std::vector<MineRequest> reqs{{db->rows, db->vert, (uint32_t)db->n, db->m, minsup, M}};
     std::vector<MineOutput> outs;
     rc = run_jobs(reqs, outs, lib_stream());
     if (rc)
@@ -443,7 +467,8 @@ int dic_batch(dic_db *const *dbs, const double *minsup, const uint64_t *M, uint3
                 first_rc = rc;
             continue;
         }
-        reqs.push_back({dbs[i]->rows, (uint32_t)dbs[i]->n, dbs[i]->m, minsup[i], M[i]});
+        reqs.push_back({dbs[i]->rows, dbs[i]->vert, (uint32_t)dbs[i]->n, dbs[i]->m, minsup[i],
+                        M[i]});
         where.push_back(i);
     }
     if (reqs.empty())

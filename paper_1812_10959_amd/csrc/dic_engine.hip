@@ -35,7 +35,8 @@ namespace {
         }                                                                                \
     } while (0)
 
-constexpr uint32_t FP_ROWS = 4096;  // rows per first-pass work item (kernel side too)
+constexpr uint32_t FP_ROWS = 4096;    // rows per first-pass work item (kernel side too)
+constexpr uint32_t FPV_WORDS = 4096;  // bitset words per first-pass work item (kernel side too)
 constexpr uint32_t TRACE_INIT = 512;
 constexpr uint32_t MAX_RESTARTS = 6;
 
@@ -144,11 +145,14 @@ struct PoolLayout {
 };
 
 std::atomic<int> g_profile{0};
+std::atomic<uint32_t> g_layout{LAYOUT_VERTICAL};
 
 }  // namespace
 
 bool profiling() { return g_profile.load() != 0; }
 void set_profiling(int on) { g_profile.store(on); }
+uint32_t count_layout() { return g_layout.load(); }
+void set_count_layout(uint32_t layout) { g_layout.store(layout); }
 
 // ---------------------------------------------------------------------------
 // threshold and sizes
@@ -178,7 +182,7 @@ bool threshold(double minsup, uint64_t n, uint64_t *tau)
 uint64_t job_bytes(uint32_t m, uint64_t cap, uint32_t trace_cap)
 {
     const uint32_t W = (m + 63u) / 64u;
-    return PoolLayout(cap, W).bytes + 2ull * m * 4 + 512 +
+    return PoolLayout(cap, W).bytes + 3ull * m * 4 + 1024 +
            (uint64_t)trace_cap * sizeof(dic_stop_trace);
 }
 
@@ -199,6 +203,7 @@ struct ActiveJob {
     void *pool = nullptr;   // candidate pool
     void *trace = nullptr;
     Job job{};
+    uint32_t layout = LAYOUT_VERTICAL;
     bool in_loop = false;   // pairs written, taking part in stops
     double count_ms = 0;
     uint64_t count_launches = 0;
@@ -277,11 +282,13 @@ int Engine::add(const std::vector<MineRequest> &reqs, const std::vector<uint64_t
     }
     std::vector<ActiveJob *> fresh;
     const auto now = std::chrono::steady_clock::now();
+    const uint32_t layout = count_layout();
     for (size_t i = 0; i < reqs.size(); ++i) {
         ActiveJob *a = new ActiveJob;
         a->id = ids[i];
         a->req = reqs[i];
         a->t0 = now;
+        a->layout = reqs[i].vert ? layout : LAYOUT_ROWS;
         fresh.push_back(a);
     }
     return add_internal(fresh);
@@ -310,6 +317,14 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
 {
     if (fresh.empty())
         return DIC_OK;
+    // one first-pass kernel per layout: split a mixed set
+    std::vector<ActiveJob *> same, other;
+    for (ActiveJob *a : fresh)
+        (a->layout == fresh[0]->layout ? same : other).push_back(a);
+    if (!other.empty()) {
+        int rc = add_impl(same);
+        return rc ? rc : add_impl(other);
+    }
     const unsigned long long *zob = zobrist(s_);
     if (!zob) {
         set_error("could not create the itemset hash table on the device");
@@ -323,6 +338,7 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         Carver c;
         const size_t p0 = c.take(sizeof(Plan)), p1 = c.take(sizeof(Plan));
         const size_t a0 = c.take(4ull * (max_jobs_ + 1)), a1 = c.take(4ull * (max_jobs_ + 1));
+        const size_t av = c.take(4ull * (max_jobs_ + 1)), bv = c.take(4ull * (max_jobs_ + 1));
         const size_t a2 = c.take(8ull * (max_jobs_ + 1)), a3 = c.take(8ull * (max_jobs_ + 1));
         const size_t b0 = c.take(4ull * (max_jobs_ + 1)), b1 = c.take(4ull * (max_jobs_ + 1));
         const size_t b2 = c.take(8ull * (max_jobs_ + 1)), b3 = c.take(8ull * (max_jobs_ + 1));
@@ -335,6 +351,8 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         d_plan_step_ = (Plan *)(pb + p0);
         d_plan_aux_ = (Plan *)(pb + p1);
         plan_step_.pre_count = (uint32_t *)(pb + a0);
+        plan_step_.pre_countv = (uint32_t *)(pb + av);
+        plan_aux_.pre_countv = (uint32_t *)(pb + bv);
         plan_step_.pre_epi = (uint32_t *)(pb + a1);
         plan_step_.pre_cg = (unsigned long long *)(pb + a2);
         plan_step_.pre_fp = (unsigned long long *)(pb + a3);
@@ -366,7 +384,7 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         }
         a->slot = free_slots_.back();
         free_slots_.pop_back();
-        a->small = dev_alloc(8ull * r.m + 256);
+        a->small = dev_alloc(12ull * r.m + 768);
         a->trace = dev_alloc(sizeof(dic_stop_trace) * a->trace_cap);
         if (!a->small || !a->trace) {
             rc = DIC_E_NOMEM;
@@ -381,6 +399,9 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         Job &J = a->job;
         std::memset(&J, 0, sizeof(Job));
         J.rows = a->req.rows;
+        J.vert = a->req.vert;
+        J.nw = (a->req.n + 63u) / 64u;
+        J.layout = a->layout;
         J.n = a->req.n;
         J.m = a->req.m;
         J.W = a->W;
@@ -389,6 +410,7 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         J.tau = a->tau;
         J.item_cnt = (uint32_t *)a->small;
         J.l1 = (uint32_t *)((char *)a->small + align_up(4ull * a->req.m, 256));
+        J.l1pos = (uint32_t *)((char *)a->small + 2 * align_up(4ull * a->req.m, 256));
         J.st = states + a->slot;
         J.out_n = outn + a->slot;
         J.trace = (dic_stop_trace *)a->trace;
@@ -398,17 +420,26 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         aux_host_[i] = J;
     }
 
-    // ---- FirstPass for the new jobs
+    // ---- FirstPass for the new jobs (all of one layout: the option at add time)
+    const bool vert = fresh[0]->layout == LAYOUT_VERTICAL;
     pre_host_.assign(nf + 1, 0);
-    for (uint32_t i = 0; i < nf; ++i)
-        pre_host_[i + 1] = pre_host_[i] + (fresh[i]->req.n + FP_ROWS - 1) / FP_ROWS;
+    for (uint32_t i = 0; i < nf; ++i) {
+        const uint64_t n = fresh[i]->req.n;
+        const uint64_t work = vert ? (uint64_t)fresh[i]->req.m * (((n + 63) / 64 + FPV_WORDS - 1) /
+                                                                   FPV_WORDS)
+                                   : (n + FP_ROWS - 1) / FP_ROWS;
+        pre_host_[i + 1] = pre_host_[i] + work;
+    }
     plan_aux_.njobs = nf;
     HIP_TRY(hipMemcpyAsync(table_aux_, aux_host_.data(), sizeof(Job) * nf,
                            hipMemcpyHostToDevice, s_));
     HIP_TRY(hipMemcpyAsync(d_plan_aux_, &plan_aux_, sizeof(Plan), hipMemcpyHostToDevice, s_));
     HIP_TRY(hipMemcpyAsync(plan_aux_.pre_fp, pre_host_.data(), 8ull * (nf + 1),
                            hipMemcpyHostToDevice, s_));
-    launch_first_pass((const Job *)table_aux_, d_plan_aux_, pre_host_[nf], s_);
+    if (vert)
+        launch_first_pass_vert((const Job *)table_aux_, d_plan_aux_, pre_host_[nf], s_);
+    else
+        launch_first_pass((const Job *)table_aux_, d_plan_aux_, pre_host_[nf], s_);
     launch_l1_and_pairs_prepare((const Job *)table_aux_, d_plan_aux_, nf, s_);
     HIP_TRY(hipGetLastError());
     if ((rc = read_states()))
@@ -536,9 +567,14 @@ int Engine::advance(uint32_t max_steps)
             events_.push_back(e);
         }
     }
+    bool any_rows = false, any_vert = false;
+    for (const Job &J : table_host_) {
+        any_rows |= J.layout == LAYOUT_ROWS;
+        any_vert |= J.layout == LAYOUT_VERTICAL;
+    }
     for (uint32_t k = 0; k < S; ++k)
-        launch_step((const Job *)table_, d_plan_step_, s_, prof ? events_[2 * k] : nullptr,
-                    prof ? events_[2 * k + 1] : nullptr);
+        launch_step((const Job *)table_, d_plan_step_, s_, any_rows, any_vert,
+                    prof ? events_[2 * k] : nullptr, prof ? events_[2 * k + 1] : nullptr);
     HIP_TRY(hipGetLastError());
     if ((rc = read_states()))
         return rc;
@@ -708,6 +744,7 @@ int Engine::harvest(std::vector<std::pair<uint64_t, MineOutput>> &done)
         b->req = a->req;
         b->t0 = a->t0;
         b->mult = a->mult * 4;
+        b->layout = a->layout;
         b->restarts = a->restarts + 1;
         b->count_ms = a->count_ms;
         b->count_launches = a->count_launches;

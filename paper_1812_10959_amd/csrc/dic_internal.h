@@ -33,6 +33,21 @@ constexpr int CW = 16;                // candidates per wave in the count kernel
 constexpr int CAND_PER_WG = CW * (WG / 64);
 constexpr int LDS_DWORDS = 8192;      // count kernel row tile (32 KiB)
 constexpr int MAX_GROUPS = 16;        // 64-row groups per row tile (1024 rows)
+constexpr int VT_WORDS = 6144;        // vertical tile: 64-bit words in LDS (48 KiB)
+constexpr int VT_MAXW = 16;           // vertical tile: words per item (1024 rows)
+
+enum : uint32_t { LAYOUT_ROWS = 0, LAYOUT_VERTICAL = 1 };
+
+// Words per frequent item in a vertical tile (the tile holds every frequent
+// item's bitset over those words) and the odd row stride that spreads the
+// items' words over the LDS banks.
+__host__ __device__ inline uint32_t vert_tile_words(uint32_t nL1)
+{
+    uint32_t t = nL1 ? (uint32_t)VT_WORDS / nL1 : (uint32_t)VT_MAXW + 1u;
+    t = t > 1u ? t - 1u : 1u;
+    return t > (uint32_t)VT_MAXW ? (uint32_t)VT_MAXW : t;
+}
+__host__ __device__ inline uint32_t vert_tile_stride(uint32_t tw) { return tw | 1u; }
 
 __host__ __device__ inline uint32_t row_tile_rows(uint32_t W)
 {
@@ -65,12 +80,18 @@ struct JobState {
     uint32_t peak_K;
     uint32_t asserts;   // invariant violations (must stay 0)
     unsigned long long tests;
-    uint32_t pad[12];
+    uint32_t fw, lw;    // vertical: 64-row words [fw, lw] hold the block
+    uint32_t tw;        // vertical: words per tile
+    uint32_t pad[9];
 };
 
 // Read-only description of one mining run (device copy in a job table).
 struct Job {
     const uint64_t *rows;  // n * W, row-major
+    const uint64_t *vert;  // m * nw: bit r of vert[i * nw + g] = item i in row 64g + r
+    uint32_t nw;           // 64-row words per item
+    uint32_t layout;       // LAYOUT_ROWS or LAYOUT_VERTICAL counting
+    uint32_t *l1pos;       // m: index of an item among the frequent items (or ~0)
     uint32_t n, m, W, Mp;
     uint32_t stop_max, tau;
     uint32_t cap;    // pool capacity (itemsets)
@@ -97,7 +118,8 @@ struct Job {
 struct Plan {
     uint32_t njobs;
     uint32_t pad;
-    uint32_t *pre_count;
+    uint32_t *pre_count;   // row-major count work items
+    uint32_t *pre_countv;  // vertical count work items
     uint32_t *pre_epi;
     unsigned long long *pre_cg;
     unsigned long long *pre_fp;  // first pass row chunks
@@ -107,12 +129,16 @@ struct Plan {
 // kernel launchers (dic_kernels.hip)
 void launch_first_pass(const Job *jobs, const Plan *plan, unsigned long long total_chunks,
                        hipStream_t s);
+void launch_first_pass_vert(const Job *jobs, const Plan *plan, unsigned long long total_chunks,
+                            hipStream_t s);
+void launch_transpose(const uint64_t *rows, uint64_t n, uint32_t m, uint64_t *vert, uint32_t nw,
+                      hipStream_t s);
 void launch_l1_and_pairs_prepare(const Job *jobs, const Plan *plan, uint32_t njobs, hipStream_t s);
 void launch_init_pairs(const Job *jobs, const Plan *plan, unsigned long long total, hipStream_t s);
 // One stop for every job in the table; when given, the two events bracket
 // the CountSupport launch on stream s.
-void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, hipEvent_t before = nullptr,
-                 hipEvent_t after = nullptr);
+void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, bool rows, bool vert,
+                 hipEvent_t before = nullptr, hipEvent_t after = nullptr);
 void launch_collect(const Job *jobs, const Plan *plan, uint32_t njobs, hipStream_t s);
 void launch_pack_lists(const uint32_t *items, const uint64_t *offsets, uint64_t n, uint32_t W,
                        uint64_t *rows, hipStream_t s);
@@ -129,7 +155,8 @@ void dev_free(void *p);
 hipStream_t lib_stream();
 
 struct MineRequest {
-    const uint64_t *rows;  // device
+    const uint64_t *rows;  // device, row-major
+    const uint64_t *vert;  // device, item bitsets (m * ceil(n/64) words)
     uint32_t n, m;
     double minsup;
     uint64_t M;
@@ -158,6 +185,8 @@ uint64_t job_bytes_bound(uint32_t m);
 
 bool profiling();
 void set_profiling(int on);
+uint32_t count_layout();
+void set_count_layout(uint32_t layout);
 
 struct ActiveJob;
 

@@ -22,6 +22,7 @@ namespace dic {
 namespace {
 
 constexpr uint32_t FP_ROWS = 4096;       // first pass rows per workgroup item
+constexpr uint32_t FPV_WORDS = 4096;     // first pass (bitsets): words per work item
 constexpr uint32_t COUNT_TARGET = 2048;  // count work items aimed at per job
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 
@@ -170,7 +171,76 @@ __device__ T block_scan_incl(T v, T *sh, T *total)
     return r;
 }
 
+// Sum of one value per thread over the workgroup (result in every thread).
+__device__ uint32_t block_sum(uint32_t v, uint32_t *sh)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += (uint32_t)__shfl_xor((int)v, off);
+    if (lane_id() == 0)
+        sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t t = 0;
+    for (int w = 0; w < WG / 64; ++w)
+        t += sh[w];
+    __syncthreads();
+    return t;
+}
+
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Item bitsets from rows: bit r of vert[i * nw + g] is set when row 64g + r
+// holds item i.  One wave per 64-row word: lane r holds row 64g + r, a ballot
+// over the lanes yields one item's word, and the lane whose index is that
+// item's bit position keeps it, so each lane stores one word per row word.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_transpose(const uint64_t *__restrict__ rows, uint64_t n,
+                                                  uint32_t m, uint32_t W, uint64_t *vert,
+                                                  uint32_t nw)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t waves = (uint64_t)gridDim.x * (WG / 64);
+    for (uint64_t g = (uint64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6); g < nw; g += waves) {
+        const uint64_t r = g * 64 + lane;
+        for (uint32_t w = 0; w < W; ++w) {
+            const uint64_t x = r < n ? rows[r * W + w] : 0ull;
+            uint64_t keep = 0;
+            for (uint32_t b = 0; b < 64; ++b) {
+                const uint64_t msk = __ballot((x >> b) & 1ull);
+                if (lane == b)
+                    keep = msk;
+            }
+            const uint32_t item = w * 64u + lane;
+            if (item < m)
+                vert[(uint64_t)item * nw + g] = keep;
+        }
+    }
+}
+
+// FirstPass on item bitsets: supp(i) is the popcount of item i's bitset.
+// Work item = (job, item, FPV_WORDS-word chunk).
+__global__ __launch_bounds__(WG) void k_first_pass_vert(const Job *__restrict__ jobs,
+                                                        const Plan *__restrict__ plan,
+                                                        unsigned long long total)
+{
+    __shared__ uint32_t sh[WG / 64];
+    for (unsigned long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const uint32_t j = find_job(plan->pre_fp, plan->njobs, it);
+        const Job *J = jobs + j;
+        const uint32_t cpi = (J->nw + FPV_WORDS - 1u) / FPV_WORDS;
+        const uint32_t local = (uint32_t)(it - plan->pre_fp[j]);
+        const uint32_t item = local / cpi, ch = local - item * cpi;
+        const uint32_t w0 = ch * FPV_WORDS;
+        const uint32_t w1 = w0 + FPV_WORDS < J->nw ? w0 + FPV_WORDS : J->nw;
+        const uint64_t *v = J->vert + (uint64_t)item * J->nw;
+        uint32_t c = 0;
+        for (uint32_t w = w0 + threadIdx.x; w < w1; w += WG)
+            c += (uint32_t)__popcll(v[w]);
+        c = block_sum(c, sh);
+        if (threadIdx.x == 0 && c)
+            atomicAdd(&J->item_cnt[item], c);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // FirstPass: support of every item over all rows (column popcount).
@@ -222,6 +292,8 @@ __global__ __launch_bounds__(WG) void k_l1(const Job *__restrict__ jobs)
         const uint32_t incl = block_scan_incl<uint32_t>(f, sh, &tot);
         if (f)
             J->l1[carry + incl - 1u] = i;
+        if (i < J->m)
+            J->l1pos[i] = f ? carry + incl - 1u : NONE;
         carry += tot;
     }
     if (threadIdx.x == 0) {
@@ -283,14 +355,15 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
 {
     __shared__ uint32_t sh[WG];
     const uint32_t njobs = plan->njobs;
-    uint32_t carry_c = 0, carry_e = 0;
+    uint32_t carry_c = 0, carry_v = 0, carry_e = 0;
     if (threadIdx.x == 0) {
         plan->pre_count[0] = 0;
+        plan->pre_countv[0] = 0;
         plan->pre_epi[0] = 0;
     }
     for (uint32_t b = 0; b < njobs; b += WG) {
         const uint32_t j = b + threadIdx.x;
-        uint32_t items = 0, K = 0;
+        uint32_t items = 0, itemsv = 0, K = 0;
         if (j < njobs) {
             const Job *J = jobs + j;
             JobState *st = J->st;
@@ -322,9 +395,28 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
                         t.stop = stop;
                         t.rows = rows;
                         t.live = K;
-                        t.promoted = t.pruned = t.generated = t.solidified = t.words = 0;
+                        t.promoted = t.pruned = t.generated = t.solidified = t.words = t.items = 0;
+                        t.reserved = 0;
                         J->trace[st->epoch - 1u] = t;
                     }
+                    if (J->layout == LAYOUT_VERTICAL) {
+                        // (candidate groups of WG) x (chunks of tiles of tw words)
+                        const uint32_t fw = (uint32_t)(first >> 6);
+                        const uint32_t lw = (uint32_t)((last - 1u) >> 6);
+                        const uint32_t tw = vert_tile_words(st->nL1);
+                        const uint32_t ntile = (lw - fw + tw) / tw;
+                        const uint32_t n_cg = (K + WG - 1u) / WG;
+                        uint32_t want = (COUNT_TARGET + n_cg - 1u) / n_cg;
+                        want = want < 1u ? 1u : (want > ntile ? ntile : want);
+                        const uint32_t tpc = (ntile + want - 1u) / want;
+                        st->fw = fw;
+                        st->lw = lw;
+                        st->tw = tw;
+                        st->n_ct = n_cg;
+                        st->rpi = tpc;
+                        st->n_ri = (ntile + tpc - 1u) / tpc;
+                        itemsv = n_cg * st->n_ri;
+                    } else {
                     const uint32_t rt = row_tile_rows(J->W);
                     const uint32_t n_ct = (K + CAND_PER_WG - 1u) / CAND_PER_WG;
                     const uint32_t tiles = (rows + rt - 1u) / rt;
@@ -339,17 +431,21 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
                     st->rpi = rpi;
                     st->n_ri = n_ri;
                     items = n_ct * n_ri;
+                    }
                 }
             }
         }
-        uint32_t tc, te;
+        uint32_t tc, tv, te;
         const uint32_t ic = block_scan_incl<uint32_t>(items, sh, &tc);
+        const uint32_t iv = block_scan_incl<uint32_t>(itemsv, sh, &tv);
         const uint32_t ie = block_scan_incl<uint32_t>(K, sh, &te);
         if (j < njobs) {
             plan->pre_count[j + 1] = carry_c + ic;
+            plan->pre_countv[j + 1] = carry_v + iv;
             plan->pre_epi[j + 1] = carry_e + ie;
         }
         carry_c += tc;
+        carry_v += tv;
         carry_e += te;
     }
 }
@@ -459,6 +555,86 @@ __global__ __launch_bounds__(WG) void k_count(const Job *__restrict__ jobs,
     }
 }
 
+// CountSupport (Algorithm 3) on item bitsets.  Work item = (group of WG
+// candidates, chunk of tiles).  A tile holds, for every frequent item, its
+// bitset over tw consecutive 64-row words of the block (edge words masked to
+// the block).  Each thread owns one candidate: it ANDs the tile rows of the
+// candidate's items word by word and popcounts the result, so a 64-bit AND
+// tests 64 transactions at once.  Lanes of a wave mostly share all but one
+// item (candidates are appended per generating itemset), so most tile reads
+// are broadcasts.
+__global__ __launch_bounds__(WG) void k_count_vert(const Job *__restrict__ jobs,
+                                                   const Plan *__restrict__ plan)
+{
+    __shared__ uint64_t tile[VT_WORDS];
+    const uint32_t total = plan->pre_countv[plan->njobs];
+    for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const uint32_t j = find_job(plan->pre_countv, plan->njobs, it);
+        const Job *J = jobs + j;
+        const JobState *st = J->st;
+        const uint32_t local = it - plan->pre_countv[j];
+        const uint32_t n_cg = st->n_ct;
+        const uint32_t rc = local / n_cg;
+        const uint32_t cg = local - rc * n_cg;
+        const uint32_t tw = st->tw, ts = vert_tile_stride(tw);
+        const uint32_t fw = st->fw, lw = st->lw, nL1 = st->nL1;
+        const uint32_t ntile = (lw - fw + tw) / tw;
+        const uint32_t t0 = rc * st->rpi;
+        const uint32_t t1 = t0 + st->rpi < ntile ? t0 + st->rpi : ntile;
+        const uint64_t lo_mask = ~0ull << (st->first & 63u);
+        const uint64_t hi_mask = (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
+        const uint32_t K = st->K;
+        const uint32_t c = cg * WG + threadIdx.x;
+        const bool valid = c < K;
+        const uint32_t p = valid ? (st->parity ? J->live1 : J->live0)[c] : 0u;
+        uint32_t cnt = 0;
+        for (uint32_t t = t0; t < t1; ++t) {
+            const uint32_t w0 = fw + t * tw;
+            const uint32_t nwt = (lw + 1u - w0) < tw ? (lw + 1u - w0) : tw;
+            __syncthreads();
+            // thread (q, r) loads word r of items q, q + per, q + 2 per, ...
+            const uint32_t per = WG / nwt;
+            const uint32_t q = threadIdx.x / nwt, r = threadIdx.x - q * nwt;
+            if (q < per) {
+                const uint32_t g = w0 + r;
+                const uint64_t mask = (g == fw ? lo_mask : ~0ull) & (g == lw ? hi_mask : ~0ull);
+#pragma unroll 4
+                for (uint32_t a = q; a < nL1; a += per)
+                    tile[a * ts + r] = J->vert[(uint64_t)J->l1[a] * J->nw + g] & mask;
+            }
+            __syncthreads();
+            if (valid) {
+                uint64_t acc[VT_MAXW];
+#pragma unroll
+                for (int w = 0; w < VT_MAXW; ++w)
+                    acc[w] = ~0ull;
+                uint64_t nzw = J->pnz[p];
+                const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+                while (nzw) {
+                    const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
+                    nzw &= nzw - 1;
+                    uint64_t bits = cm[wd];
+                    while (bits) {
+                        const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
+                        bits &= bits - 1;
+                        const uint64_t *row = tile + J->l1pos[item] * ts;
+#pragma unroll
+                        for (int w = 0; w < VT_MAXW; ++w)
+                            if ((uint32_t)w < nwt)
+                                acc[w] &= row[w];
+                    }
+                }
+#pragma unroll
+                for (int w = 0; w < VT_MAXW; ++w)
+                    if ((uint32_t)w < nwt)
+                        cnt += (uint32_t)__popcll(acc[w]);
+            }
+        }
+        if (valid && cnt)
+            atomicAdd(J->psupp + p, cnt);
+    }
+}
+
 // Prune (Algorithm 4) and CheckFullPass (Algorithm 5) for every live
 // candidate, plus the compaction of survivors into the next live list.
 // Candidates are counted for stop_I += 1 here (Algorithm 3's first line).
@@ -478,10 +654,11 @@ __global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
         const Job *J = jobs + j;
         JobState *st = J->st;
         bool promoted = false, pruned = false, solid = false, keep = false;
-        uint32_t p = 0, sc = 0, words = 0;
+        uint32_t p = 0, sc = 0, words = 0, items = 0;
         if (valid) {
             const uint32_t c = x - plan->pre_epi[j];
             p = (st->parity ? J->live1 : J->live0)[c];
+            items = J->pk[p];
             // nonzero 32-bit words of this candidate: its AND work per row
             uint64_t nzw = J->pnz[p];
             const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
@@ -527,6 +704,7 @@ __global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
         if (uniform) {
             if (tr) {
                 wave_add(&tr->words, words, true);
+                wave_add(&tr->items, items, true);
                 wave_append(&tr->promoted, promoted, true);
                 wave_append(&tr->pruned, pruned, true);
                 wave_append(&tr->solidified, solid, true);
@@ -534,6 +712,8 @@ __global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
         } else if (tr) {
             if (words)
                 atomicAdd(&tr->words, words);
+            if (items)
+                atomicAdd(&tr->items, items);
             if (promoted)
                 atomicAdd(&tr->promoted, 1u);
             if (pruned)
@@ -732,6 +912,20 @@ void launch_first_pass(const Job *jobs, const Plan *plan, unsigned long long tot
                        plan, total_chunks);
 }
 
+void launch_first_pass_vert(const Job *jobs, const Plan *plan, unsigned long long total_chunks,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_first_pass_vert, dim3(grid_for(total_chunks, 1, 8192)), dim3(WG), 0, s,
+                       jobs, plan, total_chunks);
+}
+
+void launch_transpose(const uint64_t *rows, uint64_t n, uint32_t m, uint64_t *vert, uint32_t nw,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_transpose, dim3(grid_for(nw, WG / 64, 16384)), dim3(WG), 0, s, rows, n,
+                       m, (m + 63u) / 64u, vert, nw);
+}
+
 void launch_l1_and_pairs_prepare(const Job *jobs, const Plan *, uint32_t njobs, hipStream_t s)
 {
     hipLaunchKernelGGL(k_l1, dim3(njobs), dim3(WG), 0, s, jobs);
@@ -743,14 +937,17 @@ void launch_init_pairs(const Job *jobs, const Plan *plan, unsigned long long tot
                        total);
 }
 
-void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, hipEvent_t before,
-                 hipEvent_t after)
+void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, bool rows, bool vert,
+                 hipEvent_t before, hipEvent_t after)
 {
     Plan *pl = const_cast<Plan *>(plan);
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(WG), 0, s, jobs, pl);
     if (before)
         (void)hipEventRecord(before, s);
-    hipLaunchKernelGGL(k_count, dim3(GRID_COUNT), dim3(WG), 0, s, jobs, plan);
+    if (rows)
+        hipLaunchKernelGGL(k_count, dim3(GRID_COUNT), dim3(WG), 0, s, jobs, plan);
+    if (vert)
+        hipLaunchKernelGGL(k_count_vert, dim3(GRID_COUNT), dim3(WG), 0, s, jobs, plan);
     if (after)
         (void)hipEventRecord(after, s);
     hipLaunchKernelGGL(k_epilogue, dim3(GRID_EPI), dim3(WG), 0, s, jobs, plan);

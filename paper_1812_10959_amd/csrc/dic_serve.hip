@@ -24,6 +24,7 @@ using namespace dic;
 namespace dic {
 // accessors implemented next to the database object
 const uint64_t *db_rows(dic_db *db);
+const uint64_t *db_vert(dic_db *db);
 uint64_t db_n(dic_db *db);
 uint32_t db_m(dic_db *db);
 uint32_t db_W(dic_db *db);
@@ -107,8 +108,8 @@ void worker_main(dic_server *S)
                     r->admitted = true;
                     S->used += r->bytes;
                     S->active++;
-                    add.push_back({db_rows(r->db), (uint32_t)db_n(r->db), db_m(r->db), r->minsup,
-                                   r->M});
+                    add.push_back({db_rows(r->db), db_vert(r->db), (uint32_t)db_n(r->db),
+                                   db_m(r->db), r->minsup, r->M});
                     ids.push_back(r->ticket);
                 }
                 if (!add.empty() || eng.size() > 0)

@@ -45,14 +45,25 @@ def assert_same(gpu, ref, label=""):
         assert np.array_equal(gpu.trace.astype(np.uint64), ref.trace), label
 
 
+LAYOUTS = (1, 0)  # item bitsets (default), row bitmaps
+
+
 def mine_both(dic, orc, rows, m, minsup, M, label=""):
+    """Mine on the GPU with both counting layouts and compare each with the oracle."""
     _say(f"case {label}: n={rows.shape[0]} m={m} minsup={minsup} M={M}")
     db = dic.dic_load_db(rows, m)
-    g = dic.dic_mine(db, minsup, M)
     r = orc.dic(rows, m, minsup, M)
-    assert_same(g, r, label)
-    assert is_canonical(g.masks)
-    return g
+    out = None
+    for layout in LAYOUTS:
+        dic.dic_set_option("layout", layout)
+        try:
+            g = dic.dic_mine(db, minsup, M)
+        finally:
+            dic.dic_set_option("layout", 1)
+        assert_same(g, r, f"{label} layout={layout}")
+        assert is_canonical(g.masks)
+        out = out or g
+    return out
 
 
 def test_hand_example(dic, orc):
@@ -144,6 +155,24 @@ def test_device_padding_check(dic):
     with pytest.raises(dic.DicError) as e:
         dic.dic_load_db(bad, 20)
     assert e.value.code == dic.DIC_E_INVAL
+
+
+def test_batch_mixed_layouts(dic, orc):
+    """Jobs of both layouts in one engine give the oracle's results."""
+    rows_a = synth.uniform_random(800, 100, 0.08, 41)
+    rows_b = synth.uniform_random(600, 64, 0.15, 42)
+    a, b = dic.dic_load_db(rows_a, 100), dic.dic_load_db(rows_b, 64)
+    dic.dic_set_option("layout", 0)
+    try:
+        ra = dic.dic_batch([a, b], [0.02, 0.03], [77, 600])
+    finally:
+        dic.dic_set_option("layout", 1)
+    rb = dic.dic_batch([a, b], [0.02, 0.03], [77, 600])
+    for x, y, rows, m, ms, M in ((ra[0], rb[0], rows_a, 100, 0.02, 77),
+                                 (ra[1], rb[1], rows_b, 64, 0.03, 600)):
+        ref = orc.dic(rows, m, ms, M)
+        assert_same(x, ref)
+        assert_same(y, ref)
 
 
 def test_batch_equals_solo(dic, orc):
