@@ -223,7 +223,8 @@ struct ActiveJob {
 // Engine
 // ---------------------------------------------------------------------------
 
-Engine::Engine(hipStream_t s, uint32_t max_jobs) : s_(s), max_jobs_(std::max(1u, max_jobs))
+Engine::Engine(hipStream_t s, uint32_t max_jobs)
+    : s_(s), max_jobs_(std::min(MAX_JOBS, std::max(1u, max_jobs)))
 {
     for (int i = (int)max_jobs_ - 1; i >= 0; --i)
         free_slots_.push_back(i);

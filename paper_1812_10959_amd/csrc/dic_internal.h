@@ -29,6 +29,7 @@ constexpr uint32_t NO_EPOCH = 0xFFFFFFFFu;
 constexpr unsigned long long SLOT_EMPTY = ~0ull;
 constexpr uint32_t MAX_ITEMS = 4096;  // W <= 64, so a 64-bit map covers the words
 constexpr int WG = 256;               // threads per workgroup in every kernel
+constexpr uint32_t MAX_JOBS = 4096;   // jobs in one engine (one step launch) at most
 constexpr int CW = 16;                // candidates per wave in the count kernel
 constexpr int CAND_PER_WG = CW * (WG / 64);
 constexpr int LDS_DWORDS = 8192;      // count kernel row tile (32 KiB)
@@ -82,7 +83,8 @@ struct JobState {
     unsigned long long tests;
     uint32_t fw, lw;    // vertical: 64-row words [fw, lw] hold the block
     uint32_t tw;        // vertical: words per tile
-    uint32_t pad[9];
+    uint32_t cpt;       // vertical: candidates per thread
+    uint32_t pad[8];
 };
 
 // Read-only description of one mining run (device copy in a job table).

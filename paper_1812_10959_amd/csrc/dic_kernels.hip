@@ -10,7 +10,6 @@
 //   k_count     CountSupport (Algorithm 3): live candidates x block rows
 //   k_epilogue  Prune (Algorithm 4) and CheckFullPass (Algorithm 5),
 //               compaction of the live list
-//   k_plan_cg   size MakeCandidates' work
 //   k_candgen   MakeCandidates: extend new boxes by frequent items
 // Before the loop: k_first_pass and k_l1 (FirstPass: item supports, the
 // frequent items), k_init_pairs (pairs of frequent items as candidates).
@@ -24,6 +23,8 @@ namespace {
 constexpr uint32_t FP_ROWS = 4096;       // first pass rows per workgroup item
 constexpr uint32_t FPV_WORDS = 4096;     // first pass (bitsets): words per work item
 constexpr uint32_t COUNT_TARGET = 2048;  // count work items aimed at per job
+constexpr uint32_t VT_TARGET = 768;      // bitset count: workgroups aimed at per job
+constexpr int VT_CPT = 8;                // bitset count: candidates per thread at most
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
@@ -65,33 +66,6 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *ctr, bool pred, bool u
         return base + (uint32_t)__popcll(b & lanemask_lt());
     }
     return pred ? atomicAdd(ctr, 1u) : 0u;
-}
-
-// Wave-aggregated add of a per-lane value (all lanes call).
-__device__ __forceinline__ void wave_add(uint32_t *ctr, uint32_t v, bool uniform)
-{
-    if (uniform) {
-        for (int off = 32; off > 0; off >>= 1)
-            v += (uint32_t)__shfl_xor((int)v, off);
-        if (lane_id() == 0 && v)
-            atomicAdd(ctr, v);
-    } else if (v) {
-        atomicAdd(ctr, v);
-    }
-}
-
-__device__ __forceinline__ void wave_max(uint32_t *ctr, uint32_t v, bool uniform)
-{
-    if (uniform) {
-        for (int off = 32; off > 0; off >>= 1) {
-            uint32_t o = (uint32_t)__shfl_xor((int)v, off);
-            v = o > v ? o : v;
-        }
-        if (lane_id() == 0 && v)
-            atomicMax(ctr, v);
-    } else if (v) {
-        atomicMax(ctr, v);
-    }
 }
 
 __device__ __forceinline__ dic_stop_trace *trace_of(const Job *J, const JobState *st)
@@ -184,6 +158,62 @@ __device__ uint32_t block_sum(uint32_t v, uint32_t *sh)
         t += sh[w];
     __syncthreads();
     return t;
+}
+
+// Workgroup-aggregated append: one atomic on ctr per workgroup; returns the
+// slot of a thread whose pred is true.  Every thread of the workgroup calls.
+// sh holds WG/64 + 1 words.
+__device__ uint32_t block_append(uint32_t *ctr, bool pred, uint32_t *sh)
+{
+    const unsigned long long b = __ballot(pred);
+    const uint32_t wave = threadIdx.x >> 6;
+    if (lane_id() == 0)
+        sh[wave] = (uint32_t)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < WG / 64; ++w) {
+            const uint32_t c = sh[w];
+            sh[w] = t;
+            t += c;
+        }
+        sh[WG / 64] = t ? atomicAdd(ctr, t) : 0u;
+    }
+    __syncthreads();
+    const uint32_t pos = sh[WG / 64] + sh[wave] + (uint32_t)__popcll(b & lanemask_lt());
+    __syncthreads();
+    return pos;
+}
+
+// Workgroup sums of NS values and maximum of one more; results valid in
+// thread 0.  sh holds (NS + 1) * WG/64 words.
+template <int NS>
+__device__ void block_reduce(uint32_t (&v)[NS + 1], uint32_t *sh)
+{
+    const uint32_t wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i <= NS; ++i) {
+        uint32_t x = v[i];
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)x, off);
+            x = i < NS ? x + o : (o > x ? o : x);
+        }
+        if (lane_id() == 0)
+            sh[i * (WG / 64) + wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i <= NS; ++i) {
+            uint32_t x = sh[i * (WG / 64)];
+            for (int w = 1; w < WG / 64; ++w) {
+                const uint32_t o = sh[i * (WG / 64) + w];
+                x = i < NS ? x + o : (o > x ? o : x);
+            }
+            v[i] = x;
+        }
+    }
+    __syncthreads();
 }
 
 }  // namespace
@@ -405,8 +435,14 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
                         const uint32_t lw = (uint32_t)((last - 1u) >> 6);
                         const uint32_t tw = vert_tile_words(st->nL1);
                         const uint32_t ntile = (lw - fw + tw) / tw;
-                        const uint32_t n_cg = (K + WG - 1u) / WG;
-                        uint32_t want = (COUNT_TARGET + n_cg - 1u) / n_cg;
+                        // candidates per thread: spend the parallelism beyond
+                        // VT_TARGET workgroups on fewer tile loads
+                        uint64_t cpt = ((uint64_t)K * ntile + (uint64_t)WG * VT_TARGET - 1u) /
+                                       ((uint64_t)WG * VT_TARGET);
+                        cpt = cpt < 1u ? 1u : (cpt > (uint64_t)VT_CPT ? (uint64_t)VT_CPT : cpt);
+                        st->cpt = (uint32_t)cpt;
+                        const uint32_t n_cg = (K + WG * (uint32_t)cpt - 1u) / (WG * (uint32_t)cpt);
+                        uint32_t want = (VT_TARGET + n_cg - 1u) / n_cg;
                         want = want < 1u ? 1u : (want > ntile ? ntile : want);
                         const uint32_t tpc = (ntile + want - 1u) / want;
                         st->fw = fw;
@@ -438,7 +474,7 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
         uint32_t tc, tv, te;
         const uint32_t ic = block_scan_incl<uint32_t>(items, sh, &tc);
         const uint32_t iv = block_scan_incl<uint32_t>(itemsv, sh, &tv);
-        const uint32_t ie = block_scan_incl<uint32_t>(K, sh, &te);
+        const uint32_t ie = block_scan_incl<uint32_t>((K + WG - 1u) / WG, sh, &te);
         if (j < njobs) {
             plan->pre_count[j + 1] = carry_c + ic;
             plan->pre_countv[j + 1] = carry_v + iv;
@@ -584,10 +620,15 @@ __global__ __launch_bounds__(WG) void k_count_vert(const Job *__restrict__ jobs,
         const uint64_t lo_mask = ~0ull << (st->first & 63u);
         const uint64_t hi_mask = (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
         const uint32_t K = st->K;
-        const uint32_t c = cg * WG + threadIdx.x;
-        const bool valid = c < K;
-        const uint32_t p = valid ? (st->parity ? J->live1 : J->live0)[c] : 0u;
-        uint32_t cnt = 0;
+        const uint32_t cpt = st->cpt;
+        const uint32_t *live = st->parity ? J->live1 : J->live0;
+        uint32_t pidx[VT_CPT], cnt[VT_CPT];
+#pragma unroll
+        for (int q = 0; q < VT_CPT; ++q) {
+            const uint32_t c = (cg * cpt + (uint32_t)q) * WG + threadIdx.x;
+            pidx[q] = ((uint32_t)q < cpt && c < K) ? live[c] : NONE;
+            cnt[q] = 0;
+        }
         for (uint32_t t = t0; t < t1; ++t) {
             const uint32_t w0 = fw + t * tw;
             const uint32_t nwt = (lw + 1u - w0) < tw ? (lw + 1u - w0) : tw;
@@ -603,7 +644,11 @@ __global__ __launch_bounds__(WG) void k_count_vert(const Job *__restrict__ jobs,
                     tile[a * ts + r] = J->vert[(uint64_t)J->l1[a] * J->nw + g] & mask;
             }
             __syncthreads();
-            if (valid) {
+#pragma unroll
+            for (int q = 0; q < VT_CPT; ++q) {
+                const uint32_t p = pidx[q];
+                if (p == NONE)
+                    continue;
                 uint64_t acc[VT_MAXW];
 #pragma unroll
                 for (int w = 0; w < VT_MAXW; ++w)
@@ -624,39 +669,41 @@ __global__ __launch_bounds__(WG) void k_count_vert(const Job *__restrict__ jobs,
                                 acc[w] &= row[w];
                     }
                 }
+                uint32_t sum = 0;
 #pragma unroll
                 for (int w = 0; w < VT_MAXW; ++w)
                     if ((uint32_t)w < nwt)
-                        cnt += (uint32_t)__popcll(acc[w]);
+                        sum += (uint32_t)__popcll(acc[w]);
+                cnt[q] += sum;
             }
         }
-        if (valid && cnt)
-            atomicAdd(J->psupp + p, cnt);
+#pragma unroll
+        for (int q = 0; q < VT_CPT; ++q)
+            if (pidx[q] != NONE && cnt[q])
+                atomicAdd(J->psupp + pidx[q], cnt[q]);
     }
 }
 
 // Prune (Algorithm 4) and CheckFullPass (Algorithm 5) for every live
 // candidate, plus the compaction of survivors into the next live list.
 // Candidates are counted for stop_I += 1 here (Algorithm 3's first line).
+// Work item = (job, chunk of WG candidates); appends and statistics are
+// aggregated per workgroup (one atomic per counter per workgroup).
 __global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
                                                  const Plan *__restrict__ plan)
 {
+    __shared__ uint32_t sh_app[WG / 64 + 1];
+    __shared__ uint32_t sh_red[6 * (WG / 64)];
     const uint32_t total = plan->pre_epi[plan->njobs];
-    const uint32_t lane = lane_id();
-    const uint32_t gw = (blockIdx.x * WG + threadIdx.x) >> 6;
-    const uint32_t nw = (gridDim.x * WG) >> 6;
-    for (uint32_t base = gw * 64u; base < total; base += nw * 64u) {
-        const uint32_t x = base + lane;
-        const bool valid = x < total;
-        const uint32_t j0 = find_job(plan->pre_epi, plan->njobs, base);
-        const uint32_t j = valid ? find_job(plan->pre_epi, plan->njobs, x) : j0;
-        const bool uniform = __ballot(j != j0) == 0ull;
+    for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const uint32_t j = find_job(plan->pre_epi, plan->njobs, it);
         const Job *J = jobs + j;
         JobState *st = J->st;
+        const uint32_t c = (it - plan->pre_epi[j]) * WG + threadIdx.x;
+        const bool valid = c < st->K;
         bool promoted = false, pruned = false, solid = false, keep = false;
         uint32_t p = 0, sc = 0, words = 0, items = 0;
         if (valid) {
-            const uint32_t c = x - plan->pre_epi[j];
             p = (st->parity ? J->live1 : J->live0)[c];
             items = J->pk[p];
             // nonzero 32-bit words of this candidate: its AND work per row
@@ -693,58 +740,30 @@ __global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
             J->pstate[p] = state;
         }
         uint32_t *next = st->parity ? J->live0 : J->live1;
-        const uint32_t pos = wave_append(&st->k_next, keep, uniform);
+        const uint32_t pos = block_append(&st->k_next, keep, sh_app);
         if (keep)
             next[pos] = p;
-        const uint32_t npos = wave_append(&st->n_new, promoted, uniform);
+        const uint32_t npos = block_append(&st->n_new, promoted, sh_app);
         if (promoted)
             J->newbox[npos] = p;
-        wave_max(&st->max_rem, keep ? J->stop_max - sc : 0u, uniform);
-        dic_stop_trace *tr = trace_of(J, st);
-        if (uniform) {
+        uint32_t v[6] = {words, items, promoted ? 1u : 0u, pruned ? 1u : 0u, solid ? 1u : 0u,
+                         keep ? J->stop_max - sc : 0u};
+        block_reduce<5>(v, sh_red);
+        if (threadIdx.x == 0) {
+            dic_stop_trace *tr = trace_of(J, st);
             if (tr) {
-                wave_add(&tr->words, words, true);
-                wave_add(&tr->items, items, true);
-                wave_append(&tr->promoted, promoted, true);
-                wave_append(&tr->pruned, pruned, true);
-                wave_append(&tr->solidified, solid, true);
+                atomicAdd(&tr->words, v[0]);
+                atomicAdd(&tr->items, v[1]);
+                if (v[2])
+                    atomicAdd(&tr->promoted, v[2]);
+                if (v[3])
+                    atomicAdd(&tr->pruned, v[3]);
+                if (v[4])
+                    atomicAdd(&tr->solidified, v[4]);
             }
-        } else if (tr) {
-            if (words)
-                atomicAdd(&tr->words, words);
-            if (items)
-                atomicAdd(&tr->items, items);
-            if (promoted)
-                atomicAdd(&tr->promoted, 1u);
-            if (pruned)
-                atomicAdd(&tr->pruned, 1u);
-            if (solid)
-                atomicAdd(&tr->solidified, 1u);
+            if (v[5])
+                atomicMax(&st->max_rem, v[5]);
         }
-    }
-}
-
-// Size MakeCandidates' work: (new boxes) x (frequent items) per job.
-__global__ __launch_bounds__(WG) void k_plan_cg(const Job *__restrict__ jobs, Plan *plan)
-{
-    __shared__ unsigned long long sh[WG];
-    const uint32_t njobs = plan->njobs;
-    unsigned long long carry = 0;
-    if (threadIdx.x == 0)
-        plan->pre_cg[0] = 0;
-    for (uint32_t b = 0; b < njobs; b += WG) {
-        const uint32_t j = b + threadIdx.x;
-        unsigned long long v = 0;
-        if (j < njobs) {
-            const JobState *st = jobs[j].st;
-            if (!st->done && !st->overflow)
-                v = (unsigned long long)st->n_new * st->nL1;
-        }
-        unsigned long long tot;
-        const unsigned long long incl = block_scan_incl<unsigned long long>(v, sh, &tot);
-        if (j < njobs)
-            plan->pre_cg[j + 1] = carry + incl;
-        carry += tot;
     }
 }
 
@@ -754,30 +773,49 @@ __global__ __launch_bounds__(WG) void k_plan_cg(const Job *__restrict__ jobs, Pl
 // C \ {i}: the one with the largest i, so no candidate is generated twice
 // and no set of already-known itemsets is needed (an itemset whose subsets
 // were all boxes before this stop was generated at an earlier stop).
+// Work item = (job, chunk of WG (new box, frequent item) pairs); every
+// workgroup derives the per-job prefix of chunks itself.
 __global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
                                                 const Plan *__restrict__ plan)
 {
-    const unsigned long long total = plan->pre_cg[plan->njobs];
-    const uint32_t lane = lane_id();
-    const unsigned long long gw = ((unsigned long long)blockIdx.x * WG + threadIdx.x) >> 6;
-    const unsigned long long nw = ((unsigned long long)gridDim.x * WG) >> 6;
+    __shared__ unsigned long long pre[MAX_JOBS + 1];
+    __shared__ unsigned long long sh_scan[WG];
+    __shared__ uint32_t sh_app[WG / 64 + 1];
+    __shared__ uint32_t sh_red[2 * (WG / 64)];
+    const uint32_t njobs = plan->njobs;
+    unsigned long long carry = 0;
+    if (threadIdx.x == 0)
+        pre[0] = 0;
+    for (uint32_t b = 0; b < njobs; b += WG) {
+        const uint32_t j = b + threadIdx.x;
+        unsigned long long v = 0;
+        if (j < njobs) {
+            const JobState *st = jobs[j].st;
+            if (!st->done && !st->overflow)
+                v = ((unsigned long long)st->n_new * st->nL1 + WG - 1u) / WG;
+        }
+        unsigned long long tot;
+        const unsigned long long incl = block_scan_incl<unsigned long long>(v, sh_scan, &tot);
+        if (j < njobs)
+            pre[j + 1] = carry + incl;
+        carry += tot;
+    }
+    __syncthreads();
+    const unsigned long long total = pre[njobs];
     const unsigned long long *z = plan->zobrist;
-    for (unsigned long long base = gw * 64ull; base < total; base += nw * 64ull) {
-        const unsigned long long x = base + lane;
-        const bool valid = x < total;
-        const uint32_t j0 = find_job(plan->pre_cg, plan->njobs, base);
-        const uint32_t j = valid ? find_job(plan->pre_cg, plan->njobs, x) : j0;
-        const bool uniform = __ballot(j != j0) == 0ull;
+    for (unsigned long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const uint32_t j = find_job(pre, njobs, it);
         const Job *J = jobs + j;
         JobState *st = J->st;
         const uint32_t W = J->W;
+        const uint32_t nL1 = st->nL1;
+        const unsigned long long x = (it - pre[j]) * WG + threadIdx.x;
+        const bool valid = x < (unsigned long long)st->n_new * nL1;
         bool gen = false;
         uint32_t p = 0, i = 0, k = 0;
         unsigned long long hC = 0;
         if (valid) {
-            const uint32_t nL1 = st->nL1;
-            const unsigned long long local = x - plan->pre_cg[j];
-            const uint32_t q = (uint32_t)(local / nL1), a = (uint32_t)(local % nL1);
+            const uint32_t q = (uint32_t)(x / nL1), a = (uint32_t)(x % nL1);
             p = J->newbox[q];
             i = J->l1[a];
             const uint64_t *S = J->pmask + (uint64_t)p * W;
@@ -807,7 +845,7 @@ __global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
                 }
             }
         }
-        const uint32_t np = wave_append(&st->pool_n, gen, uniform);
+        const uint32_t np = block_append(&st->pool_n, gen, sh_app);
         const bool stored = gen && np < J->cap;
         if (gen && !stored)
             st->overflow = 1u;
@@ -828,16 +866,16 @@ __global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
             hash_insert(J, hC, k + 1u, np);
         }
         uint32_t *next = st->parity ? J->live0 : J->live1;
-        const uint32_t pos = wave_append(&st->k_next, stored, uniform);
+        const uint32_t pos = block_append(&st->k_next, stored, sh_app);
         if (stored)
             next[pos] = np;
-        wave_max(&st->max_rem, stored ? J->stop_max : 0u, uniform);
-        dic_stop_trace *tr = trace_of(J, st);
-        if (uniform) {
+        uint32_t v[2] = {stored ? 1u : 0u, stored ? J->stop_max : 0u};
+        block_reduce<1>(v, sh_red);
+        if (threadIdx.x == 0 && v[0]) {
+            dic_stop_trace *tr = trace_of(J, st);
             if (tr)
-                wave_append(&tr->generated, stored, true);
-        } else if (tr && stored) {
-            atomicAdd(&tr->generated, 1u);
+                atomicAdd(&tr->generated, v[0]);
+            atomicMax(&st->max_rem, v[1]);
         }
     }
 }
@@ -951,7 +989,6 @@ void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, bool rows, bo
     if (after)
         (void)hipEventRecord(after, s);
     hipLaunchKernelGGL(k_epilogue, dim3(GRID_EPI), dim3(WG), 0, s, jobs, plan);
-    hipLaunchKernelGGL(k_plan_cg, dim3(1), dim3(WG), 0, s, jobs, pl);
     hipLaunchKernelGGL(k_candgen, dim3(GRID_CG), dim3(WG), 0, s, jobs, plan);
 }
 
