@@ -60,24 +60,49 @@ def mine_rate(stats, n, m):
     return (stats["tests"] + n * m)
 
 
-def count_roofline(results, W):
-    """Algorithmic work of every CountSupport launch, summed over results.
+def count_work(results, W, n_frequent_items, layout):
+    """Algorithmic work of the CountSupport launches of these results.
 
-    Per stop: bytes = block rows x 8W (the block is read once) + live x 8W
-    (candidate masks); lane-ops = (nonzero 32-bit words of the live masks +
-    one compare per candidate) x block rows."""
-    byt = ops = 0
+    Per stop s with B_s block rows, K_s live candidates, sum of their sizes
+    I_s and nonzero 32-bit mask words Z_s:
+      item bitsets (layout 1): bytes = F * ceil(B_s/64) * 8 (the frequent
+        items' words of the block, read once) + K_s * 16 (mask word, count);
+        lane-ops = 2 * I_s * ceil(B_s/64) (one 64-bit AND per item beyond
+        the first and one 64-bit popcount per candidate and word, two 32-bit
+        lane operations each);
+      row bitmaps (layout 0): bytes = B_s * 8W + K_s * 8W; lane-ops =
+        (Z_s + K_s) * B_s (one AND-accumulate per nonzero word and one
+        compare per candidate and row)."""
+    byt = ops = 0.0
     ms = 0.0
     launches = 0
     for r in results:
         rows = r.trace[:, 1].astype(np.float64)
         live = r.trace[:, 2].astype(np.float64)
-        words = r.words.astype(np.float64)
-        byt += float((rows * 8 * W + live * 8 * W).sum())
-        ops += float(((words + live) * rows).sum())
+        if layout == 1:
+            words64 = np.ceil(rows / 64.0)
+            byt += float((n_frequent_items * words64 * 8 + live * 16).sum())
+            ops += float((2.0 * r.items.astype(np.float64) * words64).sum())
+        else:
+            byt += float((rows * 8 * W + live * 8 * W).sum())
+            ops += float(((r.words.astype(np.float64) + live) * rows).sum())
         ms += r.stats["count_ms"]
         launches += r.stats["count_launches"]
     return byt, ops, ms, launches
+
+
+def roofline_entry(byt, ops, ms, launches):
+    achieved_tops = ops / (ms * 1e-3) / 1e12 if ms else 0.0
+    achieved_gbs = byt / (ms * 1e-3) / 1e9 if ms else 0.0
+    return {
+        "kernel": "k_count_vert", "bound": "alu", "achieved": achieved_tops,
+        "peak": ALU_PEAK_TOPS, "unit": "Tops/s (int32 VALU lane-ops)",
+        "frac": achieved_tops / ALU_PEAK_TOPS, "traffic": None,
+        "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved_gbs / HBM_PEAK_GBS},
+        "avg_launch_us": ms / launches * 1e3 if launches else 0.0,
+        "launches": launches, "count_ms": ms,
+    }
 
 
 def headline(dic, args):
@@ -89,7 +114,7 @@ def headline(dic, args):
     rows, m = c["rows"], c["m"]
     n, W = rows.shape
     db = dic.dic_load_db(rows, m)
-    dic.dic_set_option("profile", 1)
+    dic.dic_set_option("profile", 0)
     import torch
     for i in range(args.warmup):
         r = dic.dic_mine(db, c["minsup"], c["M"])
@@ -107,27 +132,38 @@ def headline(dic, args):
     st = res[0].stats
     tests = mine_rate(st, n, m)
     value = tests * args.steps / dt / 1e9
-    byt, ops, cms, launches = count_roofline(res, W)
-    log(f"  timed {args.steps} steps: {dt / args.steps * 1e3:.2f} ms/step, {value:.1f} G tests/s, "
-        f"count kernel {cms / args.steps:.2f} ms/step over {launches // args.steps} launches")
-    out = {
-        "value": value, "ms_per_step": dt / args.steps * 1e3, "stats": st,
-        "workload": c, "db": db, "rows": rows,
-        "count": {"ms_per_step": cms / args.steps, "launches_per_step": launches / args.steps,
-                  "bytes_per_step": byt / args.steps, "ops_per_step": ops / args.steps,
-                  "tests_per_step": st["tests"]},
-    }
-    achieved_tops = ops / (cms * 1e-3) / 1e12 if cms else 0.0
-    achieved_gbs = byt / (cms * 1e-3) / 1e9 if cms else 0.0
-    out["roofline"] = {
-        "kernel": "k_count", "bound": "alu", "achieved": achieved_tops, "peak": ALU_PEAK_TOPS,
-        "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved_tops / ALU_PEAK_TOPS,
-        "traffic": None,
-        "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved_gbs / HBM_PEAK_GBS},
-        "count_tests_per_s": st["tests"] / (cms / args.steps * 1e-3) if cms else 0.0,
-        "avg_launch_us": cms / launches * 1e3 if launches else 0.0,
-    }
+    log(f"  timed {args.steps} steps: {dt / args.steps * 1e3:.2f} ms/step, {value:.1f} G tests/s")
+    out = {"value": value, "ms_per_step": dt / args.steps * 1e3, "stats": st,
+           "workload": c, "db": db, "rows": rows}
+    # Count-kernel roofline: a second timed region with HIP events around
+    # every CountSupport launch (profiled runs launch directly, not as graphs).
+    n_freq_items = int((np.bitwise_count(res[0].masks).sum(axis=1) == 1).sum())
+    layouts = {}
+    for layout in (1, 0):
+        dic.dic_set_option("layout", layout)
+        dic.dic_set_option("profile", 1)
+        prof = []
+        reps = args.steps if layout == 1 else max(1, min(2, args.steps))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            prof.append(dic.dic_mine(db, c["minsup"], c["M"]))
+        pdt = (time.perf_counter() - t0) / reps
+        dic.dic_set_option("profile", 0)
+        byt, ops, cms, launches = count_work(prof, W, n_freq_items, layout)
+        entry = roofline_entry(byt, ops, cms, launches)
+        entry["kernel"] = "k_count_vert" if layout == 1 else "k_count"
+        entry["count_ms_per_step"] = cms / reps
+        entry["mine_ms_per_step_profiled"] = pdt * 1e3
+        entry["count_G_tests_per_s"] = st["tests"] / (cms / reps * 1e-3) / 1e9 if cms else 0.0
+        entry["bytes_per_step"] = byt / reps
+        entry["ops_per_step"] = ops / reps
+        layouts["item_bitsets" if layout == 1 else "row_bitmaps"] = entry
+        log(f"  layout {layout}: count {cms / reps:.2f} ms/step over {launches // reps} launches,"
+            f" {entry['achieved']:.3f} Tops/s ({100 * entry['frac']:.2f}% ALU), "
+            f"{entry['hbm']['achieved']:.1f} GB/s, mine {pdt * 1e3:.1f} ms profiled")
+    dic.dic_set_option("layout", 1)
+    out["roofline"] = layouts["item_bitsets"]
+    out["layouts"] = layouts
     return out
 
 
@@ -299,7 +335,7 @@ def main():
         "roofline": h["roofline"],
         "stats": {k: h["stats"][k] for k in ("tau", "stops", "tests", "peak_live", "n_frequent",
                                               "k_max", "known", "restarts")},
-        "count_kernel": h["count"],
+        "layouts": h["layouts"],
     }
     if not args.only_headline:
         if not args.no_cpu:

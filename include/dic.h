@@ -200,11 +200,14 @@ DIC_API int dic_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(vo
  * Library options (process-wide):
  *   "profile"  0/1: time every CountSupport launch with HIP events recorded
  *              on the stream it runs on; reported as dic_stats.count_ms.
+ *              Profiled runs launch their kernels directly (no graphs).
  *   "layout"   counting layout of runs started from now on: 1 (default)
  *              per-item bitsets over 64-row words (a candidate's support in
  *              a word is the popcount of the AND of its items' words), 0 the
  *              row bitmaps themselves (one AND/compare per row and nonzero
  *              word).  Both give identical results.
+ *   "graphs"   1 (default): stops run as replays of a captured HIP graph of
+ *              a few stops on the engine's own stream; 0: direct launches.
  */
 DIC_API int dic_set_option(const char *name, int64_t value);
 

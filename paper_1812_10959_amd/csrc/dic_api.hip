@@ -172,6 +172,10 @@ int dic_set_option(const char *name, int64_t value)
         set_profiling((int)value);
         return DIC_OK;
     }
+    if (name && std::strcmp(name, "graphs") == 0 && (value == 0 || value == 1)) {
+        set_use_graphs(value != 0);
+        return DIC_OK;
+    }
     if (name && std::strcmp(name, "layout") == 0 && (value == 0 || value == 1)) {
         set_count_layout(value ? LAYOUT_VERTICAL : LAYOUT_ROWS);
         return DIC_OK;

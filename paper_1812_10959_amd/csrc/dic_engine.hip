@@ -146,12 +146,16 @@ struct PoolLayout {
 
 std::atomic<int> g_profile{0};
 std::atomic<uint32_t> g_layout{LAYOUT_VERTICAL};
+std::atomic<bool> g_graphs{true};
+constexpr uint32_t GRAPH_STEPS = 8;  // stops per captured step graph
 
 }  // namespace
 
 bool profiling() { return g_profile.load() != 0; }
 void set_profiling(int on) { g_profile.store(on); }
 uint32_t count_layout() { return g_layout.load(); }
+bool use_graphs() { return g_graphs.load(); }
+void set_use_graphs(bool on) { g_graphs.store(on); }
 void set_count_layout(uint32_t layout) { g_layout.store(layout); }
 
 // ---------------------------------------------------------------------------
@@ -226,6 +230,12 @@ struct ActiveJob {
 Engine::Engine(hipStream_t s, uint32_t max_jobs)
     : s_(s), max_jobs_(std::min(MAX_JOBS, std::max(1u, max_jobs)))
 {
+    if (!s_) {
+        if (hipStreamCreateWithFlags(&s_, hipStreamNonBlocking) == hipSuccess)
+            own_stream_ = true;
+        else
+            s_ = nullptr;
+    }
     for (int i = (int)max_jobs_ - 1; i >= 0; --i)
         free_slots_.push_back(i);
     st_.resize(max_jobs_);
@@ -242,6 +252,69 @@ Engine::~Engine()
     dev_free(plan_buf_);
     for (hipEvent_t e : events_)
         (void)hipEventDestroy(e);
+    for (auto &a : graphs_)
+        for (hipGraphExec_t g : a)
+            if (g)
+                (void)hipGraphExecDestroy(g);
+    if (own_stream_)
+        (void)hipStreamDestroy(s_);
+}
+
+// Run at least S stops for every job in the step table: replays of a
+// captured GRAPH_STEPS-stop graph when graphs are on, direct launches
+// otherwise.  With profiling, events bracket each CountSupport launch and
+// *count_ms receives their summed elapsed time.
+int Engine::launch_steps(uint32_t S, bool rows, bool vert, bool prof, double *count_ms,
+                         uint32_t *steps_done)
+{
+    *count_ms = 0;
+    if (prof) {
+        const uint32_t need = 2 * std::max(S, GRAPH_STEPS);
+        while (events_.size() < need) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            events_.push_back(e);
+        }
+    }
+    auto add_event_times = [&](uint32_t n) -> int {
+        for (uint32_t k = 0; k < n; ++k) {
+            float t = 0;
+            HIP_TRY(hipEventElapsedTime(&t, events_[2 * k], events_[2 * k + 1]));
+            *count_ms += t;
+        }
+        return DIC_OK;
+    };
+    // Events recorded inside a captured graph cannot be timed: profile directly.
+    if (!use_graphs() || !own_stream_ || prof) {
+        for (uint32_t k = 0; k < S; ++k)
+            launch_step((const Job *)table_, d_plan_step_, s_, rows, vert,
+                        prof ? events_[2 * k] : nullptr, prof ? events_[2 * k + 1] : nullptr);
+        HIP_TRY(hipGetLastError());
+        *steps_done = S;
+        if (prof) {
+            HIP_TRY(hipStreamSynchronize(s_));
+            return add_event_times(S);
+        }
+        return DIC_OK;
+    }
+    hipGraphExec_t &g = graphs_[rows][vert];
+    if (!g) {
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+        for (uint32_t k = 0; k < GRAPH_STEPS; ++k)
+            launch_step((const Job *)table_, d_plan_step_, s_, rows, vert);
+        const hipError_t le = hipGetLastError();
+        HIP_TRY(hipStreamEndCapture(s_, &graph));
+        HIP_TRY(le);
+        const hipError_t ie = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIP_TRY(ie);
+    }
+    const uint32_t reps = (S + GRAPH_STEPS - 1) / GRAPH_STEPS;
+    for (uint32_t r = 0; r < reps; ++r)
+        HIP_TRY(hipGraphLaunch(g, s_));
+    *steps_done = reps * GRAPH_STEPS;
+    return DIC_OK;
 }
 
 bool Engine::running() const
@@ -555,41 +628,32 @@ int Engine::advance(uint32_t max_steps)
             S = std::max(S, s.max_rem);
     }
     S = std::min(S, std::max(1u, max_steps));
-    int rc = ensure_trace(S);
+    // graph replays run whole multiples of GRAPH_STEPS stops
+    const bool prof = profiling();
+    const uint32_t S_run = (use_graphs() && own_stream_ && !prof)
+                               ? (S + GRAPH_STEPS - 1) / GRAPH_STEPS * GRAPH_STEPS
+                               : S;
+    int rc = ensure_trace(S_run);
     if (rc)
         return rc;
     if (table_dirty_ && (rc = upload_table()))
         return rc;
-    const bool prof = profiling();
-    if (prof) {
-        while (events_.size() < 2 * S) {
-            hipEvent_t e;
-            HIP_TRY(hipEventCreate(&e));
-            events_.push_back(e);
-        }
-    }
     bool any_rows = false, any_vert = false;
     for (const Job &J : table_host_) {
         any_rows |= J.layout == LAYOUT_ROWS;
         any_vert |= J.layout == LAYOUT_VERTICAL;
     }
-    for (uint32_t k = 0; k < S; ++k)
-        launch_step((const Job *)table_, d_plan_step_, s_, any_rows, any_vert,
-                    prof ? events_[2 * k] : nullptr, prof ? events_[2 * k + 1] : nullptr);
-    HIP_TRY(hipGetLastError());
+    double ms = 0;
+    uint32_t done = 0;
+    if ((rc = launch_steps(S, any_rows, any_vert, prof, &ms, &done)))
+        return rc;
     if ((rc = read_states()))
         return rc;
     if (prof) {
-        double ms = 0;
-        for (uint32_t k = 0; k < S; ++k) {
-            float t = 0;
-            HIP_TRY(hipEventElapsedTime(&t, events_[2 * k], events_[2 * k + 1]));
-            ms += t;
-        }
         for (ActiveJob *a : jobs_)
             if (a->in_loop) {
                 a->count_ms += ms;
-                a->count_launches += S;
+                a->count_launches += done;
             }
     }
     return DIC_OK;
@@ -769,14 +833,43 @@ int Engine::harvest(std::vector<std::pair<uint64_t, MineOutput>> &done)
 // run a fixed set of jobs to completion
 // ---------------------------------------------------------------------------
 
+namespace {
+std::mutex g_pool_mu;
+std::vector<Engine *> g_pool;  // idle engines, each with its own stream and graphs
+
+struct PooledEngine {
+    Engine *e;
+    PooledEngine()
+    {
+        std::lock_guard<std::mutex> g(g_pool_mu);
+        if (g_pool.empty()) {
+            e = new Engine(nullptr, MAX_JOBS);
+        } else {
+            e = g_pool.back();
+            g_pool.pop_back();
+        }
+    }
+    ~PooledEngine()
+    {
+        if (e->size() == 0) {
+            std::lock_guard<std::mutex> g(g_pool_mu);
+            g_pool.push_back(e);
+        } else {
+            delete e;  // left jobs behind after an error: do not reuse
+        }
+    }
+};
+}  // namespace
+
 int run_jobs(const std::vector<MineRequest> &reqs, std::vector<MineOutput> &outs,
              hipStream_t stream)
 {
     outs.assign(reqs.size(), MineOutput{});
     if (reqs.empty())
         return DIC_OK;
-    const uint32_t cap = (uint32_t)std::min<size_t>(reqs.size(), 4096);
-    Engine eng(stream, cap);
+    PooledEngine pe;
+    Engine &eng = *pe.e;
+    const uint32_t cap = MAX_JOBS;
     std::vector<uint64_t> ids(reqs.size());
     std::iota(ids.begin(), ids.end(), 0ull);
     size_t next = 0;
@@ -805,6 +898,7 @@ int run_jobs(const std::vector<MineRequest> &reqs, std::vector<MineOutput> &outs
     }
     for (auto &d : done)
         outs[d.first] = std::move(d.second);
+    (void)stream;  // every result is on the host already: the run is complete
     return DIC_OK;
 }
 

@@ -84,7 +84,10 @@ struct JobState {
     uint32_t fw, lw;    // vertical: 64-row words [fw, lw] hold the block
     uint32_t tw;        // vertical: words per tile
     uint32_t cpt;       // vertical: candidates per thread
-    uint32_t pad[8];
+    uint32_t cmode;     // vertical: 0 LDS tiles, 1 one wave per candidate
+    uint32_t pool_base; // pool size when this stop began: entries at or above
+                        // it were created by this stop's candidate generation
+    uint32_t pad[6];
 };
 
 // Read-only description of one mining run (device copy in a job table).
@@ -175,9 +178,12 @@ struct MineOutput {
 // Compute tau from minsup; returns false on invalid minsup.
 bool threshold(double minsup, uint64_t n, uint64_t *tau);
 
-// Mine every request together (one launch per kernel per stop).
+// Mine every request together (one launch per kernel per stop) on a pooled
+// engine; stream is made to wait for the run's completion (nullptr: none).
 int run_jobs(const std::vector<MineRequest> &reqs, std::vector<MineOutput> &outs,
              hipStream_t stream);
+bool use_graphs();
+void set_use_graphs(bool on);
 
 // Device bytes of a job's working memory for a given candidate capacity.
 uint64_t job_bytes(uint32_t m, uint64_t cap, uint32_t trace_cap);
@@ -200,6 +206,8 @@ struct ActiveJob;
 // Not thread-safe: one owner thread.
 class Engine {
   public:
+    // s: the stream to run on; nullptr makes a private one (needed for
+    // graph capture, which must not see other threads' work).
     Engine(hipStream_t s, uint32_t max_jobs);
     ~Engine();
     Engine(const Engine &) = delete;
@@ -219,8 +227,12 @@ class Engine {
     int upload_table();
     int ensure_trace(uint32_t steps);
     int collect(std::vector<ActiveJob *> &fin, std::vector<std::pair<uint64_t, MineOutput>> &out);
+    int launch_steps(uint32_t S, bool rows, bool vert, bool prof, double *count_ms,
+                     uint32_t *steps_done);
 
     hipStream_t s_;
+    bool own_stream_ = false;
+    hipGraphExec_t graphs_[2][2] = {};  // [rows][vert]
     uint32_t max_jobs_;
     std::vector<ActiveJob *> jobs_;
     std::vector<int> free_slots_;

@@ -25,6 +25,8 @@ constexpr uint32_t FPV_WORDS = 4096;     // first pass (bitsets): words per work
 constexpr uint32_t COUNT_TARGET = 2048;  // count work items aimed at per job
 constexpr uint32_t VT_TARGET = 768;      // bitset count: workgroups aimed at per job
 constexpr int VT_CPT = 8;                // bitset count: candidates per thread at most
+constexpr uint32_t VT_WAVE_K = 2048;     // bitset count: below this many live candidates
+                                         // each wave counts one candidate over the block
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
@@ -96,8 +98,13 @@ __device__ __forceinline__ void hash_insert(const Job *J, unsigned long long h, 
 }
 
 // Pool index of the itemset (S | {i}) \ {x} with hash h and size k, or NONE.
+// Only itemsets that existed when the stop began (index < base) are
+// considered: one created by this stop's candidate generation is a fresh
+// circle, never the box being looked for, and its pool entry may still be
+// in flight from another workgroup, so it is skipped without being read.
 __device__ __forceinline__ uint32_t hash_find_sub(const Job *J, unsigned long long h, uint32_t k,
-                                                  const uint64_t *S, uint32_t i, uint32_t x)
+                                                  const uint64_t *S, uint32_t i, uint32_t x,
+                                                  uint32_t base)
 {
     const uint32_t tag = slot_tag(h, k);
     const uint32_t W = J->W;
@@ -107,7 +114,7 @@ __device__ __forceinline__ uint32_t hash_find_sub(const Job *J, unsigned long lo
             __hip_atomic_load(J->slots + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (v == SLOT_EMPTY)
             return NONE;
-        if ((uint32_t)v == tag) {
+        if ((uint32_t)v == tag && (uint32_t)(v >> 32) < base) {
             uint32_t idx = (uint32_t)(v >> 32);
             const uint64_t *P = J->pmask + (uint64_t)idx * W;
             bool eq = true;
@@ -404,6 +411,7 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
                 } else {
                     K = st->k_next;
                     st->K = K;
+                    st->pool_base = st->pool_n;
                     st->k_next = 0;
                     st->n_new = 0;
                     st->parity ^= 1u;
@@ -429,8 +437,15 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
                         t.reserved = 0;
                         J->trace[st->epoch - 1u] = t;
                     }
-                    if (J->layout == LAYOUT_VERTICAL) {
+                    if (J->layout == LAYOUT_VERTICAL && K < VT_WAVE_K) {
+                        // few candidates: one wave per candidate, no tile
+                        st->fw = (uint32_t)(first >> 6);
+                        st->lw = (uint32_t)((last - 1u) >> 6);
+                        st->cmode = 1;
+                        itemsv = (K + WG / 64 - 1u) / (WG / 64);
+                    } else if (J->layout == LAYOUT_VERTICAL) {
                         // (candidate groups of WG) x (chunks of tiles of tw words)
+                        st->cmode = 0;
                         const uint32_t fw = (uint32_t)(first >> 6);
                         const uint32_t lw = (uint32_t)((last - 1u) >> 6);
                         const uint32_t tw = vert_tile_words(st->nL1);
@@ -609,6 +624,40 @@ __global__ __launch_bounds__(WG) void k_count_vert(const Job *__restrict__ jobs,
         const Job *J = jobs + j;
         const JobState *st = J->st;
         const uint32_t local = it - plan->pre_countv[j];
+        if (st->cmode == 1) {
+            // wave mode: this wave owns candidate c over every word of the block
+            const uint32_t c = local * (WG / 64) + (threadIdx.x >> 6);
+            if (c >= st->K)
+                continue;
+            const uint32_t lane = threadIdx.x & 63u;
+            const uint32_t p = (st->parity ? J->live1 : J->live0)[c];
+            const uint64_t nz = J->pnz[p];
+            const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+            const uint64_t lo_mask = ~0ull << (st->first & 63u);
+            const uint64_t hi_mask =
+                (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
+            uint32_t cnt = 0;
+            for (uint32_t w = st->fw + lane; w <= st->lw; w += 64) {
+                uint64_t acc = (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull);
+                uint64_t nzw = nz;
+                while (nzw) {
+                    const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
+                    nzw &= nzw - 1;
+                    uint64_t bits = cm[wd];
+                    while (bits) {
+                        const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
+                        bits &= bits - 1;
+                        acc &= J->vert[(uint64_t)item * J->nw + w];
+                    }
+                }
+                cnt += (uint32_t)__popcll(acc);
+            }
+            for (int off = 32; off > 0; off >>= 1)
+                cnt += (uint32_t)__shfl_xor((int)cnt, off);
+            if (lane == 0 && cnt)
+                J->psupp[p] += cnt;  // the only writer of this candidate's count
+            continue;
+        }
         const uint32_t n_cg = st->n_ct;
         const uint32_t rc = local / n_cg;
         const uint32_t cg = local - rc * n_cg;
@@ -831,7 +880,31 @@ __global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
                     while (gen && bits) {
                         const uint32_t xj = wd * 64u + (uint32_t)__builtin_ctzll(bits);
                         bits &= bits - 1;
-                        const uint32_t sub = hash_find_sub(J, hC ^ z[xj], k, S, i, xj);
+                        uint32_t sub;
+                        if (k == 2u) {
+                            // the other item y of S: C \ {xj} = {y, i} is the pair
+                            // candidate at its index among pairs of frequent items
+                            // (pool slots 0 .. nC2-1, in k_init_pairs' order)
+                            uint32_t y = 0;
+                            for (uint32_t w = 0; w < W; ++w) {
+                                uint64_t o = S[w];
+                                if (w == (xj >> 6))
+                                    o &= ~(1ull << (xj & 63u));
+                                if (o) {
+                                    y = w * 64u + (uint32_t)__builtin_ctzll(o);
+                                    break;
+                                }
+                            }
+                            uint32_t u = J->l1pos[y], v = J->l1pos[i];
+                            if (u > v) {
+                                const uint32_t t = u;
+                                u = v;
+                                v = t;
+                            }
+                            sub = u * nL1 - u * (u + 1u) / 2u + (v - u - 1u);
+                        } else {
+                            sub = hash_find_sub(J, hC ^ z[xj], k, S, i, xj, st->pool_base);
+                        }
                         if (sub == NONE) {
                             gen = false;
                         } else {

@@ -67,7 +67,6 @@ struct dic_server {
     std::vector<double> lat_ms;
     bool any = false;
     clk::time_point first_submit, last_done;
-    hipStream_t stream = nullptr;
     int device = 0;
     std::thread worker;
 };
@@ -91,7 +90,7 @@ void finish(dic_server *S, Req *r, int status, MineOutput &&o)
 void worker_main(dic_server *S)
 {
     (void)hipSetDevice(S->device);
-    Engine eng(S->stream, S->max_active);
+    Engine eng(nullptr, S->max_active);  // its own stream: step graphs can be captured
     std::vector<std::pair<uint64_t, MineOutput>> done;
     for (;;) {
         std::vector<MineRequest> add;
@@ -212,11 +211,10 @@ int dic_serve_create(uint64_t hbm_budget_bytes, const dic_serve_opts *opts, dic_
     S->budget = hbm_budget_bytes;
     if (opts && opts->max_active)
         S->max_active = std::min<uint32_t>(opts->max_active, 4096);
-    if (hipGetDevice(&S->device) != hipSuccess ||
-        hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+    if (hipGetDevice(&S->device) != hipSuccess) {
         (void)hipGetLastError();
         delete S;
-        set_error("dic_serve_create: could not create a stream");
+        set_error("dic_serve_create: no device");
         return DIC_E_DEVICE;
     }
     S->worker = std::thread(worker_main, S);
@@ -351,7 +349,6 @@ int dic_serve_destroy(dic_server *S)
     }
     if (S->worker.joinable())
         S->worker.join();
-    (void)hipStreamDestroy(S->stream);
     delete S;
     return DIC_OK;
 }

@@ -190,6 +190,24 @@ def test_batch_equals_solo(dic, orc):
         assert_same(res[i], orc.dic(rows_l[i], m, ms, M), f"batch elem {i} vs oracle")
 
 
+def test_repeat_calls_deep_itemsets(dic, orc):
+    """Deep candidates (subset lookups through the hash table) mined again and
+    again on recycled device memory: every run equals the oracle."""
+    c = synth.config(3, n=20_000)
+    ref = orc.dic(c["rows"], c["m"], c["minsup"], 2_000)
+    assert ref.stats["k_max"] >= 6
+    db = dic.dic_load_db(c["rows"], c["m"])
+    for rep in range(6):
+        g = dic.dic_mine(db, c["minsup"], 2_000)
+        assert_same(g, ref, f"repeat {rep}")
+    rows, _ = synth.quest(5000, 300, n_patterns=200, pat_len_mean=4, txn_len_mean=9, seed=101,
+                          zipf_s=1.1)
+    ref = orc.dic(rows, 300, 0.005, 333)
+    db = dic.dic_load_db(rows, 300)
+    for rep in range(4):
+        assert_same(dic.dic_mine(db, 0.005, 333), ref, f"quest repeat {rep}")
+
+
 def test_repeat_calls_identical(dic):
     c = synth.config(1)
     db = dic.dic_load_db(c["rows"], 64)
