@@ -119,7 +119,8 @@ uint64_t pool_cap_for(uint32_t nL1, uint32_t mult)
 
 // Layout of a job's candidate pool buffer.
 struct PoolLayout {
-    size_t mask, hash, nz, supp, stop, state, promo, k, slots, live0, live1, newbox, omask, ocnt;
+    size_t mask, items, hash, nz, supp, stop, state, promo, k, slots, live0, live1, newbox, omask,
+        ocnt;
     size_t bytes;
     uint64_t hslots;
     PoolLayout(uint64_t cap, uint32_t W)
@@ -127,6 +128,7 @@ struct PoolLayout {
         hslots = next_pow2(2 * cap);
         Carver c;
         mask = c.take(cap * W * 8);
+        items = c.take(cap * KD * 2);
         hash = c.take(cap * 8);
         nz = c.take(cap * 8);
         supp = c.take(cap * 4);
@@ -321,7 +323,7 @@ bool Engine::running() const
 {
     for (ActiveJob *j : jobs_) {
         const JobState &s = st_[j->slot];
-        if (j->in_loop && !s.done && !s.overflow && s.k_next > 0)
+        if (j->in_loop && !s.done && !s.overflow && next_live(s, j->cap) > 0)
             return true;
     }
     return false;
@@ -540,6 +542,7 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         J.cap = a->cap;
         J.hmask = (uint32_t)(L.hslots - 1);
         J.pmask = (uint64_t *)(b + L.mask);
+        J.pitems = (uint16_t *)(b + L.items);
         J.phash = (unsigned long long *)(b + L.hash);
         J.pnz = (uint64_t *)(b + L.nz);
         J.psupp = (uint32_t *)(b + L.supp);
@@ -621,11 +624,13 @@ int Engine::advance(uint32_t max_steps)
 {
     if (!running())
         return DIC_OK;
+    // stops that the next live set certainly needs: the survivors' remaining
+    // stops, or a full pass for candidates created at the last stop
     uint32_t S = 1;
     for (ActiveJob *a : jobs_) {
         const JobState &s = st_[a->slot];
-        if (a->in_loop && !s.done && !s.overflow && s.k_next > 0)
-            S = std::max(S, s.max_rem);
+        if (a->in_loop && !s.done && !s.overflow && next_live(s, a->cap) > 0)
+            S = std::max(S, new_candidates(s, a->cap) ? a->stop_max : s.max_rem);
     }
     S = std::min(S, std::max(1u, max_steps));
     // graph replays run whole multiples of GRAPH_STEPS stops
@@ -770,7 +775,7 @@ int Engine::harvest(std::vector<std::pair<uint64_t, MineOutput>> &done)
             keep.push_back(a);
         } else if (s.overflow) {
             over.push_back(a);
-        } else if (s.done || s.k_next == 0) {
+        } else if (s.done || next_live(s, a->cap) == 0) {
             fin.push_back(a);
         } else {
             keep.push_back(a);

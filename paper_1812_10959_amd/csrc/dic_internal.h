@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <string>
@@ -66,12 +67,14 @@ struct JobState {
     uint32_t overflow;  // candidate pool capacity exceeded
     uint32_t stop;      // current block index 1..stop_max (0 before the first)
     uint32_t epoch;     // stops executed so far
+    // survivors appended to the next live list and boxes promoted at this
+    // stop: one 64-bit word so that a workgroup reserves both with one atomic
+    uint32_t k_next;
+    uint32_t n_new;
     uint32_t K;         // live candidates counted at this stop
-    uint32_t k_next;    // live candidates appended for the next stop
-    uint32_t n_new;     // boxes promoted at this stop
     uint32_t pool_n;    // itemsets in the pool (>= cap means overflow)
     uint32_t nL1;       // frequent items
-    uint32_t max_rem;   // stops the next live set certainly still needs
+    uint32_t max_rem;   // stops the surviving candidates certainly still need
     uint32_t parity;    // live list in use: live[parity]
     uint32_t first;     // block [first, last) of this stop
     uint32_t last;
@@ -86,9 +89,26 @@ struct JobState {
     uint32_t cpt;       // vertical: candidates per thread
     uint32_t cmode;     // vertical: 0 LDS tiles, 1 one wave per candidate
     uint32_t pool_base; // pool size when this stop began: entries at or above
-                        // it were created by this stop's candidate generation
+                        // it were created by this stop's candidate generation;
+                        // they follow the survivors in the next live list
     uint32_t pad[6];
 };
+static_assert(sizeof(JobState) == 128, "JobState is read back as 128-byte records");
+static_assert(offsetof(JobState, k_next) % 8 == 0, "k_next/n_new form one 64-bit word");
+
+// Candidates created since the stop began (they follow the survivors in the
+// next live list), and the size of that list.
+__host__ __device__ inline uint32_t new_candidates(const JobState &s, uint32_t cap)
+{
+    const uint32_t pn = s.pool_n < cap ? s.pool_n : cap;
+    return pn > s.pool_base ? pn - s.pool_base : 0u;
+}
+__host__ __device__ inline uint32_t next_live(const JobState &s, uint32_t cap)
+{
+    return s.k_next + new_candidates(s, cap);
+}
+
+constexpr int KD = 16;  // frequent-item indices stored per candidate (larger: decode the mask)
 
 // Read-only description of one mining run (device copy in a job table).
 struct Job {
@@ -102,6 +122,7 @@ struct Job {
     uint32_t cap;    // pool capacity (itemsets)
     uint32_t hmask;  // hash slots - 1
     uint64_t *pmask;  // cap * W
+    uint16_t *pitems; // cap * KD: frequent-item indices of each itemset (size <= KD)
     unsigned long long *phash;  // Zobrist hash of each itemset
     uint64_t *pnz;    // bitmap of nonzero words
     uint32_t *psupp, *pstop, *pstate, *ppromo, *pk;

@@ -192,6 +192,43 @@ __device__ uint32_t block_append(uint32_t *ctr, bool pred, uint32_t *sh)
     return pos;
 }
 
+// Two workgroup-aggregated appends with one 64-bit atomic: ctr points at a
+// pair of adjacent u32 counters (low word first); *pa / *pb receive the
+// slots of threads whose a / b is true.  sh holds 2 * (WG/64) + 2 words.
+__device__ void block_append2(uint32_t *ctr, bool a, bool b, uint32_t *sh, uint32_t *pa,
+                              uint32_t *pb)
+{
+    const unsigned long long ba = __ballot(a), bb = __ballot(b);
+    const uint32_t wave = threadIdx.x >> 6;
+    constexpr int NW = WG / 64;
+    if (lane_id() == 0) {
+        sh[wave] = (uint32_t)__popcll(ba);
+        sh[NW + wave] = (uint32_t)__popcll(bb);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t ta = 0, tb = 0;
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t ca = sh[w], cb = sh[NW + w];
+            sh[w] = ta;
+            sh[NW + w] = tb;
+            ta += ca;
+            tb += cb;
+        }
+        unsigned long long old = 0;
+        if (ta | tb)
+            old = atomicAdd((unsigned long long *)ctr,
+                            ((unsigned long long)tb << 32) | (unsigned long long)ta);
+        sh[2 * NW] = (uint32_t)old;
+        sh[2 * NW + 1] = (uint32_t)(old >> 32);
+    }
+    __syncthreads();
+    const unsigned long long lt = lanemask_lt();
+    *pa = sh[2 * NW] + sh[wave] + (uint32_t)__popcll(ba & lt);
+    *pb = sh[2 * NW + 1] + sh[NW + wave] + (uint32_t)__popcll(bb & lt);
+    __syncthreads();
+}
+
 // Workgroup sums of NS values and maximum of one more; results valid in
 // thread 0.  sh holds (NS + 1) * WG/64 words.
 template <int NS>
@@ -337,9 +374,10 @@ __global__ __launch_bounds__(WG) void k_l1(const Job *__restrict__ jobs)
         const uint32_t nL1 = carry;
         const uint64_t nC2 = (uint64_t)nL1 * (nL1 ? nL1 - 1u : 0u) / 2u;
         st->nL1 = nL1;
-        st->k_next = (uint32_t)nC2;
+        st->k_next = 0;  // no survivors: the next live list is the pairs alone
+        st->pool_base = 0;
         st->pool_n = (uint32_t)nC2;
-        st->max_rem = nC2 ? J->stop_max : 0u;
+        st->max_rem = 0;
     }
 }
 
@@ -371,6 +409,8 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
         J->phash[p] = h;
         J->pnz[p] = (1ull << (ia >> 6)) | (1ull << (ib >> 6));
         J->pk[p] = 2;
+        J->pitems[(uint64_t)p * KD] = (uint16_t)a;
+        J->pitems[(uint64_t)p * KD + 1] = (uint16_t)b;
         J->psupp[p] = 0;
         J->pstop[p] = 0;
         J->pstate[p] = ST_DASHED_CIRCLE;
@@ -405,13 +445,18 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
             const Job *J = jobs + j;
             JobState *st = J->st;
             if (!st->done && !st->overflow) {
-                if (st->k_next == 0) {
+                // the previous stop's MakeCandidates created pool entries
+                // [pool_base, pool_n); they follow its survivors in the list
+                const uint32_t gen = new_candidates(*st, J->cap);
+                if (st->epoch >= 1u && st->epoch - 1u < J->trace_cap)
+                    J->trace[st->epoch - 1u].generated = gen;
+                if (st->k_next + gen == 0) {
                     st->done = 1;
                     st->K = 0;
                 } else {
-                    K = st->k_next;
+                    K = st->k_next + gen;
                     st->K = K;
-                    st->pool_base = st->pool_n;
+                    st->pool_base = st->pool_n < J->cap ? st->pool_n : J->cap;
                     st->k_next = 0;
                     st->n_new = 0;
                     st->parity ^= 1u;
@@ -702,20 +747,39 @@ __global__ __launch_bounds__(WG) void k_count_vert(const Job *__restrict__ jobs,
 #pragma unroll
                 for (int w = 0; w < VT_MAXW; ++w)
                     acc[w] = ~0ull;
-                uint64_t nzw = J->pnz[p];
-                const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
-                while (nzw) {
-                    const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
-                    nzw &= nzw - 1;
-                    uint64_t bits = cm[wd];
-                    while (bits) {
-                        const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
-                        bits &= bits - 1;
-                        const uint64_t *row = tile + J->l1pos[item] * ts;
+                const uint32_t k = J->pk[p];
+                if (k <= (uint32_t)KD) {
+                    // the candidate's frequent-item indices, 16 x u16
+                    const uint4 *ip = (const uint4 *)(J->pitems + (uint64_t)p * KD);
+                    const uint4 h0 = ip[0], h1 = ip[1];
+                    const uint32_t pk32[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
 #pragma unroll
-                        for (int w = 0; w < VT_MAXW; ++w)
-                            if ((uint32_t)w < nwt)
-                                acc[w] &= row[w];
+                    for (int t = 0; t < KD; ++t) {
+                        if ((uint32_t)t < k) {
+                            const uint32_t idx = (pk32[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
+                            const uint64_t *row = tile + idx * ts;
+#pragma unroll
+                            for (int w = 0; w < VT_MAXW; ++w)
+                                if ((uint32_t)w < nwt)
+                                    acc[w] &= row[w];
+                        }
+                    }
+                } else {
+                    uint64_t nzw = J->pnz[p];
+                    const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+                    while (nzw) {
+                        const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
+                        nzw &= nzw - 1;
+                        uint64_t bits = cm[wd];
+                        while (bits) {
+                            const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
+                            bits &= bits - 1;
+                            const uint64_t *row = tile + J->l1pos[item] * ts;
+#pragma unroll
+                            for (int w = 0; w < VT_MAXW; ++w)
+                                if ((uint32_t)w < nwt)
+                                    acc[w] &= row[w];
+                        }
                     }
                 }
                 uint32_t sum = 0;
@@ -741,7 +805,7 @@ __global__ __launch_bounds__(WG) void k_count_vert(const Job *__restrict__ jobs,
 __global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
                                                  const Plan *__restrict__ plan)
 {
-    __shared__ uint32_t sh_app[WG / 64 + 1];
+    __shared__ uint32_t sh_app[2 * (WG / 64) + 2];
     __shared__ uint32_t sh_red[6 * (WG / 64)];
     const uint32_t total = plan->pre_epi[plan->njobs];
     for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
@@ -755,13 +819,15 @@ __global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
         if (valid) {
             p = (st->parity ? J->live1 : J->live0)[c];
             items = J->pk[p];
-            // nonzero 32-bit words of this candidate: its AND work per row
-            uint64_t nzw = J->pnz[p];
-            const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
-            while (nzw) {
-                const uint64_t v = cm[__builtin_ctzll(nzw)];
-                nzw &= nzw - 1;
-                words += ((uint32_t)v != 0u) + ((uint32_t)(v >> 32) != 0u);
+            if (J->layout == LAYOUT_ROWS) {
+                // nonzero 32-bit words of this candidate: its AND work per row
+                uint64_t nzw = J->pnz[p];
+                const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+                while (nzw) {
+                    const uint64_t v = cm[__builtin_ctzll(nzw)];
+                    nzw &= nzw - 1;
+                    words += ((uint32_t)v != 0u) + ((uint32_t)(v >> 32) != 0u);
+                }
             }
             sc = J->pstop[p] + 1u;
             J->pstop[p] = sc;
@@ -789,10 +855,10 @@ __global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
             J->pstate[p] = state;
         }
         uint32_t *next = st->parity ? J->live0 : J->live1;
-        const uint32_t pos = block_append(&st->k_next, keep, sh_app);
+        uint32_t pos, npos;
+        block_append2(&st->k_next, keep, promoted, sh_app, &pos, &npos);
         if (keep)
             next[pos] = p;
-        const uint32_t npos = block_append(&st->n_new, promoted, sh_app);
         if (promoted)
             J->newbox[npos] = p;
         uint32_t v[6] = {words, items, promoted ? 1u : 0u, pruned ? 1u : 0u, solid ? 1u : 0u,
@@ -830,7 +896,6 @@ __global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
     __shared__ unsigned long long pre[MAX_JOBS + 1];
     __shared__ unsigned long long sh_scan[WG];
     __shared__ uint32_t sh_app[WG / 64 + 1];
-    __shared__ uint32_t sh_red[2 * (WG / 64)];
     const uint32_t njobs = plan->njobs;
     unsigned long long carry = 0;
     if (threadIdx.x == 0)
@@ -867,9 +932,31 @@ __global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
             const uint32_t q = (uint32_t)(x / nL1), a = (uint32_t)(x % nL1);
             p = J->newbox[q];
             i = J->l1[a];
-            const uint64_t *S = J->pmask + (uint64_t)p * W;
-            if (!((S[i >> 6] >> (i & 63u)) & 1ull)) {
-                k = J->pk[p];
+            k = J->pk[p];
+            if (k == 2u) {
+                // S = {u0, u1} by frequent-item index; C's other maximal subsets
+                // {u0, a} and {u1, a} are pair candidates found at their index
+                const uint32_t h = *(const uint32_t *)(J->pitems + (uint64_t)p * KD);
+                const uint32_t u[2] = {h & 0xFFFFu, h >> 16};
+                gen = a != u[0] && a != u[1];
+                for (int t = 0; t < 2 && gen; ++t) {
+                    uint32_t lo = u[t], hi = a;
+                    if (lo > hi) {
+                        lo = a;
+                        hi = u[t];
+                    }
+                    const uint32_t sub = lo * nL1 - lo * (lo + 1u) / 2u + (hi - lo - 1u);
+                    const uint32_t s2 = J->pstate[sub];
+                    if (s2 != ST_DASHED_BOX && s2 != ST_SOLID_BOX)
+                        gen = false;
+                    else if (u[1 - t] > a && J->ppromo[sub] == st->epoch)
+                        gen = false;  // the subset dropping the larger item generates C
+                                      // (frequent items are in ascending item order)
+                }
+                if (gen)
+                    hC = J->phash[p] ^ z[i];
+            } else if (!((J->pmask[(uint64_t)p * W + (i >> 6)] >> (i & 63u)) & 1ull)) {
+                const uint64_t *S = J->pmask + (uint64_t)p * W;
                 hC = J->phash[p] ^ z[i];
                 gen = true;
                 uint64_t nzw = J->pnz[p];
@@ -880,31 +967,8 @@ __global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
                     while (gen && bits) {
                         const uint32_t xj = wd * 64u + (uint32_t)__builtin_ctzll(bits);
                         bits &= bits - 1;
-                        uint32_t sub;
-                        if (k == 2u) {
-                            // the other item y of S: C \ {xj} = {y, i} is the pair
-                            // candidate at its index among pairs of frequent items
-                            // (pool slots 0 .. nC2-1, in k_init_pairs' order)
-                            uint32_t y = 0;
-                            for (uint32_t w = 0; w < W; ++w) {
-                                uint64_t o = S[w];
-                                if (w == (xj >> 6))
-                                    o &= ~(1ull << (xj & 63u));
-                                if (o) {
-                                    y = w * 64u + (uint32_t)__builtin_ctzll(o);
-                                    break;
-                                }
-                            }
-                            uint32_t u = J->l1pos[y], v = J->l1pos[i];
-                            if (u > v) {
-                                const uint32_t t = u;
-                                u = v;
-                                v = t;
-                            }
-                            sub = u * nL1 - u * (u + 1u) / 2u + (v - u - 1u);
-                        } else {
-                            sub = hash_find_sub(J, hC ^ z[xj], k, S, i, xj, st->pool_base);
-                        }
+                        const uint32_t sub =
+                            hash_find_sub(J, hC ^ z[xj], k, S, i, xj, st->pool_base);
                         if (sub == NONE) {
                             gen = false;
                         } else {
@@ -918,6 +982,10 @@ __global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
                 }
             }
         }
+        // New entries are pool slots [pool_base, pool_n); in the next live
+        // list they follow the survivors, at k_next + (slot - pool_base).
+        // Lookups in this launch never read them (see hash_find_sub), so
+        // no fence is needed before publishing them in the hash table.
         const uint32_t np = block_append(&st->pool_n, gen, sh_app);
         const bool stored = gen && np < J->cap;
         if (gen && !stored)
@@ -935,20 +1003,16 @@ __global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
             J->pstop[np] = 0;
             J->pstate[np] = ST_DASHED_CIRCLE;
             J->ppromo[np] = NO_EPOCH;
-            __threadfence();
+            if (k + 1u <= (uint32_t)KD) {
+                const uint16_t *si = J->pitems + (uint64_t)p * KD;
+                uint16_t *ci = J->pitems + (uint64_t)np * KD;
+                for (uint32_t t = 0; t < k; ++t)
+                    ci[t] = si[t];
+                ci[k] = (uint16_t)(x % nL1);  // the frequent-item index of i
+            }
             hash_insert(J, hC, k + 1u, np);
-        }
-        uint32_t *next = st->parity ? J->live0 : J->live1;
-        const uint32_t pos = block_append(&st->k_next, stored, sh_app);
-        if (stored)
-            next[pos] = np;
-        uint32_t v[2] = {stored ? 1u : 0u, stored ? J->stop_max : 0u};
-        block_reduce<1>(v, sh_red);
-        if (threadIdx.x == 0 && v[0]) {
-            dic_stop_trace *tr = trace_of(J, st);
-            if (tr)
-                atomicAdd(&tr->generated, v[0]);
-            atomicMax(&st->max_rem, v[1]);
+            uint32_t *next = st->parity ? J->live0 : J->live1;
+            next[st->k_next + (np - st->pool_base)] = np;
         }
     }
 }

@@ -153,8 +153,17 @@ def test_profile_option_times_count_kernel(dic):
     assert 0 < r.stats["count_ms"] < r.stats["mine_ms"]
     r2 = dic.dic_mine(db, c["minsup"], c["M"])
     assert r2.stats["count_ms"] == 0 and _same(r, r2)
-    # per-stop work counter: every live candidate has at least one nonzero word
-    assert (r.words >= r.trace[:, 2]).all()
+    # per-stop work counters: every live candidate has at least two items, and
+    # with row bitmaps at least one nonzero mask word
+    assert (r.items >= 2 * r.trace[:, 2]).all()
+    dic.dic_set_option("layout", 0)
+    dic.dic_set_option("profile", 1)
+    try:
+        rr = dic.dic_mine(db, c["minsup"], c["M"])
+    finally:
+        dic.dic_set_option("profile", 0)
+        dic.dic_set_option("layout", 1)
+    assert (rr.words >= rr.trace[:, 2]).all() and _same(rr, r)
     with pytest.raises(dic.DicError):
         dic.dic_set_option("no-such-option", 1)
 
