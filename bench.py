@@ -105,12 +105,7 @@ def roofline_entry(byt, ops, ms, launches):
     }
 
 
-def headline(dic, args):
-    import synth
-    log("generating the sparse workload (n=1,000,000, m=1,000) ...")
-    t0 = time.time()
-    c = synth.config(2)
-    log(f"  generated in {time.time() - t0:.1f}s")
+def headline(dic, args, c):
     rows, m = c["rows"], c["m"]
     n, W = rows.shape
     db = dic.dic_load_db(rows, m)
@@ -193,11 +188,9 @@ def _cpu_model():
     return "unknown"
 
 
-def other_configs(dic):
-    import synth
+def other_configs(dic, inputs):
     out = {}
-    for idx in (1, 3):
-        c = synth.config(idx)
+    for c in inputs:
         rows, m = c["rows"], c["m"]
         n = rows.shape[0]
         db = dic.dic_load_db(rows, m)
@@ -219,18 +212,8 @@ def other_configs(dic):
     return out
 
 
-def _gen_batch(args_):
-    import synth
-    count, seed = args_
-    return synth.batch_config(count, seed=seed)
-
-
-def batch_vs_plain(dic, count):
-    import synth
-    log(f"generating {count} databases ...")
-    t0 = time.time()
-    dbs_spec = synth.batch_config(count)
-    log(f"  generated in {time.time() - t0:.1f}s")
+def batch_vs_plain(dic, dbs_spec):
+    count = len(dbs_spec)
     dbs = [dic.dic_load_db(d["rows"], d["m"]) for d in dbs_spec]
     ms = [d["minsup"] for d in dbs_spec]
     Ms = [d["M"] for d in dbs_spec]
@@ -259,24 +242,12 @@ def batch_vs_plain(dic, count):
     return out
 
 
-def serving(dic, seconds, rate, big_c2=None):
+def serving(dic, seconds, rate, c2, c3, small):
     import synth
     log(f"serving: Poisson {rate}/s for {seconds}s over mixed databases ...")
-    pool = []
-    if big_c2 is not None:
-        c2 = dict(big_c2)
-        c2["minsup_range"] = (0.005, 0.05)
-        pool.append(c2)
-    else:
-        c2 = synth.config(2)
-        c2["minsup_range"] = (0.005, 0.05)
-        pool.append(c2)
-    c3 = synth.config(3)
-    c3["minsup_range"] = (0.25, 0.30)
-    pool.append(c3)
-    for d in synth.batch_config(16, seed=synth.CONFIG_SEED_BASE + 5):
-        d["minsup_range"] = (0.01, 0.05)
-        pool.append(d)
+    pool = [dict(c2, minsup_range=(0.005, 0.05)), dict(c3, minsup_range=(0.25, 0.30))]
+    for d in small:
+        pool.append(dict(d, minsup_range=(0.01, 0.05)))
     dbs = [dic.dic_load_db(p["rows"], p["m"]) for p in pool]
     stream = synth.serve_stream([p["rows"].shape[0] for p in pool], rate=rate,
                                 duration_s=seconds, minsup_ranges=[p["minsup_range"] for p in pool])
@@ -319,11 +290,22 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the mining path "
               "is single-GPU in this build", file=sys.stderr)
         sys.exit(2)
+    # Every input is generated before the GPU library is loaded (the batch in
+    # a pool of spawned processes), so no worker is started from a process
+    # that holds a GPU context.
+    import synth
+    t0 = time.time()
+    c = synth.config(2)
+    others = [] if args.only_headline else [synth.config(1), synth.config(3)]
+    batch = ([] if args.only_headline or args.no_batch else
+             synth.batch_config(args.batch_count, workers=16))
+    small = ([] if args.only_headline or args.no_serve else
+             synth.batch_config(16, seed=synth.CONFIG_SEED_BASE + 5, workers=16))
+    log(f"inputs generated in {time.time() - t0:.1f}s")
     import paper_1812_10959_amd as dic
     import torch
     assert torch.cuda.is_available(), "no GPU visible"
-    h = headline(dic, args)
-    c = h["workload"]
+    h = headline(dic, args, c)
     line = {
         "metric": METRIC, "value": round(h["value"], 3), "unit": "G subset-tests/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -341,11 +323,12 @@ def main():
         if not args.no_cpu:
             line["cpu_baseline"] = cpu_baseline(c, h["rows"], args.cpu_rows)
         log("other single-database workloads ...")
-        line["workloads"] = other_configs(dic)
+        line["workloads"] = other_configs(dic, others)
         if not args.no_batch:
-            line["batched_vs_plain"] = batch_vs_plain(dic, args.batch_count)
+            line["batched_vs_plain"] = batch_vs_plain(dic, batch)
         if not args.no_serve:
-            line["serving"] = serving(dic, args.serve_seconds, args.serve_rate, big_c2=c)
+            line["serving"] = serving(dic, args.serve_seconds, args.serve_rate, c, others[1],
+                                      small)
     print(json.dumps(line), flush=True)
 
 

@@ -196,12 +196,13 @@ def config(index: int, *, n: int | None = None):
 def batch_config(count: int = 256, *, seed: int = CONFIG_SEED_BASE + 4,
                  n_lo: int = 1_000, n_hi: int = 200_000, widths=(64, 256, 1024),
                  len_lo: float = 8.0, len_hi: float = 20.0,
-                 minsup_lo: float = 0.01, minsup_hi: float = 0.05):
+                 minsup_lo: float = 0.01, minsup_hi: float = 0.05, workers: int = 0):
     """Many independent Quest-style databases of uneven size and width.
 
     Per database: n ~ U{n_lo..n_hi}, m uniform from ``widths``, transaction
     length mean ~ U[len_lo, len_hi], 2*m latent patterns of mean length 4,
     minsup ~ U[minsup_lo, minsup_hi], M = max(1, n // 20).
+    ``workers`` > 1 generates the databases in that many processes.
     Returns a list of dicts (rows, m, minsup, M, name, meta).
     """
     rng = np.random.default_rng(seed)
@@ -210,14 +211,28 @@ def batch_config(count: int = 256, *, seed: int = CONFIG_SEED_BASE + 4,
     lens = rng.uniform(len_lo, len_hi, count)
     mins = rng.uniform(minsup_lo, minsup_hi, count)
     subseeds = rng.integers(0, 2**31 - 1, count)
+    args = [(int(ns[i]), int(ms[i]), float(lens[i]), int(subseeds[i])) for i in range(count)]
+    if workers > 1 and count > 1:
+        # separate interpreters (spawned, never forked) so that a caller that
+        # already holds a GPU context is not copied; same draws as serially
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        with cf.ProcessPoolExecutor(max_workers=min(workers, count),
+                                    mp_context=mp.get_context("spawn")) as ex:
+            made = list(ex.map(_batch_one, args, chunksize=4))
+    else:
+        made = [_batch_one(a) for a in args]
     out = []
-    for i in range(count):
-        n, m = int(ns[i]), int(ms[i])
-        rows, meta = quest(n, m, n_patterns=2 * m, pat_len_mean=4, txn_len_mean=float(lens[i]),
-                           seed=int(subseeds[i]))
+    for i, (rows, meta) in enumerate(made):
+        n, m = args[i][0], args[i][1]
         out.append(dict(name=f"batch{i}_n{n}_m{m}", rows=rows, m=m, minsup=float(mins[i]),
                         M=max(1, n // 20), meta=meta))
     return out
+
+
+def _batch_one(a):
+    n, m, ln, sub = a
+    return quest(n, m, n_patterns=2 * m, pat_len_mean=4, txn_len_mean=ln, seed=sub)
 
 
 def serve_pool(*, seed: int = CONFIG_SEED_BASE + 5, n_small: int = 16, big_n_scale: float = 1.0):
