@@ -53,6 +53,11 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--cpu-rows", type=int, default=40_000)
+    ap.add_argument("--no-layouts", action="store_true",
+                    help="skip the profiled count-kernel passes (for counter runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also copy the headline rows device to device once (a copy of known "
+                         "size for scaling memory counters)")
     return ap.parse_args()
 
 
@@ -130,11 +135,16 @@ def headline(dic, args, c):
     log(f"  timed {args.steps} steps: {dt / args.steps * 1e3:.2f} ms/step, {value:.1f} G tests/s")
     out = {"value": value, "ms_per_step": dt / args.steps * 1e3, "stats": st,
            "workload": c, "db": db, "rows": rows}
+    if args.calibrate_copy:
+        t = torch.from_numpy(rows.view(np.int64)).cuda()
+        torch.cuda.synchronize()
+        dic.dic_load_db(t, m)  # one device-to-device copy of n*W*8 bytes
+        log(f"  calibration copy: {rows.nbytes} bytes device to device")
     # Count-kernel roofline: a second timed region with HIP events around
     # every CountSupport launch (profiled runs launch directly, not as graphs).
     n_freq_items = int((np.bitwise_count(res[0].masks).sum(axis=1) == 1).sum())
     layouts = {}
-    for layout in (1, 0):
+    for layout in (() if args.no_layouts else (1, 0)):
         dic.dic_set_option("layout", layout)
         dic.dic_set_option("profile", 1)
         prof = []
@@ -157,7 +167,7 @@ def headline(dic, args, c):
             f" {entry['achieved']:.3f} Tops/s ({100 * entry['frac']:.2f}% ALU), "
             f"{entry['hbm']['achieved']:.1f} GB/s, mine {pdt * 1e3:.1f} ms profiled")
     dic.dic_set_option("layout", 1)
-    out["roofline"] = layouts["item_bitsets"]
+    out["roofline"] = layouts.get("item_bitsets")
     out["layouts"] = layouts
     return out
 

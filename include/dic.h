@@ -208,6 +208,13 @@ DIC_API int dic_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(vo
  *              word).  Both give identical results.
  *   "graphs"   1 (default): stops run as replays of a captured HIP graph of
  *              a few stops on the engine's own stream; 0: direct launches.
+ *   Count planning (results never depend on them; chosen by the autotuner):
+ *   "vt_target"     workgroups aimed at per job per stop (bitsets), 64..65536
+ *   "vt_wave_k"     below this many live candidates one wave counts each
+ *                   candidate over the whole block (bitsets), 0..2^30
+ *   "vt_tile_words" 64-row words per LDS tile at most (bitsets), 1..16
+ *   "count_grid"    workgroups launched for the count kernels, 64..65536
+ *   "count_target"  work items aimed at per job per stop (rows), 64..65536
  */
 DIC_API int dic_set_option(const char *name, int64_t value);
 

@@ -374,6 +374,18 @@ def dic_set_option(name: str, value: int) -> None:
     _check(_lib.dic_set_option(name.encode(), int(value)), "dic_set_option")
 
 
+def _apply_tuning():
+    """Apply the autotuner's saved choice (tuning.json beside this file)."""
+    path = os.path.join(_HERE, "tuning.json")
+    if os.path.exists(path):
+        import json
+        with open(path) as f:
+            for k, v in json.load(f).get("settings", {}).items():
+                _lib.dic_set_option(k.encode(), int(v))
+
+
+_apply_tuning()
+
 __all__ = [n for n in ABI_FUNCTIONS] + [
     "Db", "Result", "Server", "DicError", "use_torch", "TRACE_FIELDS", "LIB_PATH",
 ]

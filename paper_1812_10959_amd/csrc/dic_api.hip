@@ -180,6 +180,8 @@ int dic_set_option(const char *name, int64_t value)
         set_count_layout(value ? LAYOUT_VERTICAL : LAYOUT_ROWS);
         return DIC_OK;
     }
+    if (name && set_knob(name, value) == DIC_OK)
+        return DIC_OK;
     set_error(std::string("dic_set_option: unknown option or value ") + (name ? name : "(null)"));
     return DIC_E_INVAL;
 }

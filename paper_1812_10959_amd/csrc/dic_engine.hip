@@ -149,6 +149,8 @@ struct PoolLayout {
 std::atomic<int> g_profile{0};
 std::atomic<uint32_t> g_layout{LAYOUT_VERTICAL};
 std::atomic<bool> g_graphs{true};
+std::mutex g_knob_mu;
+Knobs g_knobs;
 constexpr uint32_t GRAPH_STEPS = 8;  // stops per captured step graph
 
 }  // namespace
@@ -157,6 +159,31 @@ bool profiling() { return g_profile.load() != 0; }
 void set_profiling(int on) { g_profile.store(on); }
 uint32_t count_layout() { return g_layout.load(); }
 bool use_graphs() { return g_graphs.load(); }
+
+Knobs knobs()
+{
+    std::lock_guard<std::mutex> g(g_knob_mu);
+    return g_knobs;
+}
+
+int set_knob(const char *name, int64_t v)
+{
+    std::lock_guard<std::mutex> g(g_knob_mu);
+    const std::string n(name);
+    if (n == "vt_target" && v >= 64 && v <= 65536)
+        g_knobs.vt_target = (uint32_t)v;
+    else if (n == "vt_wave_k" && v >= 0 && v <= (1 << 30))
+        g_knobs.vt_wave_k = (uint32_t)v;
+    else if (n == "vt_tile_words" && v >= 1 && v <= VT_MAXW)
+        g_knobs.vt_tile_words = (uint32_t)v;
+    else if (n == "count_grid" && v >= 64 && v <= 65536)
+        g_knobs.count_grid = (uint32_t)v;
+    else if (n == "count_target" && v >= 64 && v <= 65536)
+        g_knobs.count_target = (uint32_t)v;
+    else
+        return DIC_E_INVAL;
+    return DIC_OK;
+}
 void set_use_graphs(bool on) { g_graphs.store(on); }
 void set_count_layout(uint32_t layout) { g_layout.store(layout); }
 
@@ -286,10 +313,11 @@ int Engine::launch_steps(uint32_t S, bool rows, bool vert, bool prof, double *co
         }
         return DIC_OK;
     };
+    const uint32_t grid = knobs().count_grid;
     // Events recorded inside a captured graph cannot be timed: profile directly.
     if (!use_graphs() || !own_stream_ || prof) {
         for (uint32_t k = 0; k < S; ++k)
-            launch_step((const Job *)table_, d_plan_step_, s_, rows, vert,
+            launch_step((const Job *)table_, d_plan_step_, s_, rows, vert, grid,
                         prof ? events_[2 * k] : nullptr, prof ? events_[2 * k + 1] : nullptr);
         HIP_TRY(hipGetLastError());
         *steps_done = S;
@@ -300,11 +328,16 @@ int Engine::launch_steps(uint32_t S, bool rows, bool vert, bool prof, double *co
         return DIC_OK;
     }
     hipGraphExec_t &g = graphs_[rows][vert];
+    if (g && graph_grid_[rows][vert] != grid) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
     if (!g) {
+        graph_grid_[rows][vert] = grid;
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
         for (uint32_t k = 0; k < GRAPH_STEPS; ++k)
-            launch_step((const Job *)table_, d_plan_step_, s_, rows, vert);
+            launch_step((const Job *)table_, d_plan_step_, s_, rows, vert, grid);
         const hipError_t le = hipGetLastError();
         HIP_TRY(hipStreamEndCapture(s_, &graph));
         HIP_TRY(le);
@@ -576,8 +609,21 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
     return DIC_OK;
 }
 
+bool Engine::knobs_changed() const
+{
+    const Knobs k = knobs();
+    return k.vt_target != plan_step_.vt_target || k.vt_wave_k != plan_step_.vt_wave_k ||
+           k.vt_tile_words != plan_step_.vt_tile_words ||
+           k.count_target != plan_step_.count_target;
+}
+
 int Engine::upload_table()
 {
+    const Knobs k = knobs();
+    plan_step_.vt_target = k.vt_target;
+    plan_step_.vt_wave_k = k.vt_wave_k;
+    plan_step_.vt_tile_words = k.vt_tile_words;
+    plan_step_.count_target = k.count_target;
     table_host_.clear();
     for (ActiveJob *a : jobs_)
         if (a->in_loop)
@@ -641,7 +687,7 @@ int Engine::advance(uint32_t max_steps)
     int rc = ensure_trace(S_run);
     if (rc)
         return rc;
-    if (table_dirty_ && (rc = upload_table()))
+    if ((table_dirty_ || knobs_changed()) && (rc = upload_table()))
         return rc;
     bool any_rows = false, any_vert = false;
     for (const Job &J : table_host_) {

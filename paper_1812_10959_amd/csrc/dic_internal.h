@@ -43,12 +43,25 @@ enum : uint32_t { LAYOUT_ROWS = 0, LAYOUT_VERTICAL = 1 };
 // Words per frequent item in a vertical tile (the tile holds every frequent
 // item's bitset over those words) and the odd row stride that spreads the
 // items' words over the LDS banks.
-__host__ __device__ inline uint32_t vert_tile_words(uint32_t nL1)
+__host__ __device__ inline uint32_t vert_tile_words(uint32_t nL1, uint32_t max_words)
 {
     uint32_t t = nL1 ? (uint32_t)VT_WORDS / nL1 : (uint32_t)VT_MAXW + 1u;
     t = t > 1u ? t - 1u : 1u;
-    return t > (uint32_t)VT_MAXW ? (uint32_t)VT_MAXW : t;
+    const uint32_t cap = max_words < (uint32_t)VT_MAXW ? max_words : (uint32_t)VT_MAXW;
+    return t > cap ? cap : t;
 }
+
+// Tuning knobs of the count planning and launch (set by dic_set_option or
+// the autotuner; every setting gives the same results).
+struct Knobs {
+    uint32_t vt_target = 768;      // bitset count: workgroups aimed at per job per stop
+    uint32_t vt_wave_k = 2048;     // bitset count: one wave per candidate below this
+    uint32_t vt_tile_words = 16;   // bitset count: 64-row words per LDS tile at most
+    uint32_t count_grid = 2048;    // workgroups launched for the count kernels
+    uint32_t count_target = 2048;  // row-bitmap count: work items aimed at per job
+};
+Knobs knobs();
+int set_knob(const char *name, int64_t value);
 __host__ __device__ inline uint32_t vert_tile_stride(uint32_t tw) { return tw | 1u; }
 
 __host__ __device__ inline uint32_t row_tile_rows(uint32_t W)
@@ -150,6 +163,7 @@ struct Plan {
     unsigned long long *pre_cg;
     unsigned long long *pre_fp;  // first pass row chunks
     const unsigned long long *zobrist;  // MAX_ITEMS random words
+    uint32_t vt_target, vt_wave_k, vt_tile_words, count_target;  // see Knobs
 };
 
 // kernel launchers (dic_kernels.hip)
@@ -164,7 +178,7 @@ void launch_init_pairs(const Job *jobs, const Plan *plan, unsigned long long tot
 // One stop for every job in the table; when given, the two events bracket
 // the CountSupport launch on stream s.
 void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, bool rows, bool vert,
-                 hipEvent_t before = nullptr, hipEvent_t after = nullptr);
+                 uint32_t count_grid, hipEvent_t before = nullptr, hipEvent_t after = nullptr);
 void launch_collect(const Job *jobs, const Plan *plan, uint32_t njobs, hipStream_t s);
 void launch_pack_lists(const uint32_t *items, const uint64_t *offsets, uint64_t n, uint32_t W,
                        uint64_t *rows, hipStream_t s);
@@ -246,6 +260,7 @@ class Engine {
     int add_impl(std::vector<ActiveJob *> &fresh);
     int read_states();
     int upload_table();
+    bool knobs_changed() const;
     int ensure_trace(uint32_t steps);
     int collect(std::vector<ActiveJob *> &fin, std::vector<std::pair<uint64_t, MineOutput>> &out);
     int launch_steps(uint32_t S, bool rows, bool vert, bool prof, double *count_ms,
@@ -254,6 +269,7 @@ class Engine {
     hipStream_t s_;
     bool own_stream_ = false;
     hipGraphExec_t graphs_[2][2] = {};  // [rows][vert]
+    uint32_t graph_grid_[2][2] = {};    // count grid each graph was captured with
     uint32_t max_jobs_;
     std::vector<ActiveJob *> jobs_;
     std::vector<int> free_slots_;

@@ -22,11 +22,7 @@ namespace {
 
 constexpr uint32_t FP_ROWS = 4096;       // first pass rows per workgroup item
 constexpr uint32_t FPV_WORDS = 4096;     // first pass (bitsets): words per work item
-constexpr uint32_t COUNT_TARGET = 2048;  // count work items aimed at per job
-constexpr uint32_t VT_TARGET = 768;      // bitset count: workgroups aimed at per job
 constexpr int VT_CPT = 8;                // bitset count: candidates per thread at most
-constexpr uint32_t VT_WAVE_K = 2048;     // bitset count: below this many live candidates
-                                         // each wave counts one candidate over the block
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
@@ -482,7 +478,7 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
                         t.reserved = 0;
                         J->trace[st->epoch - 1u] = t;
                     }
-                    if (J->layout == LAYOUT_VERTICAL && K < VT_WAVE_K) {
+                    if (J->layout == LAYOUT_VERTICAL && K < plan->vt_wave_k) {
                         // few candidates: one wave per candidate, no tile
                         st->fw = (uint32_t)(first >> 6);
                         st->lw = (uint32_t)((last - 1u) >> 6);
@@ -493,16 +489,17 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
                         st->cmode = 0;
                         const uint32_t fw = (uint32_t)(first >> 6);
                         const uint32_t lw = (uint32_t)((last - 1u) >> 6);
-                        const uint32_t tw = vert_tile_words(st->nL1);
+                        const uint32_t tw = vert_tile_words(st->nL1, plan->vt_tile_words);
                         const uint32_t ntile = (lw - fw + tw) / tw;
                         // candidates per thread: spend the parallelism beyond
-                        // VT_TARGET workgroups on fewer tile loads
-                        uint64_t cpt = ((uint64_t)K * ntile + (uint64_t)WG * VT_TARGET - 1u) /
-                                       ((uint64_t)WG * VT_TARGET);
+                        // vt_target workgroups on fewer tile loads
+                        const uint64_t vt_target = plan->vt_target;
+                        uint64_t cpt = ((uint64_t)K * ntile + (uint64_t)WG * vt_target - 1u) /
+                                       ((uint64_t)WG * vt_target);
                         cpt = cpt < 1u ? 1u : (cpt > (uint64_t)VT_CPT ? (uint64_t)VT_CPT : cpt);
                         st->cpt = (uint32_t)cpt;
                         const uint32_t n_cg = (K + WG * (uint32_t)cpt - 1u) / (WG * (uint32_t)cpt);
-                        uint32_t want = (VT_TARGET + n_cg - 1u) / n_cg;
+                        uint32_t want = ((uint32_t)vt_target + n_cg - 1u) / n_cg;
                         want = want < 1u ? 1u : (want > ntile ? ntile : want);
                         const uint32_t tpc = (ntile + want - 1u) / want;
                         st->fw = fw;
@@ -516,7 +513,7 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
                     const uint32_t rt = row_tile_rows(J->W);
                     const uint32_t n_ct = (K + CAND_PER_WG - 1u) / CAND_PER_WG;
                     const uint32_t tiles = (rows + rt - 1u) / rt;
-                    uint32_t want = (COUNT_TARGET + n_ct - 1u) / n_ct;
+                    uint32_t want = (plan->count_target + n_ct - 1u) / n_ct;
                     if (want < 1u)
                         want = 1u;
                     if (want > tiles)
@@ -1067,7 +1064,6 @@ __global__ __launch_bounds__(WG) void k_check_padding(const uint64_t *__restrict
 // launchers
 // ---------------------------------------------------------------------------
 namespace {
-constexpr uint32_t GRID_COUNT = 2048;
 constexpr uint32_t GRID_EPI = 512;
 constexpr uint32_t GRID_CG = 1024;
 
@@ -1113,16 +1109,16 @@ void launch_init_pairs(const Job *jobs, const Plan *plan, unsigned long long tot
 }
 
 void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, bool rows, bool vert,
-                 hipEvent_t before, hipEvent_t after)
+                 uint32_t count_grid, hipEvent_t before, hipEvent_t after)
 {
     Plan *pl = const_cast<Plan *>(plan);
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(WG), 0, s, jobs, pl);
     if (before)
         (void)hipEventRecord(before, s);
     if (rows)
-        hipLaunchKernelGGL(k_count, dim3(GRID_COUNT), dim3(WG), 0, s, jobs, plan);
+        hipLaunchKernelGGL(k_count, dim3(count_grid), dim3(WG), 0, s, jobs, plan);
     if (vert)
-        hipLaunchKernelGGL(k_count_vert, dim3(GRID_COUNT), dim3(WG), 0, s, jobs, plan);
+        hipLaunchKernelGGL(k_count_vert, dim3(count_grid), dim3(WG), 0, s, jobs, plan);
     if (after)
         (void)hipEventRecord(after, s);
     hipLaunchKernelGGL(k_epilogue, dim3(GRID_EPI), dim3(WG), 0, s, jobs, plan);

@@ -187,3 +187,37 @@ def test_concurrent_host_threads(dic):
         t.join()
     for i in range(4):
         assert _same(out[i], items[i][1])
+
+
+def test_planning_knobs_do_not_change_results(dic, orc):
+    """Every tuning knob setting gives the oracle's result (tile and wave modes,
+    tile shapes, grid sizes, row-bitmap work split)."""
+    rows, _ = synth.quest(6000, 200, n_patterns=150, pat_len_mean=4, txn_len_mean=9, seed=77,
+                          zipf_s=1.1)
+    ref = orc.dic(rows, 200, 0.006, 700)
+    db = dic.dic_load_db(rows, 200)
+    base = {"vt_target": 768, "vt_wave_k": 2048, "vt_tile_words": 16, "count_grid": 2048,
+            "count_target": 2048}
+    variants = [dict(vt_wave_k=0), dict(vt_wave_k=1 << 20), dict(vt_tile_words=1),
+                dict(vt_tile_words=5), dict(vt_target=64), dict(vt_target=8192),
+                dict(count_grid=64), dict(count_grid=5000)]
+    try:
+        for v in variants:
+            for k, x in {**base, **v}.items():
+                dic.dic_set_option(k, x)
+            g = dic.dic_mine(db, 0.006, 700)
+            assert np.array_equal(g.masks, ref.masks) and np.array_equal(g.counts, ref.counts), v
+            assert np.array_equal(g.trace.astype(np.uint64), ref.trace), v
+        dic.dic_set_option("layout", 0)
+        for ct in (64, 100000 // 10):
+            dic.dic_set_option("count_target", ct)
+            g = dic.dic_mine(db, 0.006, 700)
+            assert np.array_equal(g.counts, ref.counts), ct
+    finally:
+        dic.dic_set_option("layout", 1)
+        for k, x in base.items():
+            dic.dic_set_option(k, x)
+        import paper_1812_10959_amd
+        paper_1812_10959_amd._apply_tuning()
+    with pytest.raises(dic.DicError):
+        dic.dic_set_option("vt_tile_words", 17)
