@@ -96,6 +96,28 @@ def count_work(results, W, n_frequent_items, layout):
     return byt, ops, ms, launches
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_count_vert_quest_zipf_n1M_m1000_pmc.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1812_10959_amd", "csrc", "dic_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per k_count_vert launch from the committed rocprofv3 counter
+    runs (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None
+    when the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if sha not in txt:
+        return None
+    for ln in txt.splitlines():
+        if ln.startswith("k_count_vert traffic_bytes_per_launch:"):
+            return float(ln.split(":")[1])
+    return None
+
+
 def roofline_entry(byt, ops, ms, launches):
     achieved_tops = ops / (ms * 1e-3) / 1e12 if ms else 0.0
     achieved_gbs = byt / (ms * 1e-3) / 1e9 if ms else 0.0
@@ -107,6 +129,7 @@ def roofline_entry(byt, ops, ms, launches):
                 "frac": achieved_gbs / HBM_PEAK_GBS},
         "avg_launch_us": ms / launches * 1e3 if launches else 0.0,
         "launches": launches, "count_ms": ms,
+        "algorithmic_bytes_per_launch": byt / launches if launches else 0.0,
     }
 
 
@@ -167,6 +190,9 @@ def headline(dic, args, c):
             f" {entry['achieved']:.3f} Tops/s ({100 * entry['frac']:.2f}% ALU), "
             f"{entry['hbm']['achieved']:.1f} GB/s, mine {pdt * 1e3:.1f} ms profiled")
     dic.dic_set_option("layout", 1)
+    if "item_bitsets" in layouts:
+        layouts["item_bitsets"]["traffic"] = measured_traffic()
+        layouts["item_bitsets"]["traffic_unit"] = "bytes per launch (HBM, rocprofv3 counters)"
     out["roofline"] = layouts.get("item_bitsets")
     out["layouts"] = layouts
     return out
