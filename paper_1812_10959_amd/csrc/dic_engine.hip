@@ -50,43 +50,6 @@ uint64_t next_pow2(uint64_t x)
     return p;
 }
 
-// splitmix64 (Steele, Lea & Flood's SplitMix generator in Vigna's 64-bit
-// form): fills the per-item random words of the Zobrist itemset hash.
-uint64_t splitmix64(uint64_t &s)
-{
-    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-std::mutex g_zob_mu;
-const unsigned long long *g_zob[64] = {};
-
-const unsigned long long *zobrist(hipStream_t s)
-{
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
-        return nullptr;
-    std::lock_guard<std::mutex> g(g_zob_mu);
-    if (g_zob[dev])
-        return g_zob[dev];
-    std::vector<unsigned long long> h(MAX_ITEMS);
-    uint64_t seed = 0x5EED1812109590ull;
-    for (auto &v : h)
-        v = splitmix64(seed);
-    void *d = nullptr;
-    if (hipMalloc(&d, h.size() * 8) != hipSuccess)  // kept for the process lifetime
-        return nullptr;
-    if (hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-        (void)hipFree(d);
-        return nullptr;
-    }
-    g_zob[dev] = (const unsigned long long *)d;
-    return g_zob[dev];
-}
-
 struct Carver {
     size_t off = 0;
     size_t take(size_t bytes)
@@ -314,6 +277,7 @@ int Engine::launch_steps(uint32_t S, bool rows, bool vert, bool prof, double *co
         return DIC_OK;
     };
     const uint32_t grid = knobs().count_grid;
+    launch_begin((Job *)table_, d_plan_step_, s_);
     // Events recorded inside a captured graph cannot be timed: profile directly.
     if (!use_graphs() || !own_stream_ || prof) {
         for (uint32_t k = 0; k < S; ++k)
@@ -356,7 +320,7 @@ bool Engine::running() const
 {
     for (ActiveJob *j : jobs_) {
         const JobState &s = st_[j->slot];
-        if (j->in_loop && !s.done && !s.overflow && next_live(s, j->cap) > 0)
+        if (j->in_loop && job_running(s, j->cap))
             return true;
     }
     return false;
@@ -434,11 +398,6 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         int rc = add_impl(same);
         return rc ? rc : add_impl(other);
     }
-    const unsigned long long *zob = zobrist(s_);
-    if (!zob) {
-        set_error("could not create the itemset hash table on the device");
-        return DIC_E_DEVICE;
-    }
     // one-time device buffers
     if (!slab_) {
         slab_ = dev_alloc(sizeof(JobState) * max_jobs_ + 4ull * max_jobs_);
@@ -451,6 +410,7 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         const size_t a2 = c.take(8ull * (max_jobs_ + 1)), a3 = c.take(8ull * (max_jobs_ + 1));
         const size_t b0 = c.take(4ull * (max_jobs_ + 1)), b1 = c.take(4ull * (max_jobs_ + 1));
         const size_t b2 = c.take(8ull * (max_jobs_ + 1)), b3 = c.take(8ull * (max_jobs_ + 1));
+        const size_t tk = c.take(4ull * TICKET_WORDS);
         plan_buf_ = dev_alloc(c.off);
         if (!slab_ || !table_ || !table_aux_ || !plan_buf_) {
             set_error("device allocation failed (engine tables)");
@@ -469,7 +429,8 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         plan_aux_.pre_epi = (uint32_t *)(pb + b1);
         plan_aux_.pre_cg = (unsigned long long *)(pb + b2);
         plan_aux_.pre_fp = (unsigned long long *)(pb + b3);
-        plan_step_.zobrist = plan_aux_.zobrist = zob;
+        plan_step_.tickets = plan_aux_.tickets = (uint32_t *)(pb + tk);
+        HIP_TRY(hipMemsetAsync(pb + tk, 0, 4ull * TICKET_WORDS, s_));
         HIP_TRY(hipMemsetAsync(slab_, 0, sizeof(JobState) * max_jobs_ + 4ull * max_jobs_, s_));
     }
     JobState *states = (JobState *)slab_;
@@ -675,8 +636,8 @@ int Engine::advance(uint32_t max_steps)
     uint32_t S = 1;
     for (ActiveJob *a : jobs_) {
         const JobState &s = st_[a->slot];
-        if (a->in_loop && !s.done && !s.overflow && next_live(s, a->cap) > 0)
-            S = std::max(S, new_candidates(s, a->cap) ? a->stop_max : s.max_rem);
+        if (a->in_loop && job_running(s, a->cap))
+            S = std::max(S, job_need(s, a->cap, a->stop_max));
     }
     S = std::min(S, std::max(1u, max_steps));
     // graph replays run whole multiples of GRAPH_STEPS stops
@@ -684,7 +645,9 @@ int Engine::advance(uint32_t max_steps)
     const uint32_t S_run = (use_graphs() && own_stream_ && !prof)
                                ? (S + GRAPH_STEPS - 1) / GRAPH_STEPS * GRAPH_STEPS
                                : S;
-    int rc = ensure_trace(S_run);
+    // a pending job also begins its first stop, and the last stop of the
+    // chunk begins the next one: up to S_run + 1 new trace entries
+    int rc = ensure_trace(S_run + 1);
     if (rc)
         return rc;
     if ((table_dirty_ || knobs_changed()) && (rc = upload_table()))
@@ -821,7 +784,7 @@ int Engine::harvest(std::vector<std::pair<uint64_t, MineOutput>> &done)
             keep.push_back(a);
         } else if (s.overflow) {
             over.push_back(a);
-        } else if (s.done || next_live(s, a->cap) == 0) {
+        } else if (!job_running(s, a->cap)) {
             fin.push_back(a);
         } else {
             keep.push_back(a);

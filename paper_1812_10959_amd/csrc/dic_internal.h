@@ -104,7 +104,9 @@ struct JobState {
     uint32_t pool_base; // pool size when this stop began: entries at or above
                         // it were created by this stop's candidate generation;
                         // they follow the survivors in the next live list
-    uint32_t pad[6];
+    uint32_t pending;   // added, not yet advanced to its first stop
+    uint32_t need;      // stops the current live set certainly still needs
+    uint32_t pad[4];
 };
 static_assert(sizeof(JobState) == 128, "JobState is read back as 128-byte records");
 static_assert(offsetof(JobState, k_next) % 8 == 0, "k_next/n_new form one 64-bit word");
@@ -119,6 +121,21 @@ __host__ __device__ inline uint32_t new_candidates(const JobState &s, uint32_t c
 __host__ __device__ inline uint32_t next_live(const JobState &s, uint32_t cap)
 {
     return s.k_next + new_candidates(s, cap);
+}
+// Between chunks of stops a job is either pending (added, its first stop not
+// begun) or already begun on its next stop by the last candidate generation.
+inline bool job_running(const JobState &s, uint32_t cap)
+{
+    if (s.done || s.overflow)
+        return false;
+    return s.pending ? next_live(s, cap) > 0 : true;
+}
+// Stops the job's current live set certainly still needs.
+inline uint32_t job_need(const JobState &s, uint32_t cap, uint32_t stop_max)
+{
+    if (s.pending)
+        return new_candidates(s, cap) ? stop_max : s.max_rem;
+    return s.need;
 }
 
 constexpr int KD = 16;  // frequent-item indices stored per candidate (larger: decode the mask)
@@ -162,9 +179,14 @@ struct Plan {
     uint32_t *pre_epi;
     unsigned long long *pre_cg;
     unsigned long long *pre_fp;  // first pass row chunks
-    const unsigned long long *zobrist;  // MAX_ITEMS random words
     uint32_t vt_target, vt_wave_k, vt_tile_words, count_target;  // see Knobs
+    uint32_t *tickets;  // arrival counters of candidate generation (zero between launches)
 };
+// arrival counters: a root and TICKET_GROUPS group counters, TICKET_STRIDE
+// words apart so that no two share a cache line
+constexpr uint32_t TICKET_GROUPS = 32;
+constexpr uint32_t TICKET_STRIDE = 64;
+constexpr uint32_t TICKET_WORDS = (TICKET_GROUPS + 1) * TICKET_STRIDE;
 
 // kernel launchers (dic_kernels.hip)
 void launch_first_pass(const Job *jobs, const Plan *plan, unsigned long long total_chunks,
@@ -175,6 +197,9 @@ void launch_transpose(const uint64_t *rows, uint64_t n, uint32_t m, uint64_t *ve
                       hipStream_t s);
 void launch_l1_and_pairs_prepare(const Job *jobs, const Plan *plan, uint32_t njobs, hipStream_t s);
 void launch_init_pairs(const Job *jobs, const Plan *plan, unsigned long long total, hipStream_t s);
+// Begin the next stop for newly added jobs and plan every job's work (once
+// per chunk of stops; later stops are begun by candidate generation).
+void launch_begin(const Job *jobs, Plan *plan, hipStream_t s);
 // One stop for every job in the table; when given, the two events bracket
 // the CountSupport launch on stream s.
 void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, bool rows, bool vert,

@@ -6,11 +6,14 @@
 // locates its job by binary search over per-job prefix sums of work.
 //
 // Per stop (the loop body of Algorithm 2, Section 4.2):
-//   k_begin     advance the block with rewind, size this stop's work
 //   k_count     CountSupport (Algorithm 3): live candidates x block rows
 //   k_epilogue  Prune (Algorithm 4) and CheckFullPass (Algorithm 5),
 //               compaction of the live list
-//   k_candgen   MakeCandidates: extend new boxes by frequent items
+//   k_candgen   MakeCandidates: extend new boxes by frequent items; its last
+//               workgroup advances the block with rewind and sizes the next
+//               stop's work
+// k_begin does the same advance-and-size for newly added jobs (and re-plans
+// the others) once at the start of a chunk of stops.
 // Before the loop: k_first_pass and k_l1 (FirstPass: item supports, the
 // frequent items), k_init_pairs (pairs of frequent items as candidates).
 // After it: k_collect gathers the solid boxes.
@@ -80,6 +83,41 @@ __device__ __forceinline__ uint32_t slot_tag(unsigned long long h, uint32_t k)
     return (uint32_t)(((h >> 40) & 0xFFFFFFull) << 8) | (k & 0xFFu);
 }
 
+// Random word of frequent item a (index into the job's frequent items) for
+// the Zobrist hash of an itemset, the XOR of its items' words: output a + 1
+// of the SplitMix64 generator (Steele, Lea & Flood, in Vigna's 64-bit form)
+// from a fixed seed.  Computed in registers instead of read from a table.
+__device__ __forceinline__ unsigned long long zob(uint32_t a)
+{
+    unsigned long long z = 0x5EED1812109590ull + (unsigned long long)(a + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// A candidate's frequent-item indices (ascending, KD x u16) as 8 words.
+__device__ __forceinline__ void load_items(const uint16_t *pi, uint32_t w[KD / 2])
+{
+    const uint4 *q = (const uint4 *)pi;
+    const uint4 h0 = q[0], h1 = q[1];
+    w[0] = h0.x; w[1] = h0.y; w[2] = h0.z; w[3] = h0.w;
+    w[4] = h1.x; w[5] = h1.y; w[6] = h1.z; w[7] = h1.w;
+}
+// Item t of such a list (t must be a compile-time constant after unrolling,
+// so the list stays in registers).
+__device__ __forceinline__ uint32_t item_at(const uint32_t w[KD / 2], int t)
+{
+    return (w[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
+}
+
+// Read a hash slot.  Slots are filled by device-scope atomics, possibly
+// from another XCD, so the read is a device-scope atomic too (a plain load
+// may be served by a stale copy in this XCD's L2).
+__device__ __forceinline__ unsigned long long slot_read(const Job *J, uint32_t s)
+{
+    return __hip_atomic_load(J->slots + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void hash_insert(const Job *J, unsigned long long h, uint32_t k,
                                             uint32_t idx)
 {
@@ -106,8 +144,7 @@ __device__ __forceinline__ uint32_t hash_find_sub(const Job *J, unsigned long lo
     const uint32_t W = J->W;
     uint32_t s = (uint32_t)h & J->hmask;
     for (;;) {
-        unsigned long long v =
-            __hip_atomic_load(J->slots + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long v = slot_read(J, s);
         if (v == SLOT_EMPTY)
             return NONE;
         if ((uint32_t)v == tag && (uint32_t)(v >> 32) < base) {
@@ -134,18 +171,53 @@ __device__ __forceinline__ uint32_t hash_find_sub(const Job *J, unsigned long lo
 template <typename T>
 __device__ T block_scan_incl(T v, T *sh, T *total)
 {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (uint32_t off = 1; off < WG; off <<= 1) {
-        T add = threadIdx.x >= off ? sh[threadIdx.x - off] : (T)0;
-        __syncthreads();
-        sh[threadIdx.x] += add;
-        __syncthreads();
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    for (uint32_t off = 1; off < 64u; off <<= 1) {
+        const T t = __shfl_up(v, off);
+        if (lane >= off)
+            v += t;
     }
-    T r = sh[threadIdx.x];
-    *total = sh[WG - 1];
+    if (lane == 63u)
+        sh[wave] = v;
     __syncthreads();
-    return r;
+    T before = 0, all = 0;
+    for (uint32_t w = 0; w < WG / 64; ++w) {
+        const T x = sh[w];
+        before += w < wave ? x : (T)0;
+        all += x;
+    }
+    __syncthreads();
+    *total = all;
+    return v + before;
+}
+
+// Inclusive prefix sums of three values per thread over the workgroup, in
+// one pass: shuffles within each wave, then the wave totals through LDS.
+// tot receives the workgroup totals.  sh holds 3 * (WG/64) words.
+__device__ void block_scan3(uint32_t v[3], uint32_t *sh, uint32_t tot[3])
+{
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    for (uint32_t off = 1; off < 64u; off <<= 1)
+        for (int c = 0; c < 3; ++c) {
+            const uint32_t t = (uint32_t)__shfl_up((int)v[c], off);
+            if (lane >= off)
+                v[c] += t;
+        }
+    if (lane == 63u)
+        for (int c = 0; c < 3; ++c)
+            sh[3u * wave + c] = v[c];
+    __syncthreads();
+    for (int c = 0; c < 3; ++c) {
+        uint32_t before = 0, all = 0;
+        for (uint32_t w = 0; w < WG / 64; ++w) {
+            const uint32_t x = sh[3u * w + c];
+            before += w < wave ? x : 0u;
+            all += x;
+        }
+        v[c] += before;
+        tot[c] = all;
+    }
+    __syncthreads();
 }
 
 // Sum of one value per thread over the workgroup (result in every thread).
@@ -370,6 +442,7 @@ __global__ __launch_bounds__(WG) void k_l1(const Job *__restrict__ jobs)
         const uint32_t nL1 = carry;
         const uint64_t nC2 = (uint64_t)nL1 * (nL1 ? nL1 - 1u : 0u) / 2u;
         st->nL1 = nL1;
+        st->pending = 1;
         st->k_next = 0;  // no survivors: the next live list is the pairs alone
         st->pool_base = 0;
         st->pool_n = (uint32_t)nC2;
@@ -401,7 +474,7 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
             mk[w] = 0;
         mk[ia >> 6] |= 1ull << (ia & 63u);
         mk[ib >> 6] |= 1ull << (ib & 63u);
-        const unsigned long long h = plan->zobrist[ia] ^ plan->zobrist[ib];
+        const unsigned long long h = zob(a) ^ zob(b);
         J->phash[p] = h;
         J->pnz[p] = (1ull << (ia >> 6)) | (1ull << (ib >> 6));
         J->pk[p] = 2;
@@ -421,12 +494,147 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
 // One stop.
 // ---------------------------------------------------------------------------
 
-// Advance every job's block (Algorithm 2: stop <- stop + 1, rewinding past
-// stop_max), swap live lists, record the trace entry and plan the count and
-// epilogue work.  One workgroup.
-__global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan *plan)
+// Advance a job to its next stop (Algorithm 2: stop <- stop + 1, rewinding
+// past stop_max): the survivors and the pool entries the last stop created
+// become the live list, the trace entry is started and the work counted.
+// pool_n is passed in (read atomically where other workgroups may still
+// have been adding to it).
+__device__ void advance_job(const Job *J, JobState *st, uint32_t pool_n)
 {
-    __shared__ uint32_t sh[WG];
+    const uint32_t pn = pool_n < J->cap ? pool_n : J->cap;
+    const uint32_t gen = pn > st->pool_base ? pn - st->pool_base : 0u;
+    if (pool_n > J->cap) {  // MakeCandidates ran out of pool room
+        st->overflow = 1;
+        return;
+    }
+    if (st->epoch >= 1u && st->epoch - 1u < J->trace_cap)
+        J->trace[st->epoch - 1u].generated = gen;
+    // stops the new live set certainly needs: the survivors' remaining
+    // stops, or a full pass for a candidate created at the last stop
+    const uint32_t need = gen ? J->stop_max : st->max_rem;
+    if (st->k_next + gen == 0) {
+        st->done = 1;
+        st->K = 0;
+        st->need = 0;
+        return;
+    }
+    const uint32_t K = st->k_next + gen;
+    st->K = K;
+    st->need = need;
+    st->pool_base = pn;
+    st->k_next = 0;
+    st->n_new = 0;
+    st->parity ^= 1u;
+    st->max_rem = 0;
+    const uint32_t stop = st->stop % J->stop_max + 1u;
+    st->stop = stop;
+    st->epoch += 1u;
+    const uint64_t first = (uint64_t)(stop - 1u) * J->Mp;
+    const uint64_t end = (uint64_t)stop * J->Mp;
+    const uint64_t last = end < J->n ? end : J->n;
+    st->first = (uint32_t)first;
+    st->last = (uint32_t)last;
+    const uint32_t rows = (uint32_t)(last - first);
+    st->tests += (unsigned long long)K * rows;
+    if (K > st->peak_K)
+        st->peak_K = K;
+    if (st->epoch - 1u < J->trace_cap) {
+        dic_stop_trace t;
+        t.stop = stop;
+        t.rows = rows;
+        t.live = K;
+        t.promoted = t.pruned = t.generated = t.solidified = t.words = t.items = 0;
+        t.reserved = 0;
+        J->trace[st->epoch - 1u] = t;
+    }
+}
+
+// Plan the count and epilogue work of a job's current stop (a function of
+// its state and the knobs).  Returns the work items of the row count, the
+// bitset count and the epilogue.
+__device__ void plan_job(const Job *J, JobState *st, const Plan *plan, uint32_t *items,
+                         uint32_t *itemsv, uint32_t *epi)
+{
+    *items = *itemsv = *epi = 0;
+    if (st->done || st->overflow || st->K == 0)
+        return;
+    const uint32_t K = st->K;
+    const uint32_t first = st->first, last = st->last;
+    const uint32_t rows = last - first;
+    *epi = (K + WG - 1u) / WG;
+    if (J->layout == LAYOUT_VERTICAL && K < plan->vt_wave_k) {
+        // few candidates: one wave per candidate, no tile
+        st->fw = first >> 6;
+        st->lw = (last - 1u) >> 6;
+        st->cmode = 1;
+        *itemsv = (K + WG / 64 - 1u) / (WG / 64);
+    } else if (J->layout == LAYOUT_VERTICAL) {
+        // (candidate groups of WG * cpt) x (chunks of tiles of tw words)
+        st->cmode = 0;
+        const uint32_t fw = first >> 6;
+        const uint32_t lw = (last - 1u) >> 6;
+        const uint32_t tw = vert_tile_words(st->nL1, plan->vt_tile_words);
+        const uint32_t ntile = (lw - fw + tw) / tw;
+        // candidates per thread: spend the parallelism beyond vt_target
+        // workgroups on fewer tile loads
+        const uint64_t vt_target = plan->vt_target;
+        uint64_t cpt = ((uint64_t)K * ntile + (uint64_t)WG * vt_target - 1u) /
+                       ((uint64_t)WG * vt_target);
+        cpt = cpt < 1u ? 1u : (cpt > (uint64_t)VT_CPT ? (uint64_t)VT_CPT : cpt);
+        st->cpt = (uint32_t)cpt;
+        const uint32_t n_cg = (K + WG * (uint32_t)cpt - 1u) / (WG * (uint32_t)cpt);
+        uint32_t want = ((uint32_t)vt_target + n_cg - 1u) / n_cg;
+        want = want < 1u ? 1u : (want > ntile ? ntile : want);
+        const uint32_t tpc = (ntile + want - 1u) / want;
+        st->fw = fw;
+        st->lw = lw;
+        st->tw = tw;
+        st->n_ct = n_cg;
+        st->rpi = tpc;
+        st->n_ri = (ntile + tpc - 1u) / tpc;
+        *itemsv = n_cg * st->n_ri;
+    } else {
+        const uint32_t rt = row_tile_rows(J->W);
+        const uint32_t n_ct = (K + CAND_PER_WG - 1u) / CAND_PER_WG;
+        const uint32_t tiles = (rows + rt - 1u) / rt;
+        uint32_t want = (plan->count_target + n_ct - 1u) / n_ct;
+        want = want < 1u ? 1u : (want > tiles ? tiles : want);
+        const uint32_t rpi = ((tiles + want - 1u) / want) * rt;
+        st->n_ct = n_ct;
+        st->rpi = rpi;
+        st->n_ri = (rows + rpi - 1u) / rpi;
+        *items = n_ct * st->n_ri;
+    }
+}
+
+// Arrival counter of a launch, called by one thread per workgroup after the
+// workgroup's work: true for the workgroup that arrives last.  Two levels
+// (workgroups of a group of TICKET_GROUPS, then the groups) keep the atomics
+// on any one counter few; the last arrival clears every counter for the
+// next launch.
+__device__ bool arrive_last(uint32_t *tickets)
+{
+    const uint32_t G = TICKET_GROUPS;
+    const uint32_t g = blockIdx.x % G;
+    const uint32_t groups = gridDim.x < G ? gridDim.x : G;
+    const uint32_t members = gridDim.x / G + (g < gridDim.x % G ? 1u : 0u);
+    if (atomicAdd(&tickets[(g + 1u) * TICKET_STRIDE], 1u) != members - 1u)
+        return false;
+    if (atomicAdd(&tickets[0], 1u) != groups - 1u)
+        return false;
+    for (uint32_t x = 0; x <= groups; ++x)
+        __hip_atomic_store(&tickets[x * TICKET_STRIDE], 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+// Begin the next stop for the jobs of the table and write the step's work
+// plan.  in_tail: run by the last workgroup of a candidate generation, which
+// advances every running job; otherwise (at the start of a chunk of stops)
+// only jobs not yet advanced since they were added move, and every job is
+// re-planned.  Every thread of the workgroup calls.
+__device__ void begin_jobs(const Job *__restrict__ jobs, Plan *plan, uint32_t *sh, bool in_tail)
+{
     const uint32_t njobs = plan->njobs;
     uint32_t carry_c = 0, carry_v = 0, carry_e = 0;
     if (threadIdx.x == 0) {
@@ -436,111 +644,38 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
     }
     for (uint32_t b = 0; b < njobs; b += WG) {
         const uint32_t j = b + threadIdx.x;
-        uint32_t items = 0, itemsv = 0, K = 0;
+        uint32_t items = 0, itemsv = 0, epi = 0;
         if (j < njobs) {
             const Job *J = jobs + j;
             JobState *st = J->st;
-            if (!st->done && !st->overflow) {
-                // the previous stop's MakeCandidates created pool entries
-                // [pool_base, pool_n); they follow its survivors in the list
-                const uint32_t gen = new_candidates(*st, J->cap);
-                if (st->epoch >= 1u && st->epoch - 1u < J->trace_cap)
-                    J->trace[st->epoch - 1u].generated = gen;
-                if (st->k_next + gen == 0) {
-                    st->done = 1;
-                    st->K = 0;
-                } else {
-                    K = st->k_next + gen;
-                    st->K = K;
-                    st->pool_base = st->pool_n < J->cap ? st->pool_n : J->cap;
-                    st->k_next = 0;
-                    st->n_new = 0;
-                    st->parity ^= 1u;
-                    st->max_rem = 0;
-                    const uint32_t stop = st->stop % J->stop_max + 1u;
-                    st->stop = stop;
-                    st->epoch += 1u;
-                    const uint64_t first = (uint64_t)(stop - 1u) * J->Mp;
-                    const uint64_t end = (uint64_t)stop * J->Mp;
-                    const uint64_t last = end < J->n ? end : J->n;
-                    st->first = (uint32_t)first;
-                    st->last = (uint32_t)last;
-                    const uint32_t rows = (uint32_t)(last - first);
-                    st->tests += (unsigned long long)K * rows;
-                    if (K > st->peak_K)
-                        st->peak_K = K;
-                    if (st->epoch - 1u < J->trace_cap) {
-                        dic_stop_trace t;
-                        t.stop = stop;
-                        t.rows = rows;
-                        t.live = K;
-                        t.promoted = t.pruned = t.generated = t.solidified = t.words = t.items = 0;
-                        t.reserved = 0;
-                        J->trace[st->epoch - 1u] = t;
-                    }
-                    if (J->layout == LAYOUT_VERTICAL && K < plan->vt_wave_k) {
-                        // few candidates: one wave per candidate, no tile
-                        st->fw = (uint32_t)(first >> 6);
-                        st->lw = (uint32_t)((last - 1u) >> 6);
-                        st->cmode = 1;
-                        itemsv = (K + WG / 64 - 1u) / (WG / 64);
-                    } else if (J->layout == LAYOUT_VERTICAL) {
-                        // (candidate groups of WG) x (chunks of tiles of tw words)
-                        st->cmode = 0;
-                        const uint32_t fw = (uint32_t)(first >> 6);
-                        const uint32_t lw = (uint32_t)((last - 1u) >> 6);
-                        const uint32_t tw = vert_tile_words(st->nL1, plan->vt_tile_words);
-                        const uint32_t ntile = (lw - fw + tw) / tw;
-                        // candidates per thread: spend the parallelism beyond
-                        // vt_target workgroups on fewer tile loads
-                        const uint64_t vt_target = plan->vt_target;
-                        uint64_t cpt = ((uint64_t)K * ntile + (uint64_t)WG * vt_target - 1u) /
-                                       ((uint64_t)WG * vt_target);
-                        cpt = cpt < 1u ? 1u : (cpt > (uint64_t)VT_CPT ? (uint64_t)VT_CPT : cpt);
-                        st->cpt = (uint32_t)cpt;
-                        const uint32_t n_cg = (K + WG * (uint32_t)cpt - 1u) / (WG * (uint32_t)cpt);
-                        uint32_t want = ((uint32_t)vt_target + n_cg - 1u) / n_cg;
-                        want = want < 1u ? 1u : (want > ntile ? ntile : want);
-                        const uint32_t tpc = (ntile + want - 1u) / want;
-                        st->fw = fw;
-                        st->lw = lw;
-                        st->tw = tw;
-                        st->n_ct = n_cg;
-                        st->rpi = tpc;
-                        st->n_ri = (ntile + tpc - 1u) / tpc;
-                        itemsv = n_cg * st->n_ri;
-                    } else {
-                    const uint32_t rt = row_tile_rows(J->W);
-                    const uint32_t n_ct = (K + CAND_PER_WG - 1u) / CAND_PER_WG;
-                    const uint32_t tiles = (rows + rt - 1u) / rt;
-                    uint32_t want = (plan->count_target + n_ct - 1u) / n_ct;
-                    if (want < 1u)
-                        want = 1u;
-                    if (want > tiles)
-                        want = tiles;
-                    const uint32_t rpi = ((tiles + want - 1u) / want) * rt;
-                    const uint32_t n_ri = (rows + rpi - 1u) / rpi;
-                    st->n_ct = n_ct;
-                    st->rpi = rpi;
-                    st->n_ri = n_ri;
-                    items = n_ct * n_ri;
-                    }
-                }
+            if (!st->done && !st->overflow && (in_tail || st->pending)) {
+                const uint32_t pool_n =
+                    in_tail ? __hip_atomic_load(&st->pool_n, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                            : st->pool_n;
+                advance_job(J, st, pool_n);
+                st->pending = 0;
             }
+            plan_job(J, st, plan, &items, &itemsv, &epi);
         }
-        uint32_t tc, tv, te;
-        const uint32_t ic = block_scan_incl<uint32_t>(items, sh, &tc);
-        const uint32_t iv = block_scan_incl<uint32_t>(itemsv, sh, &tv);
-        const uint32_t ie = block_scan_incl<uint32_t>((K + WG - 1u) / WG, sh, &te);
+        uint32_t v[3] = {items, itemsv, epi}, t[3];
+        block_scan3(v, sh, t);
         if (j < njobs) {
-            plan->pre_count[j + 1] = carry_c + ic;
-            plan->pre_countv[j + 1] = carry_v + iv;
-            plan->pre_epi[j + 1] = carry_e + ie;
+            plan->pre_count[j + 1] = carry_c + v[0];
+            plan->pre_countv[j + 1] = carry_v + v[1];
+            plan->pre_epi[j + 1] = carry_e + v[2];
         }
-        carry_c += tc;
-        carry_v += tv;
-        carry_e += te;
+        carry_c += t[0];
+        carry_v += t[1];
+        carry_e += t[2];
     }
+}
+
+// Standalone begin, once at the start of a chunk of stops.  One workgroup.
+__global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan *plan)
+{
+    __shared__ uint32_t sh[WG];
+    begin_jobs(jobs, plan, sh, false);
 }
 
 // CountSupport (Algorithm 3).  Work item = (row range, group of CAND_PER_WG
@@ -879,6 +1014,168 @@ __global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
     }
 }
 
+// Copy W 64-bit words (the loads of a group of eight are issued together).
+__device__ __forceinline__ void copy_words(uint64_t *dst, const uint64_t *src, uint32_t W)
+{
+    for (uint32_t w = 0; w < W; w += 8u) {
+        uint64_t r[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            r[u] = w + u < W ? src[w + u] : 0ull;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (w + u < W)
+                dst[w + u] = r[u];
+    }
+}
+
+// Item v of C = S | {a} in ascending order, given S's ascending list sw and
+// a's place pos in C (v a compile-time constant after unrolling).
+__device__ __forceinline__ uint32_t c_item(const uint32_t sw[KD / 2], uint32_t pos, uint32_t a,
+                                           int v)
+{
+    const uint32_t lo = v < KD ? item_at(sw, v) : 0u;
+    const uint32_t hi = v > 0 ? item_at(sw, v - 1) : 0u;
+    return (uint32_t)v < pos ? lo : ((uint32_t)v == pos ? a : hi);
+}
+
+// Whether the k-item list pw equals C's ascending list (k + 1 items) without
+// its element at position ct.
+__device__ __forceinline__ bool list_equals(const uint32_t pw[KD / 2], const uint32_t sw[KD / 2],
+                                            uint32_t pos, uint32_t a, uint32_t ct, uint32_t k)
+{
+    bool eq = true;
+#pragma unroll
+    for (int u = 0; u < KD; ++u)
+        if ((uint32_t)u < k)
+            eq &= item_at(pw, u) ==
+                  ((uint32_t)u < ct ? c_item(sw, pos, a, u) : c_item(sw, pos, a, u + 1));
+    return eq;
+}
+
+// Continue the linear probe for the k-itemset "C without position ct"
+// (hash h) after slot s.  Only itemsets that existed when the stop began
+// (index < base) are considered: one created by this stop's candidate
+// generation is a fresh circle, never the box being looked for, and its
+// pool entry may still be in flight from another workgroup, so it is
+// skipped without being read.
+__device__ __forceinline__ uint32_t probe_list(const Job *J, unsigned long long h, uint32_t k,
+                                               const uint32_t sw[KD / 2], uint32_t pos, uint32_t a,
+                                               uint32_t ct, uint32_t s, uint32_t base)
+{
+    const uint32_t tag = slot_tag(h, k);
+    for (;;) {
+        s = (s + 1u) & J->hmask;
+        const unsigned long long v = slot_read(J, s);
+        if (v == SLOT_EMPTY)
+            return NONE;
+        if ((uint32_t)v == tag && (uint32_t)(v >> 32) < base) {
+            const uint32_t idx = (uint32_t)(v >> 32);
+            uint32_t pw[KD / 2];
+            load_items(J->pitems + (uint64_t)idx * KD, pw);
+            if (list_equals(pw, sw, pos, a, ct, k))
+                return idx;
+        }
+    }
+}
+
+// MakeCandidates' admission test for C = S | {a}, |S| = k with 3 <= k <= KD:
+// every maximal subset (S \ {s_t}) | {a} other than S must be a box, and
+// none that drops an item larger than a may have been promoted at this stop
+// (that subset generates C).  sw: S's ascending list; pos: a's
+// place in C.  Subsets are checked in groups of SUBG whose hash-slot,
+// item-list and state loads are issued together.
+constexpr int SUBG = 2;
+__device__ __forceinline__ bool subsets_are_boxes(const Job *J, const uint32_t sw[KD / 2],
+                                                  uint32_t k, uint32_t a, uint32_t pos,
+                                                  unsigned long long hC,
+                                                  uint32_t base, uint32_t epoch)
+{
+    bool ok = true;
+#pragma unroll
+    for (int g = 0; g < KD; g += SUBG) {
+        if (!ok || (uint32_t)g >= k)
+            continue;
+        unsigned long long h[SUBG], v[SUBG];
+        uint32_t slot[SUBG];
+#pragma unroll
+        for (int u = 0; u < SUBG; ++u) {
+            h[u] = hC ^ zob(item_at(sw, g + u));
+            slot[u] = (uint32_t)h[u] & J->hmask;
+            v[u] = (uint32_t)(g + u) < k ? slot_read(J, slot[u]) : SLOT_EMPTY;
+        }
+        uint32_t idx[SUBG], pw[SUBG][KD / 2], sst[SUBG], spr[SUBG];
+#pragma unroll
+        for (int u = 0; u < SUBG; ++u) {
+            const bool hit = v[u] != SLOT_EMPTY && (uint32_t)v[u] == slot_tag(h[u], k) &&
+                             (uint32_t)(v[u] >> 32) < base;
+            idx[u] = hit ? (uint32_t)(v[u] >> 32) : NONE;
+            if (hit) {
+                load_items(J->pitems + (uint64_t)idx[u] * KD, pw[u]);
+                sst[u] = J->pstate[idx[u]];
+                spr[u] = J->ppromo[idx[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SUBG; ++u) {
+            const int t = g + u;
+            if ((uint32_t)t >= k)
+                continue;
+            const uint32_t drop = item_at(sw, t);
+            const uint32_t ct = (uint32_t)t < pos ? (uint32_t)t : (uint32_t)t + 1u;
+            uint32_t sub = idx[u], s2 = 0, pr = 0;
+            if (sub != NONE && list_equals(pw[u], sw, pos, a, ct, k)) {
+                s2 = sst[u];
+                pr = spr[u];
+            } else if (v[u] == SLOT_EMPTY) {
+                sub = NONE;
+            } else {
+                sub = probe_list(J, h[u], k, sw, pos, a, ct, slot[u], base);
+                if (sub != NONE) {
+                    s2 = J->pstate[sub];
+                    pr = J->ppromo[sub];
+                }
+            }
+            if (sub == NONE || (s2 != ST_DASHED_BOX && s2 != ST_SOLID_BOX))
+                ok = false;
+            else if (drop > a && pr == epoch)
+                ok = false;
+        }
+    }
+    return ok;
+}
+
+// The same test for |S| = k > KD (no item list): S's items come from its
+// bit mask and subsets are compared by mask.
+__device__ __forceinline__ bool subsets_are_boxes_wide(const Job *J, uint32_t p, uint32_t k, uint32_t a,
+                                       unsigned long long hC, uint32_t base, uint32_t epoch)
+{
+    const uint32_t W = J->W;
+    const uint32_t i = J->l1[a];
+    const uint64_t *S = J->pmask + (uint64_t)p * W;
+    if ((S[i >> 6] >> (i & 63u)) & 1ull)
+        return false;
+    uint64_t nzw = J->pnz[p];
+    while (nzw) {
+        const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
+        nzw &= nzw - 1;
+        uint64_t bits = S[wd];
+        while (bits) {
+            const uint32_t xj = wd * 64u + (uint32_t)__builtin_ctzll(bits);
+            bits &= bits - 1;
+            const uint32_t sub = hash_find_sub(J, hC ^ zob(J->l1pos[xj]), k, S, i, xj, base);
+            if (sub == NONE)
+                return false;
+            const uint32_t s2 = J->pstate[sub];
+            if (s2 != ST_DASHED_BOX && s2 != ST_SOLID_BOX)
+                return false;
+            if (xj > i && J->ppromo[sub] == epoch)
+                return false;  // a subset dropping a larger item generates C
+        }
+    }
+    return true;
+}
+
 // MakeCandidates: for each itemset S promoted at this stop and each frequent
 // item i not in S, C = S | {i} is admitted when every maximal proper subset
 // of C is a box.  C is produced by exactly one of its newly promoted subsets
@@ -887,8 +1184,7 @@ __global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
 // were all boxes before this stop was generated at an earlier stop).
 // Work item = (job, chunk of WG (new box, frequent item) pairs); every
 // workgroup derives the per-job prefix of chunks itself.
-__global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
-                                                const Plan *__restrict__ plan)
+__global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs, Plan *plan)
 {
     __shared__ unsigned long long pre[MAX_JOBS + 1];
     __shared__ unsigned long long sh_scan[WG];
@@ -913,86 +1209,73 @@ __global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
     }
     __syncthreads();
     const unsigned long long total = pre[njobs];
-    const unsigned long long *z = plan->zobrist;
     for (unsigned long long it = blockIdx.x; it < total; it += gridDim.x) {
         const uint32_t j = find_job(pre, njobs, it);
         const Job *J = jobs + j;
         JobState *st = J->st;
         const uint32_t W = J->W;
         const uint32_t nL1 = st->nL1;
+        const uint32_t base = st->pool_base;
         const unsigned long long x = (it - pre[j]) * WG + threadIdx.x;
         const bool valid = x < (unsigned long long)st->n_new * nL1;
         bool gen = false;
-        uint32_t p = 0, i = 0, k = 0;
+        uint32_t p = 0, a = 0, k = 0;
         unsigned long long hC = 0;
+        uint32_t sw[KD / 2];  // S's frequent-item indices, ascending (k <= KD)
+        uint32_t pos = 0;     // a's place in C = S | {a}
         if (valid) {
-            const uint32_t q = (uint32_t)(x / nL1), a = (uint32_t)(x % nL1);
+            const uint32_t q = (uint32_t)(x / nL1);
+            a = (uint32_t)(x % nL1);  // the new item, as a frequent-item index
             p = J->newbox[q];
-            i = J->l1[a];
             k = J->pk[p];
-            if (k == 2u) {
-                // S = {u0, u1} by frequent-item index; C's other maximal subsets
-                // {u0, a} and {u1, a} are pair candidates found at their index
-                const uint32_t h = *(const uint32_t *)(J->pitems + (uint64_t)p * KD);
-                const uint32_t u[2] = {h & 0xFFFFu, h >> 16};
-                gen = a != u[0] && a != u[1];
-                for (int t = 0; t < 2 && gen; ++t) {
-                    uint32_t lo = u[t], hi = a;
-                    if (lo > hi) {
-                        lo = a;
-                        hi = u[t];
+            const unsigned long long hS = J->phash[p];
+            if (k <= (uint32_t)KD) {
+                load_items(J->pitems + (uint64_t)p * KD, sw);
+                // a's place in S's ascending list; a already in S: no extension
+                bool in = false;
+#pragma unroll
+                for (int t = 0; t < KD; ++t)
+                    if ((uint32_t)t < k) {
+                        const uint32_t v = item_at(sw, t);
+                        pos += v < a ? 1u : 0u;
+                        in |= v == a;
                     }
-                    const uint32_t sub = lo * nL1 - lo * (lo + 1u) / 2u + (hi - lo - 1u);
-                    const uint32_t s2 = J->pstate[sub];
-                    if (s2 != ST_DASHED_BOX && s2 != ST_SOLID_BOX)
-                        gen = false;
-                    else if (u[1 - t] > a && J->ppromo[sub] == st->epoch)
-                        gen = false;  // the subset dropping the larger item generates C
-                                      // (frequent items are in ascending item order)
+                hC = hS ^ zob(a);
+                if (!in && k == 2u) {
+                    // C's other maximal subsets {s0, a} and {s1, a} are pair
+                    // candidates found at their lexicographic index
+                    const uint32_t s0 = item_at(sw, 0), s1 = item_at(sw, 1);
+                    const uint32_t lo0 = s0 < a ? s0 : a, hi0 = s0 < a ? a : s0;
+                    const uint32_t lo1 = s1 < a ? s1 : a, hi1 = s1 < a ? a : s1;
+                    const uint32_t sub0 = lo0 * nL1 - lo0 * (lo0 + 1u) / 2u + (hi0 - lo0 - 1u);
+                    const uint32_t sub1 = lo1 * nL1 - lo1 * (lo1 + 1u) / 2u + (hi1 - lo1 - 1u);
+                    const uint32_t st0 = J->pstate[sub0], st1 = J->pstate[sub1];
+                    const uint32_t pr0 = J->ppromo[sub0], pr1 = J->ppromo[sub1];
+                    gen = (st0 == ST_DASHED_BOX || st0 == ST_SOLID_BOX) &&
+                          (st1 == ST_DASHED_BOX || st1 == ST_SOLID_BOX) &&
+                          // a subset dropping a larger item than a, promoted
+                          // at this stop, generates C instead
+                          !(s1 > a && pr0 == st->epoch) && !(s0 > a && pr1 == st->epoch);
+                } else if (!in) {
+                    gen = subsets_are_boxes(J, sw, k, a, pos, hC, base, st->epoch);
                 }
-                if (gen)
-                    hC = J->phash[p] ^ z[i];
-            } else if (!((J->pmask[(uint64_t)p * W + (i >> 6)] >> (i & 63u)) & 1ull)) {
-                const uint64_t *S = J->pmask + (uint64_t)p * W;
-                hC = J->phash[p] ^ z[i];
-                gen = true;
-                uint64_t nzw = J->pnz[p];
-                while (gen && nzw) {
-                    const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
-                    nzw &= nzw - 1;
-                    uint64_t bits = S[wd];
-                    while (gen && bits) {
-                        const uint32_t xj = wd * 64u + (uint32_t)__builtin_ctzll(bits);
-                        bits &= bits - 1;
-                        const uint32_t sub =
-                            hash_find_sub(J, hC ^ z[xj], k, S, i, xj, st->pool_base);
-                        if (sub == NONE) {
-                            gen = false;
-                        } else {
-                            const uint32_t s2 = J->pstate[sub];
-                            if (s2 != ST_DASHED_BOX && s2 != ST_SOLID_BOX)
-                                gen = false;
-                            else if (xj > i && J->ppromo[sub] == st->epoch)
-                                gen = false;  // a subset dropping a larger item generates C
-                        }
-                    }
-                }
+            } else {
+                hC = hS ^ zob(a);
+                gen = subsets_are_boxes_wide(J, p, k, a, hC, base, st->epoch);
             }
         }
         // New entries are pool slots [pool_base, pool_n); in the next live
         // list they follow the survivors, at k_next + (slot - pool_base).
-        // Lookups in this launch never read them (see hash_find_sub), so
-        // no fence is needed before publishing them in the hash table.
+        // Lookups in this launch never read them (see probe_list), so no
+        // fence is needed before publishing them in the hash table.
         const uint32_t np = block_append(&st->pool_n, gen, sh_app);
         const bool stored = gen && np < J->cap;
         if (gen && !stored)
             st->overflow = 1u;
         if (stored) {
-            const uint64_t *S = J->pmask + (uint64_t)p * W;
-            uint64_t *C = J->pmask + (uint64_t)np * W;
-            for (uint32_t w = 0; w < W; ++w)
-                C[w] = S[w];
-            C[i >> 6] |= 1ull << (i & 63u);
+            const uint32_t i = J->l1[a];
+            copy_words(J->pmask + (uint64_t)np * W, J->pmask + (uint64_t)p * W, W);
+            J->pmask[(uint64_t)np * W + (i >> 6)] |= 1ull << (i & 63u);
             J->phash[np] = hC;
             J->pnz[np] = J->pnz[p] | (1ull << (i >> 6));
             J->pk[np] = k + 1u;
@@ -1001,17 +1284,30 @@ __global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs,
             J->pstate[np] = ST_DASHED_CIRCLE;
             J->ppromo[np] = NO_EPOCH;
             if (k + 1u <= (uint32_t)KD) {
-                const uint16_t *si = J->pitems + (uint64_t)p * KD;
-                uint16_t *ci = J->pitems + (uint64_t)np * KD;
-                for (uint32_t t = 0; t < k; ++t)
-                    ci[t] = si[t];
-                ci[k] = (uint16_t)(x % nL1);  // the frequent-item index of i
+                uint32_t w[KD / 2];
+#pragma unroll
+                for (int u = 0; u < KD / 2; ++u)
+                    w[u] = ((uint32_t)(2 * u) <= k ? c_item(sw, pos, a, 2 * u) : 0u) |
+                           (((uint32_t)(2 * u + 1) <= k ? c_item(sw, pos, a, 2 * u + 1) : 0u) << 16);
+                uint4 *ci = (uint4 *)(J->pitems + (uint64_t)np * KD);
+                ci[0] = make_uint4(w[0], w[1], w[2], w[3]);
+                ci[1] = make_uint4(w[4], w[5], w[6], w[7]);
             }
             hash_insert(J, hC, k + 1u, np);
             uint32_t *next = st->parity ? J->live0 : J->live1;
             next[st->k_next + (np - st->pool_base)] = np;
         }
     }
+    // The last workgroup to finish begins the next stop for every job (the
+    // state it needs was written by earlier kernels, except pool_n, which it
+    // reads atomically after all other workgroups took their ticket).
+    __shared__ uint32_t sh_last;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        sh_last = arrive_last(plan->tickets);
+    __syncthreads();
+    if (sh_last)
+        begin_jobs(jobs, plan, (uint32_t *)sh_scan, true);
 }
 
 // Gather solid boxes (the output L without its 1-itemsets).
@@ -1108,11 +1404,15 @@ void launch_init_pairs(const Job *jobs, const Plan *plan, unsigned long long tot
                        total);
 }
 
+void launch_begin(const Job *jobs, Plan *plan, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(WG), 0, s, jobs, plan);
+}
+
 void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, bool rows, bool vert,
                  uint32_t count_grid, hipEvent_t before, hipEvent_t after)
 {
     Plan *pl = const_cast<Plan *>(plan);
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(WG), 0, s, jobs, pl);
     if (before)
         (void)hipEventRecord(before, s);
     if (rows)
@@ -1122,7 +1422,7 @@ void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, bool rows, bo
     if (after)
         (void)hipEventRecord(after, s);
     hipLaunchKernelGGL(k_epilogue, dim3(GRID_EPI), dim3(WG), 0, s, jobs, plan);
-    hipLaunchKernelGGL(k_candgen, dim3(GRID_CG), dim3(WG), 0, s, jobs, plan);
+    hipLaunchKernelGGL(k_candgen, dim3(GRID_CG), dim3(WG), 0, s, jobs, pl);
 }
 
 void launch_collect(const Job *jobs, const Plan *, uint32_t njobs, hipStream_t s)

@@ -28,6 +28,23 @@ def _same(a, b):
             and np.array_equal(a.trace, b.trace) and a.stats["tests"] == b.stats["tests"])
 
 
+def _diff(a, b):
+    """Which parts of two results differ (for the failure message)."""
+    out = []
+    if a.masks.shape != b.masks.shape or not np.array_equal(a.masks, b.masks):
+        out.append(f"itemsets {a.masks.shape[0]} vs {b.masks.shape[0]}")
+    elif not np.array_equal(a.counts, b.counts):
+        out.append("counts")
+    if a.trace is None or b.trace is None or a.trace.shape != b.trace.shape:
+        out.append("trace shape")
+    elif not np.array_equal(a.trace, b.trace):
+        s = int(np.argwhere((a.trace != b.trace).any(axis=1))[0, 0])
+        out.append(f"trace from stop entry {s}: {a.trace[s].tolist()} vs {b.trace[s].tolist()}")
+    if a.stats["tests"] != b.stats["tests"]:
+        out.append("tests")
+    return "; ".join(out)
+
+
 def test_batch_of_256_full_size(orc):
     import paper_1812_10959_amd as dic
     _say("generating 256 databases")
@@ -40,7 +57,7 @@ def test_batch_of_256_full_size(orc):
     rng = np.random.default_rng(4)
     for i, (d, r) in enumerate(zip(spec, batched)):
         solo = dic.dic_mine(dbs[i], ms[i], Ms[i])
-        assert _same(r, solo), i
+        assert _same(r, solo), (i, _diff(r, solo))
         n, m = d["rows"].shape[0], d["m"]
         tau = orc.tau(ms[i], n)
         assert r.stats["tau"] == tau
