@@ -807,27 +807,51 @@ __global__ __launch_bounds__(WG) void k_count_vert(const Job *__restrict__ jobs,
             if (c >= st->K)
                 continue;
             const uint32_t lane = threadIdx.x & 63u;
-            const uint32_t p = (st->parity ? J->live1 : J->live0)[c];
-            const uint64_t nz = J->pnz[p];
-            const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+            const uint32_t p =
+                __builtin_amdgcn_readfirstlane((st->parity ? J->live1 : J->live0)[c]);
+            const uint32_t k = J->pk[p];
             const uint64_t lo_mask = ~0ull << (st->first & 63u);
             const uint64_t hi_mask =
                 (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
+            const uint32_t nw = J->nw;
             uint32_t cnt = 0;
-            for (uint32_t w = st->fw + lane; w <= st->lw; w += 64) {
-                uint64_t acc = (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull);
-                uint64_t nzw = nz;
-                while (nzw) {
-                    const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
-                    nzw &= nzw - 1;
-                    uint64_t bits = cm[wd];
-                    while (bits) {
-                        const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
-                        bits &= bits - 1;
-                        acc &= J->vert[(uint64_t)item * J->nw + w];
-                    }
+            if (k <= (uint32_t)KD) {
+                // item rows from the candidate's item list: the loads of all
+                // its items for a word are independent
+                uint32_t iw[KD / 2];
+                load_items(J->pitems + (uint64_t)p * KD, iw);
+                uint32_t row[KD];
+#pragma unroll
+                for (int t = 0; t < KD; ++t)
+                    row[t] = (uint32_t)t < k ? J->l1[item_at(iw, t)] : 0u;
+                for (uint32_t w = st->fw + lane; w <= st->lw; w += 64) {
+                    uint64_t acc =
+                        (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull);
+#pragma unroll
+                    for (int t = 0; t < KD; ++t)
+                        if ((uint32_t)t < k)
+                            acc &= J->vert[(uint64_t)row[t] * nw + w];
+                    cnt += (uint32_t)__popcll(acc);
                 }
-                cnt += (uint32_t)__popcll(acc);
+            } else {
+                const uint64_t nz = J->pnz[p];
+                const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+                for (uint32_t w = st->fw + lane; w <= st->lw; w += 64) {
+                    uint64_t acc =
+                        (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull);
+                    uint64_t nzw = nz;
+                    while (nzw) {
+                        const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
+                        nzw &= nzw - 1;
+                        uint64_t bits = cm[wd];
+                        while (bits) {
+                            const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
+                            bits &= bits - 1;
+                            acc &= J->vert[(uint64_t)item * nw + w];
+                        }
+                    }
+                    cnt += (uint32_t)__popcll(acc);
+                }
             }
             for (int off = 32; off > 0; off >>= 1)
                 cnt += (uint32_t)__shfl_xor((int)cnt, off);
