@@ -86,6 +86,14 @@ def _load():
     L.oracle_result_trace.argtypes = [p]
     L.oracle_result_free.argtypes = [p]
     L.oracle_result_free.restype = None
+    L.oracle_rules.argtypes = [p, p, u64, u32, ctypes.c_double, pp]
+    L.oracle_rules_size.restype = u64
+    L.oracle_rules_size.argtypes = [p]
+    for f in ("oracle_rules_itemset", "oracle_rules_code", "oracle_rules_supp_x"):
+        getattr(L, f).restype = p
+        getattr(L, f).argtypes = [p]
+    L.oracle_rules_free.argtypes = [p]
+    L.oracle_rules_free.restype = None
     _lib = L
     return L
 
@@ -195,4 +203,37 @@ def count_block(rows, m, masks, first: int = 0, last: int | None = None) -> np.n
                               int(first), int(last), out.ctypes.data)
     if rc:
         raise OracleError(rc, "oracle_count_block")
+    return out
+
+
+@dataclass
+class Rules:
+    """Association rules X => I \\ X: itemset[r] indexes I in the input,
+    code[r] selects X's items among I's ascending items, supp_x[r] = supp(X)."""
+    itemset: np.ndarray  # uint32[R]
+    code: np.ndarray     # uint32[R]
+    supp_x: np.ndarray   # uint32[R]
+
+
+def rules(masks, counts, minconf: float) -> Rules:
+    """All rules of confidence >= minconf from frequent itemsets (see the C header)."""
+    L = _load()
+    mk = np.ascontiguousarray(masks, dtype=np.uint64)
+    if mk.ndim != 2:
+        raise ValueError("masks must be uint64[q, W]")
+    ct = np.ascontiguousarray(counts, dtype=np.uint32)
+    h = ctypes.c_void_p()
+    rc = L.oracle_rules(mk.ctypes.data, ct.ctypes.data, mk.shape[0], mk.shape[1],
+                        float(minconf), ctypes.byref(h))
+    if rc:
+        raise OracleError(rc, "oracle_rules")
+    R = L.oracle_rules_size(h)
+
+    def arr(fn):
+        if not R:
+            return np.zeros(0, np.uint32)
+        return np.ctypeslib.as_array(ctypes.cast(fn(h), ctypes.POINTER(ctypes.c_uint32)),
+                                     shape=(R,)).copy()
+    out = Rules(arr(L.oracle_rules_itemset), arr(L.oracle_rules_code), arr(L.oracle_rules_supp_x))
+    L.oracle_rules_free(h)
     return out

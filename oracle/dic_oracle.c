@@ -95,13 +95,9 @@ static uint32_t n_items(const uint64_t *I, uint32_t W)
 static int has_item(const uint64_t *I, uint32_t p) { return (int)((I[p >> 6] >> (p & 63)) & 1u); }
 
 /* Canonical order: size ascending, then ascending item lists lexicographic. */
-static uint32_t canon_W;
-static const uint64_t *canon_masks;
-static int canon_cmp(const void *pa, const void *pb)
+static int mask_cmp(const uint64_t *A, const uint64_t *B, uint32_t W)
 {
-    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
-    const uint64_t *A = canon_masks + a * canon_W, *B = canon_masks + b * canon_W;
-    uint32_t ka = n_items(A, canon_W), kb = n_items(B, canon_W);
+    uint32_t ka = n_items(A, W), kb = n_items(B, W);
     if (ka != kb)
         return ka < kb ? -1 : 1;
     /* walk both item lists in ascending order; first difference decides */
@@ -118,6 +114,14 @@ static int canon_cmp(const void *pa, const void *pb)
         xb &= xb - 1;
     }
     return 0;
+}
+
+static uint32_t canon_W;
+static const uint64_t *canon_masks;
+static int canon_cmp(const void *pa, const void *pb)
+{
+    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    return mask_cmp(canon_masks + a * canon_W, canon_masks + b * canon_W, canon_W);
 }
 
 /* Build a result from q itemsets (masks q*W, counts q), sorting canonically. */
@@ -1072,6 +1076,130 @@ int oracle_count_block(const uint64_t *rows, uint64_t n, uint32_t m, const uint6
     }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* association rules                                                         */
+/* ------------------------------------------------------------------------ */
+
+struct or_rules {
+    uint64_t size, cap;
+    uint32_t *itemset, *code, *supp_x;
+};
+
+static int rules_push(or_rules *R, uint32_t i, uint32_t code, uint32_t sx)
+{
+    if (R->size == R->cap) {
+        uint64_t nc = R->cap ? 2 * R->cap : 1024;
+        uint32_t *a = (uint32_t *)realloc(R->itemset, nc * sizeof(uint32_t));
+        if (!a)
+            return OR_E_NOMEM;
+        R->itemset = a;
+        uint32_t *b = (uint32_t *)realloc(R->code, nc * sizeof(uint32_t));
+        if (!b)
+            return OR_E_NOMEM;
+        R->code = b;
+        uint32_t *c = (uint32_t *)realloc(R->supp_x, nc * sizeof(uint32_t));
+        if (!c)
+            return OR_E_NOMEM;
+        R->supp_x = c;
+        R->cap = nc;
+    }
+    R->itemset[R->size] = i;
+    R->code[R->size] = code;
+    R->supp_x[R->size] = sx;
+    R->size++;
+    return OR_OK;
+}
+
+void oracle_rules_free(or_rules *R)
+{
+    if (!R)
+        return;
+    free(R->itemset);
+    free(R->code);
+    free(R->supp_x);
+    free(R);
+}
+
+int oracle_rules(const uint64_t *masks, const uint32_t *counts, uint64_t q, uint32_t W,
+                 double minconf, or_rules **out)
+{
+    if (!out || W == 0 || (q && (!masks || !counts)) || minconf != minconf)
+        return OR_E_INVAL;
+    *out = NULL;
+    for (uint64_t i = 0; i < q; ++i)
+        if (n_items(masks + i * W, W) > OR_RULES_KMAX)
+            return OR_E_RANGE;
+    or_rules *R = (or_rules *)calloc(1, sizeof(*R));
+    uint64_t *perm = (uint64_t *)malloc((q ? q : 1) * sizeof(uint64_t));
+    uint64_t *X = (uint64_t *)malloc(W * sizeof(uint64_t));
+    if (!R || !perm || !X) {
+        free(perm);
+        free(X);
+        oracle_rules_free(R);
+        return OR_E_NOMEM;
+    }
+    /* itemsets in canonical order, so supp(X) is found by binary search */
+    for (uint64_t i = 0; i < q; ++i)
+        perm[i] = i;
+    canon_W = W;
+    canon_masks = masks;
+    qsort(perm, q, sizeof(uint64_t), canon_cmp);
+    int rc = OR_OK;
+    uint32_t items[OR_RULES_KMAX];
+    for (uint64_t i = 0; i < q && rc == OR_OK; ++i) {
+        const uint64_t *I = masks + i * W;
+        uint32_t k = 0;
+        for (uint32_t p = 0; p < 64u * W; ++p)
+            if (has_item(I, p))
+                items[k++] = p;
+        if (k < 2)
+            continue;
+        const uint32_t full = (1u << k) - 1u;
+        for (uint32_t code = 1; code < full && rc == OR_OK; ++code) {
+            /* X: the items of I selected by the bits of code */
+            memset(X, 0, W * sizeof(uint64_t));
+            for (uint32_t t = 0; t < k; ++t)
+                if ((code >> t) & 1u)
+                    X[items[t] >> 6] |= 1ull << (items[t] & 63u);
+            uint64_t lo = 0, hi = q;
+            int found = 0;
+            while (lo < hi) {
+                uint64_t mid = lo + (hi - lo) / 2;
+                int c = mask_cmp(X, masks + perm[mid] * W, W);
+                if (c == 0) {
+                    lo = mid;
+                    found = 1;
+                    break;
+                }
+                if (c < 0)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            if (!found) {
+                rc = OR_E_INVAL; /* a subset of a frequent itemset is missing */
+                break;
+            }
+            const uint32_t sx = counts[perm[lo]];
+            if ((double)counts[i] >= minconf * (double)sx)
+                rc = rules_push(R, (uint32_t)i, code, sx);
+        }
+    }
+    free(perm);
+    free(X);
+    if (rc) {
+        oracle_rules_free(R);
+        return rc;
+    }
+    *out = R;
+    return OR_OK;
+}
+
+uint64_t oracle_rules_size(const or_rules *R) { return R ? R->size : 0; }
+const uint32_t *oracle_rules_itemset(const or_rules *R) { return R ? R->itemset : NULL; }
+const uint32_t *oracle_rules_code(const or_rules *R) { return R ? R->code : NULL; }
+const uint32_t *oracle_rules_supp_x(const or_rules *R) { return R ? R->supp_x : NULL; }
 
 /* ------------------------------------------------------------------------ */
 /* result accessors                                                          */

@@ -91,6 +91,29 @@ int oracle_item_counts(const uint64_t *rows, uint64_t n, uint32_t m, uint32_t *c
 int oracle_count_block(const uint64_t *rows, uint64_t n, uint32_t m, const uint64_t *masks,
                        uint64_t q, uint64_t first, uint64_t last, uint32_t *counts);
 
+/*
+ * Association rules, the second subtask of association rule mining named in
+ * Section 1 (rule and confidence as defined by Agrawal et al., the paper's
+ * reference [1]).  Input: q frequent itemsets (masks q*W) with exact counts.
+ * For every itemset I with |I| >= 2 and every nonempty proper subset X of I,
+ * the rule X => I \ X has confidence supp(I) / supp(X); it is kept when
+ * (double)supp(I) >= minconf * (double)supp(X) in IEEE double arithmetic.
+ * Rules are ordered by I's position in the input, then by the subset code of
+ * X: bit t of the code selects the t-th smallest item of I.  supp(X) is
+ * looked up among the input itemsets; a missing subset (input not downward
+ * closed) gives OR_E_INVAL, an itemset of more than OR_RULES_KMAX items
+ * gives OR_E_RANGE.
+ */
+#define OR_RULES_KMAX 24u
+typedef struct or_rules or_rules;
+int oracle_rules(const uint64_t *masks, const uint32_t *counts, uint64_t q, uint32_t W,
+                 double minconf, or_rules **out);
+uint64_t oracle_rules_size(const or_rules *R);
+const uint32_t *oracle_rules_itemset(const or_rules *R); /* index of I in the input  */
+const uint32_t *oracle_rules_code(const or_rules *R);    /* subset code of X over I   */
+const uint32_t *oracle_rules_supp_x(const or_rules *R);  /* supp(X)                   */
+void oracle_rules_free(or_rules *R);
+
 uint64_t oracle_result_size(const or_result *r);
 uint32_t oracle_result_words(const or_result *r);
 const uint64_t *oracle_result_masks(const or_result *r);
