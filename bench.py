@@ -248,6 +248,32 @@ def other_configs(dic, inputs):
     return out
 
 
+def rules_bench(dic, cases, minconf=0.5):
+    """Association rules from mining results: device time of the two passes,
+    whole-call time, and the oracle's time on the same itemsets."""
+    import oracle
+    out = {}
+    for name, db, c in cases:
+        res = dic.dic_mine(db, c["minsup"], c["M"])
+        dic.dic_rules(res, minconf)
+        runs = [dic.dic_rules(res, minconf) for _ in range(5)]
+        k_ms = float(np.median([r.stats["kernel_ms"] for r in runs]))
+        t_ms = float(np.median([r.stats["total_ms"] for r in runs]))
+        st = runs[0].stats
+        t0 = time.perf_counter()
+        ref = oracle.rules(res.masks, res.counts, minconf)
+        o_s = time.perf_counter() - t0
+        assert len(ref.itemset) == st["rules"]
+        out[name] = {"minconf": minconf, "itemsets": int(st["itemsets"]),
+                     "splits": int(st["splits"]), "rules": int(st["rules"]),
+                     "kernel_ms": k_ms, "total_ms": t_ms,
+                     "G_splits_per_s_kernel": st["splits"] / (k_ms * 1e-3) / 1e9 if k_ms else None,
+                     "oracle_s": o_s, "oracle_cores": 1}
+        log(f"  rules {name}: {st['splits']} splits, {st['rules']} rules, kernel {k_ms:.3f} ms, "
+            f"call {t_ms:.2f} ms, oracle {o_s:.2f} s")
+    return out
+
+
 def batch_vs_plain(dic, dbs_spec):
     count = len(dbs_spec)
     dbs = [dic.dic_load_db(d["rows"], d["m"]) for d in dbs_spec]
@@ -360,6 +386,10 @@ def main():
             line["cpu_baseline"] = cpu_baseline(c, h["rows"], args.cpu_rows)
         log("other single-database workloads ...")
         line["workloads"] = other_configs(dic, others)
+        log("association rules ...")
+        line["rules"] = rules_bench(dic, [
+            ("quest_zipf_n1M_m1000", h["db"], c),
+            ("dense_n500k_m128", dic.dic_load_db(others[1]["rows"], others[1]["m"]), others[1])])
         if not args.no_batch:
             line["batched_vs_plain"] = batch_vs_plain(dic, batch)
         if not args.no_serve:

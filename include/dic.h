@@ -162,6 +162,54 @@ DIC_API int dic_result_stats(const dic_result *r, dic_stats *s);
 DIC_API const dic_stop_trace *dic_result_trace(const dic_result *r, uint64_t *n_stops);
 DIC_API void dic_result_free(dic_result *r);
 
+/* ---------------------------------------------------------------------------
+ * Association rules (the second subtask of association rule mining named in
+ * Section 1; rule X => Y and its confidence supp(X u Y) / supp(X) as defined
+ * in the paper's reference [1]; the paper does not define them itself).
+ *
+ * For every itemset I of a mining result with |I| >= 2 and every nonempty
+ * proper subset X of I, the rule X => I \ X is kept when
+ *     (double)supp(I) >= minconf * (double)supp(X)
+ * in IEEE double arithmetic.  supp(X) is the count of X in the same result
+ * (X is frequent whenever I is).  Rules are ordered by I's position in the
+ * result, then by X's subset code: bit t of the code selects the t-th
+ * smallest item of I.  Computed on the device (itemset hash table, every
+ * split looked up in parallel); the result lives in host memory.
+ *
+ * Errors: DIC_E_INVAL for NULL out, a NaN minconf, W outside [1, 64], an
+ * itemset of more than DIC_RULES_KMAX items, or itemsets that are not
+ * downward closed (a subset of some I missing); DIC_E_NOMEM; DIC_E_DEVICE.
+ * minconf <= 0 keeps every split, minconf > 1 keeps none.
+ * ------------------------------------------------------------------------- */
+#define DIC_RULES_KMAX 24
+typedef struct dic_rules_result dic_rules_result;
+typedef struct dic_rules_stats {
+    uint64_t itemsets;  /* itemsets of the input                                */
+    uint64_t splits;    /* (I, X) pairs examined: sum over |I| >= 2 of 2^|I| - 2 */
+    uint64_t rules;     /* rules kept                                           */
+    double kernel_ms;   /* device time of the two passes                        */
+    double total_ms;    /* the whole call, transfers included                   */
+} dic_rules_stats;
+
+/* Rules of a result from dic_mine / dic_batch / the server.  *out is owned by
+ * the caller (dic_rules_free). */
+DIC_API int dic_rules(const dic_result *r, double minconf, dic_rules_result **out);
+/* The same from host arrays: q itemsets as masks (q * W words, item p at bit
+ * p & 63 of word p >> 6) with their counts.  The arrays are read during the
+ * call only. */
+DIC_API int dic_rules_from_arrays(const uint64_t *masks, const uint32_t *counts, uint64_t q,
+                                  uint32_t W, double minconf, dic_rules_result **out);
+/* Rule accessors; pointers stay valid until dic_rules_free (NULL when empty). */
+DIC_API uint64_t dic_rules_size(const dic_rules_result *r);
+DIC_API uint32_t dic_rules_words(const dic_rules_result *r);
+DIC_API const uint32_t *dic_rules_itemset(const dic_rules_result *r); /* index of I        */
+DIC_API const uint32_t *dic_rules_code(const dic_rules_result *r);    /* subset code of X  */
+DIC_API const uint32_t *dic_rules_supp_x(const dic_rules_result *r);  /* supp(X)           */
+DIC_API const uint64_t *dic_rules_antecedent(const dic_rules_result *r); /* X, size * W    */
+DIC_API const uint64_t *dic_rules_consequent(const dic_rules_result *r); /* I \ X, size * W */
+DIC_API int dic_rules_stats_of(const dic_rules_result *r, dic_rules_stats *s);
+DIC_API void dic_rules_free(dic_rules_result *r);
+
 /*
  * Serving: a request loop that keeps databases and candidate tables on the
  * device and runs admitted requests together (continuous batching: a

@@ -51,7 +51,9 @@ ABI_FUNCTIONS = (
     "dic_result_masks", "dic_result_counts", "dic_result_stats", "dic_result_trace",
     "dic_result_free", "dic_serve_create", "dic_serve_submit", "dic_serve_poll",
     "dic_serve_wait", "dic_serve_stats", "dic_serve_destroy", "dic_set_allocator",
-    "dic_set_option", "dic_last_error",
+    "dic_set_option", "dic_last_error", "dic_rules", "dic_rules_from_arrays", "dic_rules_size",
+    "dic_rules_words", "dic_rules_itemset", "dic_rules_code", "dic_rules_supp_x",
+    "dic_rules_antecedent", "dic_rules_consequent", "dic_rules_stats_of", "dic_rules_free",
 )
 
 
@@ -72,6 +74,12 @@ class dic_stats(ctypes.Structure):
         "tau", "block", "stop_max", "stops", "tests", "peak_live", "n_frequent", "k_max",
         "known", "restarts")] + [("mine_ms", ctypes.c_double), ("count_ms", ctypes.c_double),
                                  ("count_launches", ctypes.c_uint64)]
+
+
+class dic_rules_stats(ctypes.Structure):
+    _fields_ = [("itemsets", ctypes.c_uint64), ("splits", ctypes.c_uint64),
+                ("rules", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
 
 
 class dic_serve_opts(ctypes.Structure):
@@ -112,6 +120,17 @@ _sig = {
     "dic_set_allocator": ([_ALLOC_T, _FREE_T, _p], ctypes.c_int),
     "dic_set_option": ([ctypes.c_char_p, _i64], ctypes.c_int),
     "dic_last_error": ([], ctypes.c_char_p),
+    "dic_rules": ([_p, ctypes.c_double, _pp], ctypes.c_int),
+    "dic_rules_from_arrays": ([_p, _p, _u64, _u32, ctypes.c_double, _pp], ctypes.c_int),
+    "dic_rules_size": ([_p], _u64),
+    "dic_rules_words": ([_p], _u32),
+    "dic_rules_itemset": ([_p], _p),
+    "dic_rules_code": ([_p], _p),
+    "dic_rules_supp_x": ([_p], _p),
+    "dic_rules_antecedent": ([_p], _p),
+    "dic_rules_consequent": ([_p], _p),
+    "dic_rules_stats_of": ([_p, ctypes.POINTER(dic_rules_stats)], ctypes.c_int),
+    "dic_rules_free": ([_p], None),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -272,6 +291,51 @@ def dic_batch(dbs, minsups, Ms, raise_on_error: bool = True):
 
 
 # --------------------------------------------------------------------------- serving
+
+@dataclass
+class Rules:
+    """Association rules X => I \\ X of a result, in (itemset, subset code) order.
+
+    itemset[r] indexes I among the result's itemsets; bit t of code[r] selects
+    the t-th smallest item of I into X; supp_x[r] = supp(X), so the confidence
+    is counts[itemset[r]] / supp_x[r].  antecedent / consequent are the masks
+    of X and I \\ X (uint64[R, W])."""
+    itemset: np.ndarray
+    code: np.ndarray
+    supp_x: np.ndarray
+    antecedent: np.ndarray
+    consequent: np.ndarray
+    stats: dict = field(default_factory=dict)
+
+
+def dic_rules(result: Result, minconf: float) -> Rules:
+    """Rules of confidence >= minconf from a mining result, computed on the GPU."""
+    masks = np.ascontiguousarray(result.masks, dtype=np.uint64)
+    counts = np.ascontiguousarray(result.counts, dtype=np.uint32)
+    q, W = masks.shape
+    h = _p()
+    _check(_lib.dic_rules_from_arrays(masks.ctypes.data if q else None,
+                                      counts.ctypes.data if q else None, q, W,
+                                      float(minconf), ctypes.byref(h)), "dic_rules")
+    try:
+        R = int(_lib.dic_rules_size(h))
+
+        def arr(fn, ctype, shape, dtype):
+            if not R:
+                return np.zeros(shape, dtype)
+            ptr = ctypes.cast(fn(h), ctypes.POINTER(ctype))
+            return np.ctypeslib.as_array(ptr, shape=(int(np.prod(shape)),)).reshape(shape).copy()
+        st = dic_rules_stats()
+        _check(_lib.dic_rules_stats_of(h, ctypes.byref(st)), "dic_rules_stats_of")
+        return Rules(arr(_lib.dic_rules_itemset, ctypes.c_uint32, (R,), np.uint32),
+                     arr(_lib.dic_rules_code, ctypes.c_uint32, (R,), np.uint32),
+                     arr(_lib.dic_rules_supp_x, ctypes.c_uint32, (R,), np.uint32),
+                     arr(_lib.dic_rules_antecedent, ctypes.c_uint64, (R, W), np.uint64),
+                     arr(_lib.dic_rules_consequent, ctypes.c_uint64, (R, W), np.uint64),
+                     {f: getattr(st, f) for f, _ in dic_rules_stats._fields_})
+    finally:
+        _lib.dic_rules_free(h)
+
 
 class Server:
     def __init__(self, handle: int):

@@ -140,6 +140,26 @@ inline uint32_t job_need(const JobState &s, uint32_t cap, uint32_t stop_max)
 
 constexpr int KD = 16;  // frequent-item indices stored per candidate (larger: decode the mask)
 
+// Random word of item a for the Zobrist hash of an itemset, the XOR of its
+// items' words (mining keys items by frequent-item index): output a + 1
+// of the SplitMix64 generator (Steele, Lea & Flood, in Vigna's 64-bit form)
+// from a fixed seed.  Computed in registers instead of read from a table.
+__device__ __forceinline__ unsigned long long zob(uint32_t a)
+{
+    unsigned long long z = 0x5EED1812109590ull + (unsigned long long)(a + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Hash slot key: pool index in the high half, a 24-bit fingerprint and the
+// itemset size (mod 256) in the low half.  Lookups of k-itemsets never match
+// a slot of a (k+1)-itemset being inserted concurrently.
+__device__ __forceinline__ uint32_t slot_tag(unsigned long long h, uint32_t k)
+{
+    return (uint32_t)(((h >> 40) & 0xFFFFFFull) << 8) | (k & 0xFFu);
+}
+
 // Read-only description of one mining run (device copy in a job table).
 struct Job {
     const uint64_t *rows;  // n * W, row-major

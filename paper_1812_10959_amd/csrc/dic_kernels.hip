@@ -75,26 +75,6 @@ __device__ __forceinline__ dic_stop_trace *trace_of(const Job *J, const JobState
     return (e >= 1 && e - 1 < J->trace_cap) ? J->trace + (e - 1) : nullptr;
 }
 
-// Hash slot key: pool index in the high half, a 24-bit fingerprint and the
-// itemset size (mod 256) in the low half.  Lookups of k-itemsets never match
-// a slot of a (k+1)-itemset being inserted concurrently.
-__device__ __forceinline__ uint32_t slot_tag(unsigned long long h, uint32_t k)
-{
-    return (uint32_t)(((h >> 40) & 0xFFFFFFull) << 8) | (k & 0xFFu);
-}
-
-// Random word of frequent item a (index into the job's frequent items) for
-// the Zobrist hash of an itemset, the XOR of its items' words: output a + 1
-// of the SplitMix64 generator (Steele, Lea & Flood, in Vigna's 64-bit form)
-// from a fixed seed.  Computed in registers instead of read from a table.
-__device__ __forceinline__ unsigned long long zob(uint32_t a)
-{
-    unsigned long long z = 0x5EED1812109590ull + (unsigned long long)(a + 1u) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
 // A candidate's frequent-item indices (ascending, KD x u16) as 8 words.
 __device__ __forceinline__ void load_items(const uint16_t *pi, uint32_t w[KD / 2])
 {

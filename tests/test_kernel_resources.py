@@ -41,10 +41,10 @@ def _report(src: str, tmp) -> dict:
 
 @pytest.mark.skipif(not shutil.which("hipcc") and not os.path.exists("/opt/rocm/bin/hipcc"),
                     reason="hipcc not available")
-def test_no_kernel_uses_scratch(tmp_path):
-    src = os.path.join(PKG, "csrc", "dic_kernels.hip")
-    rep = _report(src, tmp_path)
+@pytest.mark.parametrize("name,min_kernels", [("dic_kernels.hip", 10), ("dic_rules.hip", 3)])
+def test_no_kernel_uses_scratch(tmp_path, name, min_kernels):
+    rep = _report(os.path.join(PKG, "csrc", name), tmp_path)
     kernels = {k: v for k, v in rep.items() if "_ZN3dic" in k and "ScratchSize" in v}
-    assert len(kernels) >= 10, sorted(rep)
+    assert len(kernels) >= min_kernels, sorted(rep)
     bad = {k: v["ScratchSize"] for k, v in kernels.items() if v["ScratchSize"] != 0}
     assert not bad, f"kernels using scratch (bytes/lane): {bad}"
