@@ -67,6 +67,8 @@ def _load():
     pp = ctypes.POINTER(ctypes.c_void_p)
     L.oracle_tau.argtypes = [ctypes.c_double, u64, ctypes.POINTER(u64)]
     L.oracle_dic.argtypes = [p, u64, u32, ctypes.c_double, u64, ctypes.c_int, pp]
+    L.oracle_dic_init.argtypes = [p, u64, u32, ctypes.c_double, u64, ctypes.c_int, ctypes.c_int,
+                                  pp]
     for f in ("oracle_apriori", "oracle_bruteforce", "oracle_tidlist"):
         getattr(L, f).argtypes = [p, u64, u32, ctypes.c_double, pp]
     L.oracle_item_counts.argtypes = [p, u64, u32, p]
@@ -148,13 +150,15 @@ def tau(minsup: float, n: int) -> int:
     return int(out.value)
 
 
-def dic(rows, m: int, minsup: float, M: int, candgen_mode: int = 0) -> Result:
-    """Frequent itemsets by the oracle's serial ParallelDIC (Algorithm 2)."""
+def dic(rows, m: int, minsup: float, M: int, candgen_mode: int = 0, init_mode: int = 0) -> Result:
+    """Frequent itemsets by the oracle's serial ParallelDIC (Algorithm 2);
+    init_mode 1 starts from classic DIC's all-1-itemset Dashed Circle
+    (Algorithm 1) instead of FirstPass."""
     L = _load()
     r = _rows(rows)
     h = ctypes.c_void_p()
-    rc = L.oracle_dic(r.ctypes.data, r.shape[0], int(m), float(minsup), int(M),
-                      int(candgen_mode), ctypes.byref(h))
+    rc = L.oracle_dic_init(r.ctypes.data, r.shape[0], int(m), float(minsup), int(M),
+                           int(candgen_mode), int(init_mode), ctypes.byref(h))
     if rc:
         raise OracleError(rc, "oracle_dic")
     return _collect(L, h, "dic")

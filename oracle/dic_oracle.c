@@ -373,13 +373,19 @@ static void dic_state_free(dic_state *S)
 int oracle_dic(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, uint64_t M,
                int candgen_mode, or_result **out)
 {
+    return oracle_dic_init(rows, n, m, minsup, M, candgen_mode, 0, out);
+}
+
+int oracle_dic_init(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, uint64_t M,
+                    int candgen_mode, int init_mode, or_result **out)
+{
     if (!out)
         return OR_E_INVAL;
     *out = NULL;
     int rc = check_db(rows, n, m);
     if (rc)
         return rc;
-    if (M == 0 || (candgen_mode != 0 && candgen_mode != 1))
+    if (M == 0 || (candgen_mode != 0 && candgen_mode != 1) || (init_mode != 0 && init_mode != 1))
         return OR_E_INVAL;
     uint64_t tau;
     if ((rc = oracle_tau(minsup, n, &tau)))
@@ -404,6 +410,23 @@ int oracle_dic(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, uint
     rc = OR_E_NOMEM;
     if (!C || !tmp || !known_init(&S.known, W, 4096))
         goto done;
+
+    if (init_mode == 1) {
+        /* Algorithm 1 (classic DIC): every 1-itemset starts in Dashed Circle
+         * and is counted block by block like any candidate; no FirstPass.
+         * Every item may extend a box (its singleton's shape decides). */
+        L1 = (uint32_t *)malloc((m ? m : 1) * sizeof(uint32_t));
+        if (!L1)
+            goto done;
+        for (uint32_t i = 0; i < m; ++i) {
+            memset(C, 0, W * sizeof(uint64_t));
+            C[i >> 6] = 1ull << (i & 63);
+            if (!add_candidate(&S, C, 1))
+                goto done;
+            L1[nL1++] = i;
+        }
+        goto main_loop;
+    }
 
     /* Algorithm 2, initialisation: every 1-itemset goes to SOLID. */
     for (uint32_t i = 0; i < m; ++i) {
@@ -458,6 +481,7 @@ int oracle_dic(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, uint
             }
     }
 
+main_loop:;
     /* Algorithm 2, main loop: one iteration per stop until DASHED is empty. */
     uint64_t stop = 0;
     while (S.nd > 0) {

@@ -72,6 +72,18 @@ int oracle_tau(double minsup, uint64_t n, uint64_t *tau);
 int oracle_dic(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, uint64_t M,
                int candgen_mode, or_result **out);
 
+/*
+ * The same with a choice of initialisation.  init_mode 0 is the paper's
+ * FirstPass (Section 4.1): one full pass counts the 1-itemsets, the frequent
+ * ones are solid boxes and their pairs the first candidates.  init_mode 1 is
+ * classic DIC (Algorithm 1, Section 3): every 1-itemset starts as a dashed
+ * circle and is counted, promoted, pruned and solidified like any other
+ * candidate; pairs appear when their two items are boxes.  Both give the
+ * same frequent itemsets; the trace differs.
+ */
+int oracle_dic_init(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, uint64_t M,
+                    int candgen_mode, int init_mode, or_result **out);
+
 /* Level-wise Apriori over sorted item arrays; counts by item-presence lookup. */
 int oracle_apriori(const uint64_t *rows, uint64_t n, uint32_t m, double minsup,
                    or_result **out);
