@@ -254,6 +254,14 @@ DIC_API int dic_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(vo
  *              a word is the popcount of the AND of its items' words), 0 the
  *              row bitmaps themselves (one AND/compare per row and nonzero
  *              word).  Both give identical results.
+ *   "init"     start of runs started from now on: 0 (default) the paper's
+ *              FirstPass (Section 4.1: one full pass counts the 1-itemsets,
+ *              pairs of frequent items are the first candidates); 1 classic
+ *              DIC (Algorithm 1, Section 3): every 1-itemset starts as a
+ *              dashed circle and is counted block by block like any other
+ *              candidate.  Both give identical itemsets and counts; the
+ *              per-stop trace differs.  With M >= n either is level-wise
+ *              Apriori (one block per pass).
  *   "graphs"   1 (default): stops run as replays of a captured HIP graph of
  *              a few stops on the engine's own stream; 0: direct launches.
  *   Count planning (results never depend on them; chosen by the autotuner):

@@ -176,6 +176,10 @@ int dic_set_option(const char *name, int64_t value)
         set_use_graphs(value != 0);
         return DIC_OK;
     }
+    if (name && std::strcmp(name, "init") == 0 && (value == 0 || value == 1)) {
+        set_init_mode((uint32_t)value);
+        return DIC_OK;
+    }
     if (name && std::strcmp(name, "layout") == 0 && (value == 0 || value == 1)) {
         set_count_layout(value ? LAYOUT_VERTICAL : LAYOUT_ROWS);
         return DIC_OK;

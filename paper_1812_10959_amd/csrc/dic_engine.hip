@@ -111,6 +111,7 @@ struct PoolLayout {
 
 std::atomic<int> g_profile{0};
 std::atomic<uint32_t> g_layout{LAYOUT_VERTICAL};
+std::atomic<uint32_t> g_init{0};  // 0: FirstPass, 1: classic DIC initialisation
 std::atomic<bool> g_graphs{true};
 std::mutex g_knob_mu;
 Knobs g_knobs;
@@ -121,6 +122,8 @@ constexpr uint32_t GRAPH_STEPS = 8;  // stops per captured step graph
 bool profiling() { return g_profile.load() != 0; }
 void set_profiling(int on) { g_profile.store(on); }
 uint32_t count_layout() { return g_layout.load(); }
+uint32_t init_mode() { return g_init.load(); }
+void set_init_mode(uint32_t mode) { g_init.store(mode); }
 bool use_graphs() { return g_graphs.load(); }
 
 Knobs knobs()
@@ -200,7 +203,8 @@ struct ActiveJob {
     void *trace = nullptr;
     Job job{};
     uint32_t layout = LAYOUT_VERTICAL;
-    bool in_loop = false;   // pairs written, taking part in stops
+    uint32_t classic = 0;   // classic DIC start: every 1-itemset a candidate, no FirstPass
+    bool in_loop = false;   // first candidates written, taking part in stops
     double count_ms = 0;
     uint64_t count_launches = 0;
     std::chrono::steady_clock::time_point t0;
@@ -356,12 +360,14 @@ int Engine::add(const std::vector<MineRequest> &reqs, const std::vector<uint64_t
     std::vector<ActiveJob *> fresh;
     const auto now = std::chrono::steady_clock::now();
     const uint32_t layout = count_layout();
+    const uint32_t classic = init_mode();
     for (size_t i = 0; i < reqs.size(); ++i) {
         ActiveJob *a = new ActiveJob;
         a->id = ids[i];
         a->req = reqs[i];
         a->t0 = now;
         a->layout = reqs[i].vert ? layout : LAYOUT_ROWS;
+        a->classic = classic;
         fresh.push_back(a);
     }
     return add_internal(fresh);
@@ -472,6 +478,7 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         J.vert = a->req.vert;
         J.nw = (a->req.n + 63u) / 64u;
         J.layout = a->layout;
+        J.classic = a->classic;
         J.n = a->req.n;
         J.m = a->req.m;
         J.W = a->W;
@@ -495,9 +502,10 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
     pre_host_.assign(nf + 1, 0);
     for (uint32_t i = 0; i < nf; ++i) {
         const uint64_t n = fresh[i]->req.n;
-        const uint64_t work = vert ? (uint64_t)fresh[i]->req.m * (((n + 63) / 64 + FPV_WORDS - 1) /
-                                                                   FPV_WORDS)
-                                   : (n + FP_ROWS - 1) / FP_ROWS;
+        const uint64_t work = fresh[i]->classic ? 0  // classic DIC counts items in the stops
+                              : vert ? (uint64_t)fresh[i]->req.m *
+                                           (((n + 63) / 64 + FPV_WORDS - 1) / FPV_WORDS)
+                                     : (n + FP_ROWS - 1) / FP_ROWS;
         pre_host_[i + 1] = pre_host_[i] + work;
     }
     plan_aux_.njobs = nf;
@@ -553,8 +561,12 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         HIP_TRY(hipMemsetAsync(J.slots, 0xFF, L.hslots * 8, s_));
         aux_host_[i] = J;
     }
+    // first candidates: pairs of frequent items (nL1 x nL1 work), or every
+    // 1-itemset in classic mode (nL1 = m)
     for (uint32_t i = 0; i < nf; ++i)
-        pre_host_[i + 1] = pre_host_[i] + (unsigned long long)fresh[i]->nL1 * fresh[i]->nL1;
+        pre_host_[i + 1] = pre_host_[i] + (fresh[i]->classic
+                                               ? (unsigned long long)fresh[i]->nL1
+                                               : (unsigned long long)fresh[i]->nL1 * fresh[i]->nL1);
     HIP_TRY(hipMemcpyAsync(table_aux_, aux_host_.data(), sizeof(Job) * nf,
                            hipMemcpyHostToDevice, s_));
     HIP_TRY(hipMemcpyAsync(plan_aux_.pre_cg, pre_host_.data(), 8ull * (nf + 1),
@@ -764,7 +776,8 @@ int Engine::collect(std::vector<ActiveJob *> &fin,
         S.peak_live = s.peak_K;
         S.n_frequent = q;
         S.k_max = kmax;
-        S.known = (uint64_t)a->req.m + std::min(s.pool_n, a->cap);
+        // itemsets ever created: the 1-itemsets are pool entries in classic mode
+        S.known = (a->classic ? 0ull : (uint64_t)a->req.m) + std::min(s.pool_n, a->cap);
         S.restarts = a->restarts;
         S.mine_ms = std::chrono::duration<double, std::milli>(now - a->t0).count();
         S.count_ms = a->count_ms;
@@ -824,6 +837,7 @@ int Engine::harvest(std::vector<std::pair<uint64_t, MineOutput>> &done)
         b->t0 = a->t0;
         b->mult = a->mult * 4;
         b->layout = a->layout;
+        b->classic = a->classic;
         b->restarts = a->restarts + 1;
         b->count_ms = a->count_ms;
         b->count_launches = a->count_launches;

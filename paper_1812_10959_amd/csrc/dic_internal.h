@@ -183,7 +183,7 @@ struct Job {
     uint32_t *item_cnt;         // m
     dic_stop_trace *trace;
     uint32_t trace_cap;
-    uint32_t pad0;
+    uint32_t classic;  // classic DIC start (Algorithm 1): 1-itemsets are pool entries 0..m-1
     JobState *st;
     uint64_t *out_mask;   // collect: cap * W
     uint32_t *out_cnt;    // cap
@@ -275,6 +275,8 @@ bool profiling();
 void set_profiling(int on);
 uint32_t count_layout();
 void set_count_layout(uint32_t layout);
+uint32_t init_mode();
+void set_init_mode(uint32_t mode);
 
 struct ActiveJob;
 

@@ -406,6 +406,23 @@ __global__ __launch_bounds__(WG) void k_l1(const Job *__restrict__ jobs)
     __shared__ uint32_t sh[WG];
     const Job *J = jobs + blockIdx.x;
     JobState *st = J->st;
+    if (J->classic) {
+        // classic DIC: every item may extend a box, and every 1-itemset is a
+        // first candidate (pool entries 0..m-1)
+        for (uint32_t i = threadIdx.x; i < J->m; i += WG) {
+            J->l1[i] = i;
+            J->l1pos[i] = i;
+        }
+        if (threadIdx.x == 0) {
+            st->nL1 = J->m;
+            st->pending = 1;
+            st->k_next = 0;
+            st->pool_base = 0;
+            st->pool_n = J->m;
+            st->max_rem = 0;
+        }
+        return;
+    }
     uint32_t carry = 0;
     for (uint32_t b = 0; b < J->m; b += WG) {
         const uint32_t i = b + threadIdx.x;
@@ -430,8 +447,9 @@ __global__ __launch_bounds__(WG) void k_l1(const Job *__restrict__ jobs)
     }
 }
 
-// Candidate 2-itemsets: bitwise OR of every pair of frequent items, written
-// as pool entries 0..nC2-1 and as the first live list.
+// First candidates, written as pool entries and as the first live list:
+// the bitwise OR of every pair of frequent items (entries 0..nC2-1), or in
+// classic mode every 1-itemset (entries 0..m-1).
 __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
                                                    const Plan *__restrict__ plan,
                                                    unsigned long long total)
@@ -443,6 +461,25 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
         const Job *J = jobs + j;
         const uint32_t nL1 = J->st->nL1;
         const unsigned long long local = x - plan->pre_cg[j];
+        if (J->classic) {
+            // 1-itemset {a} at pool entry a
+            const uint32_t a = (uint32_t)local, W = J->W;
+            uint64_t *mk = J->pmask + (uint64_t)a * W;
+            for (uint32_t w = 0; w < W; ++w)
+                mk[w] = 0;
+            mk[a >> 6] = 1ull << (a & 63u);
+            J->phash[a] = zob(a);
+            J->pnz[a] = 1ull << (a >> 6);
+            J->pk[a] = 1;
+            J->pitems[(uint64_t)a * KD] = (uint16_t)a;
+            J->psupp[a] = 0;
+            J->pstop[a] = 0;
+            J->pstate[a] = ST_DASHED_CIRCLE;
+            J->ppromo[a] = NO_EPOCH;
+            J->live1[a] = a;
+            hash_insert(J, zob(a), 1, a);
+            continue;
+        }
         const uint32_t a = (uint32_t)(local / nL1), b = (uint32_t)(local % nL1);
         if (a >= b)
             continue;
@@ -1245,9 +1282,10 @@ __global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs, Pl
                         in |= v == a;
                     }
                 hC = hS ^ zob(a);
-                if (!in && k == 2u) {
+                if (!in && k == 2u && !J->classic) {
                     // C's other maximal subsets {s0, a} and {s1, a} are pair
-                    // candidates found at their lexicographic index
+                    // candidates found at their lexicographic index (pairs
+                    // are created up front, except in classic mode)
                     const uint32_t s0 = item_at(sw, 0), s1 = item_at(sw, 1);
                     const uint32_t lo0 = s0 < a ? s0 : a, hi0 = s0 < a ? a : s0;
                     const uint32_t lo1 = s1 < a ? s1 : a, hi1 = s1 < a ? a : s1;
