@@ -304,15 +304,13 @@ def batch_vs_plain(dic, dbs_spec):
     return out
 
 
-def serving(dic, seconds, rate, c2, c3, small):
+def _serve_run(dic, pool, dbs, rate, seconds, seed=None):
+    """Open-loop Poisson arrivals at `rate` for `seconds` on a fresh server."""
     import synth
-    log(f"serving: Poisson {rate}/s for {seconds}s over mixed databases ...")
-    pool = [dict(c2, minsup_range=(0.005, 0.05)), dict(c3, minsup_range=(0.25, 0.30))]
-    for d in small:
-        pool.append(dict(d, minsup_range=(0.01, 0.05)))
-    dbs = [dic.dic_load_db(p["rows"], p["m"]) for p in pool]
+    kw = {} if seed is None else {"seed": seed}
     stream = synth.serve_stream([p["rows"].shape[0] for p in pool], rate=rate,
-                                duration_s=seconds, minsup_ranges=[p["minsup_range"] for p in pool])
+                                duration_s=seconds, minsup_ranges=[p["minsup_range"] for p in pool],
+                                **kw)
     srv = dic.dic_serve_create(200 << 30, max_active=64)
     tickets = []
     t_start = time.perf_counter()
@@ -322,13 +320,23 @@ def serving(dic, seconds, rate, c2, c3, small):
             time.sleep(t_arr - now)
         M = pool[j]["M"] if j < 2 else max(1, pool[j]["rows"].shape[0] // 20)
         tickets.append((dic.dic_serve_submit(srv, dbs[j], minsup, M), j, minsup, M))
-    log(f"  submitted {len(tickets)} requests; waiting ...")
     results = []
     for (t, j, minsup, M) in tickets:
         results.append((dic.dic_serve_wait(srv, t), j, minsup, M))
     wall = time.perf_counter() - t_start
     p50, p99, rps = dic.dic_serve_stats(srv)
     dic.dic_serve_destroy(srv)
+    return results, wall, p50, p99, rps
+
+
+def serving(dic, seconds, rate, c2, c3, small):
+    log(f"serving: Poisson {rate}/s for {seconds}s over mixed databases ...")
+    pool = [dict(c2, minsup_range=(0.005, 0.05)), dict(c3, minsup_range=(0.25, 0.30))]
+    for d in small:
+        pool.append(dict(d, minsup_range=(0.01, 0.05)))
+    dbs = [dic.dic_load_db(p["rows"], p["m"]) for p in pool]
+    results, wall, p50, p99, rps = _serve_run(dic, pool, dbs, rate, seconds)
+    log(f"  {len(results)} requests served")
     # spot-check that served results equal solo mining
     rng = np.random.default_rng(0)
     ok = True
@@ -343,6 +351,23 @@ def serving(dic, seconds, rate, c2, c3, small):
            "G_tests_per_s": tests / wall / 1e9, "budget_bytes": 200 << 30,
            "spot_check_identical": bool(ok)}
     log(f"  p50 {p50:.1f} ms, p99 {p99:.1f} ms, {rps:.1f} req/s, spot-check identical={ok}")
+    # sustainable rate: offered rates doubled until the server falls behind
+    # (completions below 95 % of the offered rate or p99 above 250 ms)
+    sweep, best = [], None
+    r = 2 * rate
+    while r <= 32 * rate:
+        res, w, a50, a99, arps = _serve_run(dic, pool, dbs, r, 3.0, seed=int(r))
+        kept = arps >= 0.95 * r and a99 <= 250.0
+        sweep.append({"rate_req_per_s": r, "requests": len(res), "p50_ms": a50, "p99_ms": a99,
+                      "throughput_req_per_s": arps, "keeps_up": bool(kept)})
+        log(f"  offered {r:.0f}/s: {arps:.0f} req/s done, p50 {a50:.1f} ms, p99 {a99:.1f} ms")
+        if not kept:
+            break
+        best = r
+        r *= 2
+    out["rate_sweep"] = sweep
+    out["sustainable_req_per_s"] = best if best is not None else (rate if rps >= 0.95 * rate
+                                                                   else None)
     return out
 
 
