@@ -12,11 +12,13 @@ workgroups and tiles:
 * ``count_grid``     workgroups launched for the count kernels (blocks in
   flight per CU).
 
-No setting changes any result.  ``tune`` times mining of a workload sample
+No setting changes any result.  ``tune`` times each workload of a sample
 under each combination (after a warm-up), checks that every combination
-returns exactly the same itemsets, counts and traces, and records the
-fastest.  ``save`` writes the choice to JSON; the package applies
-``tuning.json`` beside it at import.
+returns exactly the same itemsets, counts and traces, and picks the
+combination with the lowest mean of per-workload time ratios to the
+defaults (so a long workload does not outweigh a short one).  ``save``
+writes the choice to JSON; the package applies ``tuning.json`` beside it at
+import.
 
     python -m paper_1812_10959_amd.autotune --batch 48 --out paper_1812_10959_amd/tuning.json
 """
@@ -36,7 +38,7 @@ TUNING_JSON = os.path.join(HERE, "tuning.json")
 
 DEFAULTS = {"vt_target": 768, "vt_wave_k": 2048, "vt_tile_words": 16, "count_grid": 2048}
 GRID = {
-    "vt_target": (768, 1536, 3072),
+    "vt_target": (512, 768, 1024, 1536),
     "vt_wave_k": (2048, 8192, 16384),
     "vt_tile_words": (8, 16),
     "count_grid": (1024, 2048),
@@ -49,17 +51,35 @@ def apply(settings: dict) -> None:
         dic_set_option(k, int(v))
 
 
+def _run_one(dic, item):
+    kind, payload = item
+    if kind == "mine":
+        db, ms, M = payload
+        return [dic.dic_mine(db, ms, M)]
+    dbs, ms, Ms = payload
+    return list(dic.dic_batch(dbs, ms, Ms))
+
+
 def _run(dic, work):
     """Mine every (kind, payload) item; returns results in order."""
     out = []
-    for kind, payload in work:
-        if kind == "mine":
-            db, ms, M = payload
-            out.append(dic.dic_mine(db, ms, M))
-        else:
-            dbs, ms, Ms = payload
-            out.extend(dic.dic_batch(dbs, ms, Ms))
+    for item in work:
+        out.extend(_run_one(dic, item))
     return out
+
+
+def _timed(dic, work, reps):
+    """Per-item median seconds over reps, and the results of the last rep."""
+    times, res = [], []
+    for item in work:
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = _run_one(dic, item)
+            ts.append(time.perf_counter() - t0)
+        times.append(float(np.median(ts)))
+        res.extend(r)
+    return times, res
 
 
 def _same(a, b):
@@ -76,31 +96,29 @@ def tune(work, grid=GRID, reps: int = 2, log=print) -> dict:
     import paper_1812_10959_amd as dic
     apply(DEFAULTS)
     _run(dic, work)  # warm graphs and caches
-    ref = _run(dic, work)
+    base, ref = _timed(dic, work, reps)
     names = list(grid)
     table = []
     for combo in itertools.product(*(grid[n] for n in names)):
         settings = dict(zip(names, combo))
         apply(settings)
         _run(dic, work)  # warm-up under these settings
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            res = _run(dic, work)
-        dt = (time.perf_counter() - t0) / reps
+        times, res = _timed(dic, work, reps)
         if not _same(res, ref):
             apply(DEFAULTS)
             raise AssertionError(f"settings {settings} changed a result")
-        table.append((settings, dt))
-        log(f"  {settings}: {dt * 1e3:.2f} ms")
-    best, best_t = min(table, key=lambda kv: kv[1])
-    default_t = next(t for s, t in table if s == {k: DEFAULTS[k] for k in names})
+        score = float(np.mean([t / b for t, b in zip(times, base)]))
+        table.append((settings, score, times))
+        log(f"  {settings}: score {score:.4f}, " +
+            ", ".join(f"{t * 1e3:.2f} ms" for t in times))
+    best, best_score, best_times = min(table, key=lambda kv: kv[1])
     apply(best)
-    return {"best": best, "seconds": best_t, "default_seconds": default_t,
-            "table": [[s, t] for s, t in table]}
+    return {"best": best, "score": best_score, "seconds": best_times, "default_seconds": base,
+            "table": [[s, sc, t] for s, sc, t in table]}
 
 
 def save(result: dict, path: str = TUNING_JSON, workload: str = "") -> None:
-    doc = {"settings": result["best"], "seconds": result["seconds"],
+    doc = {"settings": result["best"], "score": result["score"], "seconds": result["seconds"],
            "default_seconds": result["default_seconds"], "workload": workload,
            "table": result["table"]}
     with open(path, "w") as f:
@@ -134,8 +152,9 @@ def main(argv=None):
             ("batch", (dbs, [d["minsup"] for d in spec], [d["M"] for d in spec]))]
     res = tune(work, reps=a.reps, log=lambda *x: print(*x, flush=True))
     save(res, a.out, workload=f"n=1e6 m=1000 mine + batch of {a.batch}")
-    print(json.dumps({"best": res["best"], "ms": res["seconds"] * 1e3,
-                      "default_ms": res["default_seconds"] * 1e3}))
+    print(json.dumps({"best": res["best"], "score": res["score"],
+                      "ms": [t * 1e3 for t in res["seconds"]],
+                      "default_ms": [t * 1e3 for t in res["default_seconds"]]}))
 
 
 if __name__ == "__main__":
