@@ -104,9 +104,10 @@ struct JobState {
     uint32_t pool_base; // pool size when this stop began: entries at or above
                         // it were created by this stop's candidate generation;
                         // they follow the survivors in the next live list
-    uint32_t pending;   // added, not yet advanced to its first stop
+    uint32_t pending;   // added, not yet moved to its first block
     uint32_t need;      // stops the current live set certainly still needs
-    uint32_t pad[4];
+    uint32_t ks;        // candidates at the head of the current list counted by X
+    uint32_t pad[3];
 };
 static_assert(sizeof(JobState) == 128, "JobState is read back as 128-byte records");
 static_assert(offsetof(JobState, k_next) % 8 == 0, "k_next/n_new form one 64-bit word");

@@ -5,15 +5,16 @@
 // a step launches each kernel once for all jobs, and each workgroup or wave
 // locates its job by binary search over per-job prefix sums of work.
 //
-// Per stop (the loop body of Algorithm 2, Section 4.2):
-//   k_count     CountSupport (Algorithm 3): live candidates x block rows
-//   k_epilogue  Prune (Algorithm 4) and CheckFullPass (Algorithm 5),
-//               compaction of the live list
-//   k_candgen   MakeCandidates: extend new boxes by frequent items; its last
-//               workgroup advances the block with rewind and sizes the next
-//               stop's work
-// k_begin does the same advance-and-size for newly added jobs (and re-plans
-// the others) once at the start of a chunk of stops.
+// Per stop (the loop body of Algorithm 2, Section 4.2), two launches:
+//   k_stepx     MakeCandidates (extend new boxes by frequent items) and, in
+//               other workgroups, CountSupport (Algorithm 3) of the last
+//               stop's survivors on the next block (k_count counts row-bitmap
+//               jobs just before); the last workgroup completes the stop
+//   k_stepz     CountSupport of the new candidates, then Prune (Algorithm 4)
+//               and CheckFullPass (Algorithm 5) with compaction of the live
+//               list; the last workgroup moves every job to its next block
+// k_begin starts a chunk of stops: newly added jobs move to their first
+// block, and every job is planned for the current job table.
 // Before the loop: k_first_pass and k_l1 (FirstPass: item supports, the
 // frequent items), k_init_pairs (pairs of frequent items as candidates).
 // After it: k_collect gathers the solid boxes.
@@ -171,26 +172,30 @@ __device__ T block_scan_incl(T v, T *sh, T *total)
     return v + before;
 }
 
-// Inclusive prefix sums of three values per thread over the workgroup, in
-// one pass: shuffles within each wave, then the wave totals through LDS.
-// tot receives the workgroup totals.  sh holds 3 * (WG/64) words.
-__device__ void block_scan3(uint32_t v[3], uint32_t *sh, uint32_t tot[3])
+// Inclusive prefix sums of NV values per thread over the workgroup, in one
+// pass: shuffles within each wave, then the wave totals through LDS.  tot
+// receives the workgroup totals.  sh holds NV * (WG/64) words.
+template <int NV>
+__device__ void block_scan_n(uint32_t (&v)[NV], uint32_t *sh, uint32_t (&tot)[NV])
 {
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     for (uint32_t off = 1; off < 64u; off <<= 1)
-        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
             const uint32_t t = (uint32_t)__shfl_up((int)v[c], off);
             if (lane >= off)
                 v[c] += t;
         }
     if (lane == 63u)
-        for (int c = 0; c < 3; ++c)
-            sh[3u * wave + c] = v[c];
+#pragma unroll
+        for (int c = 0; c < NV; ++c)
+            sh[NV * wave + c] = v[c];
     __syncthreads();
-    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
         uint32_t before = 0, all = 0;
         for (uint32_t w = 0; w < WG / 64; ++w) {
-            const uint32_t x = sh[3u * w + c];
+            const uint32_t x = sh[NV * w + c];
             before += w < wave ? x : 0u;
             all += x;
         }
@@ -511,12 +516,43 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
 // One stop.
 // ---------------------------------------------------------------------------
 
-// Advance a job to its next stop (Algorithm 2: stop <- stop + 1, rewinding
-// past stop_max): the survivors and the pool entries the last stop created
-// become the live list, the trace entry is started and the work counted.
-// pool_n is passed in (read atomically where other workgroups may still
-// have been adding to it).
-__device__ void advance_job(const Job *J, JobState *st, uint32_t pool_n)
+// A stop runs as two launches, the first overlapping the next block:
+//   X(e)   MakeCandidates for the boxes promoted at stop e and, in other
+//          workgroups, CountSupport of stop e's survivors on block e + 1
+//          (they are already in the next live list); the last workgroup
+//          finishes stop e (the new candidates join the list) and plans Z;
+//   Z(e+1) CountSupport of the candidates created at stop e (one wave each)
+//          on block e + 1, then Prune and CheckFullPass of every candidate of
+//          stop e + 1; the last workgroup moves each job to block e + 2 for
+//          its survivors and plans X.
+// Counting the survivors before MakeCandidates is done changes nothing they
+// count, so results and traces are those of the paper's order.
+
+// Move a job to its next block (Algorithm 2: stop <- stop + 1, rewinding past
+// stop_max) for the survivors in its next live list; they are counted by X.
+__device__ void to_next_block(const Job *J, JobState *st)
+{
+    const uint32_t stop = st->stop % J->stop_max + 1u;
+    st->stop = stop;
+    const uint64_t first = (uint64_t)(stop - 1u) * J->Mp;
+    const uint64_t end = (uint64_t)stop * J->Mp;
+    st->first = (uint32_t)first;
+    st->last = (uint32_t)(end < J->n ? end : J->n);
+    st->fw = st->first >> 6;  // the block's 64-row words, for the bitset counts
+    st->lw = (st->last - 1u) >> 6;
+    // stops the live set certainly still needs: one fewer than when this
+    // stop began, at least the survivors' remaining stops, and at least one
+    // if MakeCandidates is still to run for new boxes
+    const uint32_t left = st->need > 1u ? st->need - 1u : 0u;
+    const uint32_t floor = st->max_rem > (st->n_new ? 1u : 0u) ? st->max_rem
+                                                                 : (st->n_new ? 1u : 0u);
+    st->need = left > floor ? left : floor;
+}
+
+// Finish stop e after MakeCandidates: the created pool entries follow the
+// survivors in the list, which becomes the current list of stop e + 1.
+// pool_n is read atomically (other workgroups of the launch added to it).
+__device__ void finish_stop(const Job *J, JobState *st, uint32_t pool_n)
 {
     const uint32_t pn = pool_n < J->cap ? pool_n : J->cap;
     const uint32_t gen = pn > st->pool_base ? pn - st->pool_base : 0u;
@@ -526,38 +562,30 @@ __device__ void advance_job(const Job *J, JobState *st, uint32_t pool_n)
     }
     if (st->epoch >= 1u && st->epoch - 1u < J->trace_cap)
         J->trace[st->epoch - 1u].generated = gen;
-    // stops the new live set certainly needs: the survivors' remaining
-    // stops, or a full pass for a candidate created at the last stop
-    const uint32_t need = gen ? J->stop_max : st->max_rem;
-    if (st->k_next + gen == 0) {
+    const uint32_t K = st->k_next + gen;
+    st->K = K;
+    if (K == 0) {
         st->done = 1;
-        st->K = 0;
         st->need = 0;
         return;
     }
-    const uint32_t K = st->k_next + gen;
-    st->K = K;
-    st->need = need;
+    // stops the new live set certainly needs: a full pass for a created
+    // candidate, else the survivors' remaining stops (from the last Prune)
+    st->need = gen ? J->stop_max : st->max_rem;
+    st->ks = st->k_next;  // counted already, by X
     st->pool_base = pn;
     st->k_next = 0;
     st->n_new = 0;
-    st->parity ^= 1u;
     st->max_rem = 0;
-    const uint32_t stop = st->stop % J->stop_max + 1u;
-    st->stop = stop;
+    st->parity ^= 1u;
     st->epoch += 1u;
-    const uint64_t first = (uint64_t)(stop - 1u) * J->Mp;
-    const uint64_t end = (uint64_t)stop * J->Mp;
-    const uint64_t last = end < J->n ? end : J->n;
-    st->first = (uint32_t)first;
-    st->last = (uint32_t)last;
-    const uint32_t rows = (uint32_t)(last - first);
+    const uint32_t rows = st->last - st->first;
     st->tests += (unsigned long long)K * rows;
     if (K > st->peak_K)
         st->peak_K = K;
     if (st->epoch - 1u < J->trace_cap) {
         dic_stop_trace t;
-        t.stop = stop;
+        t.stop = st->stop;
         t.rows = rows;
         t.live = K;
         t.promoted = t.pruned = t.generated = t.solidified = t.words = t.items = 0;
@@ -566,19 +594,22 @@ __device__ void advance_job(const Job *J, JobState *st, uint32_t pool_n)
     }
 }
 
-// Plan the count and epilogue work of a job's current stop (a function of
-// its state and the knobs).  Returns the work items of the row count, the
-// bitset count and the epilogue.
-__device__ void plan_job(const Job *J, JobState *st, const Plan *plan, uint32_t *items,
-                         uint32_t *itemsv, uint32_t *epi)
+// Work of X for one job: chunks of MakeCandidates (WG (new box, item) pairs
+// each) and the counting work items of its survivors (k_next of them, in the
+// next list) on the current block, by layout.
+__device__ void plan_x(const Job *J, JobState *st, const Plan *plan, uint32_t *items,
+                       uint32_t *itemsv, unsigned long long *chunks)
 {
-    *items = *itemsv = *epi = 0;
-    if (st->done || st->overflow || st->K == 0)
+    *items = *itemsv = 0;
+    *chunks = 0;
+    if (st->done || st->overflow)
         return;
-    const uint32_t K = st->K;
+    *chunks = ((unsigned long long)st->n_new * st->nL1 + WG - 1u) / WG;
+    const uint32_t K = st->k_next;
+    if (K == 0)
+        return;
     const uint32_t first = st->first, last = st->last;
     const uint32_t rows = last - first;
-    *epi = (K + WG - 1u) / WG;
     if (J->layout == LAYOUT_VERTICAL && K < plan->vt_wave_k) {
         // few candidates: one wave per candidate, no tile
         st->fw = first >> 6;
@@ -624,6 +655,15 @@ __device__ void plan_job(const Job *J, JobState *st, const Plan *plan, uint32_t 
     }
 }
 
+// Work of Z for one job: chunks of WG survivors (counted by X), then groups
+// of WG/64 new candidates, one wave each.
+__device__ uint32_t plan_z(const JobState *st)
+{
+    if (st->done || st->overflow || st->K == 0)
+        return 0;
+    return (st->ks + WG - 1u) / WG + (st->K - st->ks + WG / 64 - 1u) / (WG / 64);
+}
+
 // Arrival counter of a launch, called by one thread per workgroup after the
 // workgroup's work: true for the workgroup that arrives last.  Two levels
 // (workgroups of a group of TICKET_GROUPS, then the groups) keep the atomics
@@ -645,54 +685,81 @@ __device__ bool arrive_last(uint32_t *tickets)
     return true;
 }
 
-// Begin the next stop for the jobs of the table and write the step's work
-// plan.  in_tail: run by the last workgroup of a candidate generation, which
-// advances every running job; otherwise (at the start of a chunk of stops)
-// only jobs not yet advanced since they were added move, and every job is
-// re-planned.  Every thread of the workgroup calls.
-__device__ void begin_jobs(const Job *__restrict__ jobs, Plan *plan, uint32_t *sh, bool in_tail)
+// Write per-job prefix sums of work: X (rows count, bitset count,
+// MakeCandidates chunks) or Z.  One workgroup, every thread calls; sh holds
+// 2 * (WG/64) words.
+__device__ void write_plan_x(const Job *__restrict__ jobs, Plan *plan, uint32_t *sh,
+                             unsigned long long *shc)
 {
     const uint32_t njobs = plan->njobs;
-    uint32_t carry_c = 0, carry_v = 0, carry_e = 0;
+    uint32_t carry_c = 0, carry_v = 0;
+    unsigned long long carry_g = 0;
     if (threadIdx.x == 0) {
         plan->pre_count[0] = 0;
         plan->pre_countv[0] = 0;
-        plan->pre_epi[0] = 0;
+        plan->pre_cg[0] = 0;
     }
     for (uint32_t b = 0; b < njobs; b += WG) {
         const uint32_t j = b + threadIdx.x;
-        uint32_t items = 0, itemsv = 0, epi = 0;
-        if (j < njobs) {
-            const Job *J = jobs + j;
-            JobState *st = J->st;
-            if (!st->done && !st->overflow && (in_tail || st->pending)) {
-                const uint32_t pool_n =
-                    in_tail ? __hip_atomic_load(&st->pool_n, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT)
-                            : st->pool_n;
-                advance_job(J, st, pool_n);
-                st->pending = 0;
-            }
-            plan_job(J, st, plan, &items, &itemsv, &epi);
-        }
-        uint32_t v[3] = {items, itemsv, epi}, t[3];
-        block_scan3(v, sh, t);
+        uint32_t items = 0, itemsv = 0;
+        unsigned long long chunks = 0;
+        if (j < njobs)
+            plan_x(jobs + j, jobs[j].st, plan, &items, &itemsv, &chunks);
+        uint32_t v[2] = {items, itemsv}, t[2];
+        block_scan_n<2>(v, sh, t);
+        unsigned long long tg;
+        const unsigned long long g = block_scan_incl<unsigned long long>(chunks, shc, &tg);
         if (j < njobs) {
             plan->pre_count[j + 1] = carry_c + v[0];
             plan->pre_countv[j + 1] = carry_v + v[1];
-            plan->pre_epi[j + 1] = carry_e + v[2];
+            plan->pre_cg[j + 1] = carry_g + g;
         }
         carry_c += t[0];
         carry_v += t[1];
-        carry_e += t[2];
+        carry_g += tg;
     }
 }
 
-// Standalone begin, once at the start of a chunk of stops.  One workgroup.
+__device__ void write_plan_z(const Job *__restrict__ jobs, Plan *plan, uint32_t *sh)
+{
+    const uint32_t njobs = plan->njobs;
+    uint32_t carry = 0;
+    if (threadIdx.x == 0)
+        plan->pre_epi[0] = 0;
+    for (uint32_t b = 0; b < njobs; b += WG) {
+        const uint32_t j = b + threadIdx.x;
+        uint32_t v[1] = {j < njobs ? plan_z(jobs[j].st) : 0u}, t[1];
+        block_scan_n<1>(v, sh, t);
+        if (j < njobs)
+            plan->pre_epi[j + 1] = carry + v[0];
+        carry += t[0];
+    }
+}
+
+// Start of a chunk of stops (one workgroup).  A job added since the last
+// chunk has its first candidates in the next live list: they become its
+// survivors (counted by X like any), and it moves to its first block.  Every
+// job is then planned for X against the current job table.
 __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan *plan)
 {
-    __shared__ uint32_t sh[WG];
-    begin_jobs(jobs, plan, sh, false);
+    __shared__ uint32_t sh[2 * (WG / 64)];
+    __shared__ unsigned long long shc[WG / 64];
+    for (uint32_t j = threadIdx.x; j < plan->njobs; j += WG) {
+        JobState *st = jobs[j].st;
+        if (st->pending && !st->done && !st->overflow) {
+            const uint32_t pn = st->pool_n < jobs[j].cap ? st->pool_n : jobs[j].cap;
+            st->k_next = pn;  // every first candidate, in the next list
+            st->pool_base = pn;
+            st->n_new = 0;
+            st->max_rem = 0;
+            st->need = 0;
+            to_next_block(jobs + j, st);
+            st->need = jobs[j].stop_max;  // they need a full pass
+            st->pending = 0;
+        }
+    }
+    __syncthreads();
+    write_plan_x(jobs, plan, sh, shc);
 }
 
 // CountSupport (Algorithm 3).  Work item = (row range, group of CAND_PER_WG
@@ -722,8 +789,9 @@ __global__ __launch_bounds__(WG) void k_count(const Job *__restrict__ jobs,
         const uint32_t r_begin = st->first + ri * st->rpi;
         const uint32_t r_lim = r_begin + st->rpi;
         const uint32_t r_end = r_lim < st->last ? r_lim : st->last;
-        const uint32_t K = st->K;
-        const uint32_t *live = st->parity ? J->live1 : J->live0;
+        // X counts the survivors of the last stop, at the head of the next list
+        const uint32_t K = st->k_next;
+        const uint32_t *live = st->parity ? J->live0 : J->live1;
         const uint32_t c0 = ct * CAND_PER_WG + wave * CW;
 
         uint32_t pidx[CW];
@@ -808,250 +876,349 @@ __global__ __launch_bounds__(WG) void k_count(const Job *__restrict__ jobs,
 // tests 64 transactions at once.  Lanes of a wave mostly share all but one
 // item (candidates are appended per generating itemset), so most tile reads
 // are broadcasts.
-__global__ __launch_bounds__(WG) void k_count_vert(const Job *__restrict__ jobs,
-                                                   const Plan *__restrict__ plan)
+// CountSupport of candidate p by one wave over every 64-row word of the
+// current block, straight from the item bitsets (no tile).  Returns the
+// count in every lane.
+__device__ __forceinline__ uint32_t count_wave_bitsets(const Job *J, const JobState *st, uint32_t p)
 {
-    __shared__ uint64_t tile[VT_WORDS];
-    const uint32_t total = plan->pre_countv[plan->njobs];
-    for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
-        const uint32_t j = find_job(plan->pre_countv, plan->njobs, it);
-        const Job *J = jobs + j;
-        const JobState *st = J->st;
-        const uint32_t local = it - plan->pre_countv[j];
-        if (st->cmode == 1) {
-            // wave mode: this wave owns candidate c over every word of the block
-            const uint32_t c = local * (WG / 64) + (threadIdx.x >> 6);
-            if (c >= st->K)
-                continue;
-            const uint32_t lane = threadIdx.x & 63u;
-            const uint32_t p =
-                __builtin_amdgcn_readfirstlane((st->parity ? J->live1 : J->live0)[c]);
-            const uint32_t k = J->pk[p];
-            const uint64_t lo_mask = ~0ull << (st->first & 63u);
-            const uint64_t hi_mask =
-                (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
-            const uint32_t nw = J->nw;
-            uint32_t cnt = 0;
-            if (k <= (uint32_t)KD) {
-                // item rows from the candidate's item list: the loads of all
-                // its items for a word are independent
-                uint32_t iw[KD / 2];
-                load_items(J->pitems + (uint64_t)p * KD, iw);
-                uint32_t row[KD];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t k = J->pk[p];
+    const uint64_t lo_mask = ~0ull << (st->first & 63u);
+    const uint64_t hi_mask =
+        (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
+    const uint32_t nw = J->nw;
+    uint32_t cnt = 0;
+    if (k <= (uint32_t)KD) {
+        // item rows from the candidate's item list: the loads of all
+        // its items for a word are independent
+        uint32_t iw[KD / 2];
+        load_items(J->pitems + (uint64_t)p * KD, iw);
+        uint32_t row[KD];
 #pragma unroll
-                for (int t = 0; t < KD; ++t)
-                    row[t] = (uint32_t)t < k ? J->l1[item_at(iw, t)] : 0u;
-                for (uint32_t w = st->fw + lane; w <= st->lw; w += 64) {
-                    uint64_t acc =
-                        (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull);
+        for (int t = 0; t < KD; ++t)
+            row[t] = (uint32_t)t < k ? J->l1[item_at(iw, t)] : 0u;
+        for (uint32_t w = st->fw + lane; w <= st->lw; w += 64) {
+            uint64_t acc =
+                (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull);
 #pragma unroll
-                    for (int t = 0; t < KD; ++t)
-                        if ((uint32_t)t < k)
-                            acc &= J->vert[(uint64_t)row[t] * nw + w];
-                    cnt += (uint32_t)__popcll(acc);
-                }
-            } else {
-                const uint64_t nz = J->pnz[p];
-                const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
-                for (uint32_t w = st->fw + lane; w <= st->lw; w += 64) {
-                    uint64_t acc =
-                        (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull);
-                    uint64_t nzw = nz;
-                    while (nzw) {
-                        const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
-                        nzw &= nzw - 1;
-                        uint64_t bits = cm[wd];
-                        while (bits) {
-                            const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
-                            bits &= bits - 1;
-                            acc &= J->vert[(uint64_t)item * nw + w];
-                        }
-                    }
-                    cnt += (uint32_t)__popcll(acc);
+            for (int t = 0; t < KD; ++t)
+                if ((uint32_t)t < k)
+                    acc &= J->vert[(uint64_t)row[t] * nw + w];
+            cnt += (uint32_t)__popcll(acc);
+        }
+    } else {
+        const uint64_t nz = J->pnz[p];
+        const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+        for (uint32_t w = st->fw + lane; w <= st->lw; w += 64) {
+            uint64_t acc =
+                (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull);
+            uint64_t nzw = nz;
+            while (nzw) {
+                const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
+                nzw &= nzw - 1;
+                uint64_t bits = cm[wd];
+                while (bits) {
+                    const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    acc &= J->vert[(uint64_t)item * nw + w];
                 }
             }
-            for (int off = 32; off > 0; off >>= 1)
-                cnt += (uint32_t)__shfl_xor((int)cnt, off);
-            if (lane == 0 && cnt)
-                J->psupp[p] += cnt;  // the only writer of this candidate's count
-            continue;
+            cnt += (uint32_t)__popcll(acc);
         }
-        const uint32_t n_cg = st->n_ct;
-        const uint32_t rc = local / n_cg;
-        const uint32_t cg = local - rc * n_cg;
-        const uint32_t tw = st->tw, ts = vert_tile_stride(tw);
-        const uint32_t fw = st->fw, lw = st->lw, nL1 = st->nL1;
-        const uint32_t ntile = (lw - fw + tw) / tw;
-        const uint32_t t0 = rc * st->rpi;
-        const uint32_t t1 = t0 + st->rpi < ntile ? t0 + st->rpi : ntile;
-        const uint64_t lo_mask = ~0ull << (st->first & 63u);
-        const uint64_t hi_mask = (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
-        const uint32_t K = st->K;
-        const uint32_t cpt = st->cpt;
-        const uint32_t *live = st->parity ? J->live1 : J->live0;
-        uint32_t pidx[VT_CPT], cnt[VT_CPT];
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        cnt += (uint32_t)__shfl_xor((int)cnt, off);
+    return cnt;
+}
+
+// CountSupport (Algorithm 3) on item bitsets, one work item of X: the
+// survivors of the last stop (head of the next live list) on the current
+// block.  Work item = (group of WG candidates, chunk of tiles).  A tile
+// holds, for every frequent item, its bitset over tw consecutive 64-row
+// words of the block (edge words masked to the block).  Each thread owns
+// cpt candidates: it ANDs the tile rows of each candidate's items word by
+// word and popcounts the result, so a 64-bit AND tests 64 transactions at
+// once.  With few candidates (wave mode) one wave counts each candidate
+// with no tile.  Every thread of the workgroup calls.
+__device__ __forceinline__ void count_vert_item(const Job *J, const JobState *st, uint32_t local, uint64_t *tile)
+{
+    if (st->cmode == 1) {
+        const uint32_t c = local * (WG / 64) + (threadIdx.x >> 6);
+        if (c < st->k_next) {
+            const uint32_t p =
+                __builtin_amdgcn_readfirstlane((st->parity ? J->live0 : J->live1)[c]);
+            const uint32_t cnt = count_wave_bitsets(J, st, p);
+            if ((threadIdx.x & 63u) == 0 && cnt)
+                J->psupp[p] += cnt;  // the only writer of this candidate's count
+        }
+        return;
+    }
+    const uint32_t n_cg = st->n_ct;
+    const uint32_t rc = local / n_cg;
+    const uint32_t cg = local - rc * n_cg;
+    const uint32_t tw = st->tw, ts = vert_tile_stride(tw);
+    const uint32_t fw = st->fw, lw = st->lw, nL1 = st->nL1;
+    const uint32_t ntile = (lw - fw + tw) / tw;
+    const uint32_t t0 = rc * st->rpi;
+    const uint32_t t1 = t0 + st->rpi < ntile ? t0 + st->rpi : ntile;
+    const uint64_t lo_mask = ~0ull << (st->first & 63u);
+    const uint64_t hi_mask = (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
+    const uint32_t K = st->k_next;  // survivors, at the head of the next list
+    const uint32_t cpt = st->cpt;
+    const uint32_t *live = st->parity ? J->live0 : J->live1;
+    uint32_t pidx[VT_CPT], cnt[VT_CPT];
+#pragma unroll
+    for (int q = 0; q < VT_CPT; ++q) {
+        const uint32_t c = (cg * cpt + (uint32_t)q) * WG + threadIdx.x;
+        pidx[q] = ((uint32_t)q < cpt && c < K) ? live[c] : NONE;
+        cnt[q] = 0;
+    }
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t w0 = fw + t * tw;
+        const uint32_t nwt = (lw + 1u - w0) < tw ? (lw + 1u - w0) : tw;
+        __syncthreads();
+        // thread (q, r) loads word r of items q, q + per, q + 2 per, ...
+        const uint32_t per = WG / nwt;
+        const uint32_t q = threadIdx.x / nwt, r = threadIdx.x - q * nwt;
+        if (q < per) {
+            const uint32_t g = w0 + r;
+            const uint64_t mask = (g == fw ? lo_mask : ~0ull) & (g == lw ? hi_mask : ~0ull);
+#pragma unroll 4
+            for (uint32_t a = q; a < nL1; a += per)
+                tile[a * ts + r] = J->vert[(uint64_t)J->l1[a] * J->nw + g] & mask;
+        }
+        __syncthreads();
 #pragma unroll
         for (int q = 0; q < VT_CPT; ++q) {
-            const uint32_t c = (cg * cpt + (uint32_t)q) * WG + threadIdx.x;
-            pidx[q] = ((uint32_t)q < cpt && c < K) ? live[c] : NONE;
-            cnt[q] = 0;
-        }
-        for (uint32_t t = t0; t < t1; ++t) {
-            const uint32_t w0 = fw + t * tw;
-            const uint32_t nwt = (lw + 1u - w0) < tw ? (lw + 1u - w0) : tw;
-            __syncthreads();
-            // thread (q, r) loads word r of items q, q + per, q + 2 per, ...
-            const uint32_t per = WG / nwt;
-            const uint32_t q = threadIdx.x / nwt, r = threadIdx.x - q * nwt;
-            if (q < per) {
-                const uint32_t g = w0 + r;
-                const uint64_t mask = (g == fw ? lo_mask : ~0ull) & (g == lw ? hi_mask : ~0ull);
-#pragma unroll 4
-                for (uint32_t a = q; a < nL1; a += per)
-                    tile[a * ts + r] = J->vert[(uint64_t)J->l1[a] * J->nw + g] & mask;
-            }
-            __syncthreads();
+            const uint32_t p = pidx[q];
+            if (p == NONE)
+                continue;
+            uint64_t acc[VT_MAXW];
 #pragma unroll
-            for (int q = 0; q < VT_CPT; ++q) {
-                const uint32_t p = pidx[q];
-                if (p == NONE)
-                    continue;
-                uint64_t acc[VT_MAXW];
+            for (int w = 0; w < VT_MAXW; ++w)
+                acc[w] = ~0ull;
+            const uint32_t k = J->pk[p];
+            if (k <= (uint32_t)KD) {
+                // the candidate's frequent-item indices, 16 x u16
+                const uint4 *ip = (const uint4 *)(J->pitems + (uint64_t)p * KD);
+                const uint4 h0 = ip[0], h1 = ip[1];
+                const uint32_t pk32[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
 #pragma unroll
-                for (int w = 0; w < VT_MAXW; ++w)
-                    acc[w] = ~0ull;
-                const uint32_t k = J->pk[p];
-                if (k <= (uint32_t)KD) {
-                    // the candidate's frequent-item indices, 16 x u16
-                    const uint4 *ip = (const uint4 *)(J->pitems + (uint64_t)p * KD);
-                    const uint4 h0 = ip[0], h1 = ip[1];
-                    const uint32_t pk32[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+                for (int t = 0; t < KD; ++t) {
+                    if ((uint32_t)t < k) {
+                        const uint32_t idx = (pk32[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
+                        const uint64_t *row = tile + idx * ts;
 #pragma unroll
-                    for (int t = 0; t < KD; ++t) {
-                        if ((uint32_t)t < k) {
-                            const uint32_t idx = (pk32[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
-                            const uint64_t *row = tile + idx * ts;
-#pragma unroll
-                            for (int w = 0; w < VT_MAXW; ++w)
-                                if ((uint32_t)w < nwt)
-                                    acc[w] &= row[w];
-                        }
-                    }
-                } else {
-                    uint64_t nzw = J->pnz[p];
-                    const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
-                    while (nzw) {
-                        const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
-                        nzw &= nzw - 1;
-                        uint64_t bits = cm[wd];
-                        while (bits) {
-                            const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
-                            bits &= bits - 1;
-                            const uint64_t *row = tile + J->l1pos[item] * ts;
-#pragma unroll
-                            for (int w = 0; w < VT_MAXW; ++w)
-                                if ((uint32_t)w < nwt)
-                                    acc[w] &= row[w];
-                        }
+                        for (int w = 0; w < VT_MAXW; ++w)
+                            if ((uint32_t)w < nwt)
+                                acc[w] &= row[w];
                     }
                 }
-                uint32_t sum = 0;
+            } else {
+                uint64_t nzw = J->pnz[p];
+                const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+                while (nzw) {
+                    const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
+                    nzw &= nzw - 1;
+                    uint64_t bits = cm[wd];
+                    while (bits) {
+                        const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
+                        bits &= bits - 1;
+                        const uint64_t *row = tile + J->l1pos[item] * ts;
 #pragma unroll
-                for (int w = 0; w < VT_MAXW; ++w)
-                    if ((uint32_t)w < nwt)
-                        sum += (uint32_t)__popcll(acc[w]);
-                cnt[q] += sum;
+                        for (int w = 0; w < VT_MAXW; ++w)
+                            if ((uint32_t)w < nwt)
+                                acc[w] &= row[w];
+                    }
+                }
+            }
+            uint32_t sum = 0;
+#pragma unroll
+            for (int w = 0; w < VT_MAXW; ++w)
+                if ((uint32_t)w < nwt)
+                    sum += (uint32_t)__popcll(acc[w]);
+            cnt[q] += sum;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < VT_CPT; ++q)
+        if (pidx[q] != NONE && cnt[q])
+            atomicAdd(J->psupp + pidx[q], cnt[q]);
+}
+
+// Prune (Algorithm 4) and CheckFullPass (Algorithm 5) for live candidate p
+// (when valid) whose support after this stop's count is supp.  It is counted
+// for stop_I += 1 here (Algorithm 3's first line).  Survivors go to the next
+// live list and new boxes to the promoted list; appends and statistics are
+// aggregated over the workgroup (one atomic per counter), so every thread of
+// the workgroup calls.
+__device__ void prune_and_check(const Job *J, JobState *st, bool valid, uint32_t p, uint32_t supp,
+                                uint32_t *sh_app, uint32_t *sh_red)
+{
+    bool promoted = false, pruned = false, solid = false, keep = false;
+    uint32_t sc = 0, words = 0, items = 0;
+    if (valid) {
+        items = J->pk[p];
+        if (J->layout == LAYOUT_ROWS) {
+            // nonzero 32-bit words of this candidate: its AND work per row
+            uint64_t nzw = J->pnz[p];
+            const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+            while (nzw) {
+                const uint64_t v = cm[__builtin_ctzll(nzw)];
+                nzw &= nzw - 1;
+                words += ((uint32_t)v != 0u) + ((uint32_t)(v >> 32) != 0u);
             }
         }
-#pragma unroll
-        for (int q = 0; q < VT_CPT; ++q)
-            if (pidx[q] != NONE && cnt[q])
-                atomicAdd(J->psupp + pidx[q], cnt[q]);
+        sc = J->pstop[p] + 1u;
+        J->pstop[p] = sc;
+        uint32_t state = J->pstate[p];
+        if (state == ST_DASHED_CIRCLE) {
+            if (supp >= J->tau) {
+                state = ST_DASHED_BOX;
+                J->ppromo[p] = st->epoch;
+                promoted = true;
+            } else if ((uint64_t)supp + (uint64_t)J->Mp * (uint64_t)(J->stop_max - sc) <
+                       (uint64_t)J->tau) {
+                state = ST_PRUNED;
+                pruned = true;
+            }
+        }
+        if (!pruned) {
+            if (sc == J->stop_max) {
+                solid = true;
+                state = state == ST_DASHED_BOX ? ST_SOLID_BOX : ST_SOLID_CIRCLE;
+            } else {
+                keep = true;
+            }
+        }
+        J->pstate[p] = state;
+    }
+    uint32_t *next = st->parity ? J->live0 : J->live1;
+    uint32_t pos, npos;
+    block_append2(&st->k_next, keep, promoted, sh_app, &pos, &npos);
+    if (keep)
+        next[pos] = p;
+    if (promoted)
+        J->newbox[npos] = p;
+    uint32_t v[6] = {words, items, promoted ? 1u : 0u, pruned ? 1u : 0u, solid ? 1u : 0u,
+                     keep ? J->stop_max - sc : 0u};
+    block_reduce<5>(v, sh_red);
+    if (threadIdx.x == 0) {
+        dic_stop_trace *tr = trace_of(J, st);
+        if (tr) {
+            atomicAdd(&tr->words, v[0]);
+            atomicAdd(&tr->items, v[1]);
+            if (v[2])
+                atomicAdd(&tr->promoted, v[2]);
+            if (v[3])
+                atomicAdd(&tr->pruned, v[3]);
+            if (v[4])
+                atomicAdd(&tr->solidified, v[4]);
+        }
+        if (v[5])
+            atomicMax(&st->max_rem, v[5]);
     }
 }
 
-// Prune (Algorithm 4) and CheckFullPass (Algorithm 5) for every live
-// candidate, plus the compaction of survivors into the next live list.
-// Candidates are counted for stop_I += 1 here (Algorithm 3's first line).
-// Work item = (job, chunk of WG candidates); appends and statistics are
-// aggregated per workgroup (one atomic per counter per workgroup).
-__global__ __launch_bounds__(WG) void k_epilogue(const Job *__restrict__ jobs,
-                                                 const Plan *__restrict__ plan)
+// CountSupport of a candidate by one wave over the current block in row
+// bitmaps: lanes take rows, each testing (row & I) == I on I's nonzero words.
+__device__ uint32_t count_wave_rows(const Job *J, const JobState *st, uint32_t p)
+{
+    const uint32_t W = J->W, lane = threadIdx.x & 63u;
+    const uint64_t *I = J->pmask + (uint64_t)p * W;
+    const uint64_t nz = J->pnz[p];
+    uint32_t cnt = 0;
+    for (uint32_t r = st->first + lane; r < st->last; r += 64u) {
+        const uint64_t *row = J->rows + (uint64_t)r * W;
+        bool in = true;
+        uint64_t nzw = nz;
+        while (nzw && in) {
+            const uint32_t w = (uint32_t)__builtin_ctzll(nzw);
+            nzw &= nzw - 1;
+            in = (row[w] & I[w]) == I[w];
+        }
+        cnt += in ? 1u : 0u;
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        cnt += (uint32_t)__shfl_xor((int)cnt, off);
+    return cnt;
+}
+
+// Z: Prune and CheckFullPass of every candidate of the stop.  Work items of a
+// job: chunks of WG survivors (counted by X), then groups of WG/64 candidates
+// created at the last stop, which one wave each counts on the block first.
+// The last workgroup to finish moves every job to its next block and plans X.
+__global__ __launch_bounds__(WG) void k_stepz(const Job *__restrict__ jobs, Plan *plan)
 {
     __shared__ uint32_t sh_app[2 * (WG / 64) + 2];
     __shared__ uint32_t sh_red[6 * (WG / 64)];
+    __shared__ uint32_t sh_supp[WG / 64];
+    __shared__ unsigned long long shc[WG / 64];
+    __shared__ uint32_t sh_last;
     const uint32_t total = plan->pre_epi[plan->njobs];
     for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
         const uint32_t j = find_job(plan->pre_epi, plan->njobs, it);
         const Job *J = jobs + j;
         JobState *st = J->st;
-        const uint32_t c = (it - plan->pre_epi[j]) * WG + threadIdx.x;
-        const bool valid = c < st->K;
-        bool promoted = false, pruned = false, solid = false, keep = false;
-        uint32_t p = 0, sc = 0, words = 0, items = 0;
-        if (valid) {
-            p = (st->parity ? J->live1 : J->live0)[c];
-            items = J->pk[p];
-            if (J->layout == LAYOUT_ROWS) {
-                // nonzero 32-bit words of this candidate: its AND work per row
-                uint64_t nzw = J->pnz[p];
-                const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
-                while (nzw) {
-                    const uint64_t v = cm[__builtin_ctzll(nzw)];
-                    nzw &= nzw - 1;
-                    words += ((uint32_t)v != 0u) + ((uint32_t)(v >> 32) != 0u);
+        const uint32_t local = it - plan->pre_epi[j];
+        const uint32_t *cur = st->parity ? J->live1 : J->live0;
+        const uint32_t ks = st->ks, K = st->K;
+        const uint32_t nsc = (ks + WG - 1u) / WG;
+        if (local < nsc) {
+            const uint32_t c = local * WG + threadIdx.x;
+            const bool valid = c < ks;
+            const uint32_t p = valid ? cur[c] : 0u;
+            prune_and_check(J, st, valid, p, valid ? J->psupp[p] : 0u, sh_app, sh_red);
+        } else {
+            const uint32_t c0 = ks + (local - nsc) * (WG / 64);
+            const uint32_t wave = threadIdx.x >> 6;
+            if (c0 + wave < K) {
+                const uint32_t p = __builtin_amdgcn_readfirstlane(cur[c0 + wave]);
+                const uint32_t cnt = J->layout == LAYOUT_VERTICAL ? count_wave_bitsets(J, st, p)
+                                                                  : count_wave_rows(J, st, p);
+                if ((threadIdx.x & 63u) == 0) {
+                    const uint32_t supp = J->psupp[p] + cnt;  // the only writer
+                    J->psupp[p] = supp;
+                    sh_supp[wave] = supp;
                 }
             }
-            sc = J->pstop[p] + 1u;
-            J->pstop[p] = sc;
-            uint32_t state = J->pstate[p];
-            const uint32_t supp = J->psupp[p];
-            if (state == ST_DASHED_CIRCLE) {
-                if (supp >= J->tau) {
-                    state = ST_DASHED_BOX;
-                    J->ppromo[p] = st->epoch;
-                    promoted = true;
-                } else if ((uint64_t)supp + (uint64_t)J->Mp * (uint64_t)(J->stop_max - sc) <
-                           (uint64_t)J->tau) {
-                    state = ST_PRUNED;
-                    pruned = true;
-                }
-            }
-            if (!pruned) {
-                if (sc == J->stop_max) {
-                    solid = true;
-                    state = state == ST_DASHED_BOX ? ST_SOLID_BOX : ST_SOLID_CIRCLE;
-                } else {
-                    keep = true;
-                }
-            }
-            J->pstate[p] = state;
+            __syncthreads();
+            const bool valid = threadIdx.x < WG / 64 && c0 + threadIdx.x < K;
+            const uint32_t p = valid ? cur[c0 + threadIdx.x] : 0u;
+            prune_and_check(J, st, valid, p, valid ? sh_supp[threadIdx.x] : 0u, sh_app, sh_red);
         }
-        uint32_t *next = st->parity ? J->live0 : J->live1;
-        uint32_t pos, npos;
-        block_append2(&st->k_next, keep, promoted, sh_app, &pos, &npos);
-        if (keep)
-            next[pos] = p;
-        if (promoted)
-            J->newbox[npos] = p;
-        uint32_t v[6] = {words, items, promoted ? 1u : 0u, pruned ? 1u : 0u, solid ? 1u : 0u,
-                         keep ? J->stop_max - sc : 0u};
-        block_reduce<5>(v, sh_red);
-        if (threadIdx.x == 0) {
-            dic_stop_trace *tr = trace_of(J, st);
-            if (tr) {
-                atomicAdd(&tr->words, v[0]);
-                atomicAdd(&tr->items, v[1]);
-                if (v[2])
-                    atomicAdd(&tr->promoted, v[2]);
-                if (v[3])
-                    atomicAdd(&tr->pruned, v[3]);
-                if (v[4])
-                    atomicAdd(&tr->solidified, v[4]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        sh_last = arrive_last(plan->tickets);
+    __syncthreads();
+    if (sh_last) {
+        for (uint32_t j = threadIdx.x; j < plan->njobs; j += WG) {
+            JobState *st = jobs[j].st;
+            if (st->done || st->overflow)
+                continue;
+            // the survivor and new-box counts and the survivors' remaining
+            // stops were updated by atomics of this launch: read them at
+            // device scope (a cached copy of the state may predate them) and
+            // keep them for the plain reads below
+            const uint32_t kn = __hip_atomic_load(&st->k_next, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t nn = __hip_atomic_load(&st->n_new, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t mr = __hip_atomic_load(&st->max_rem, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            st->k_next = kn;
+            st->n_new = nn;
+            st->max_rem = mr;
+            if (kn == 0 && nn == 0) {
+                st->done = 1;  // no survivor and no new box: nothing left to count
+                st->need = 0;
+            } else {
+                to_next_block(jobs + j, st);
             }
-            if (v[5])
-                atomicMax(&st->max_rem, v[5]);
         }
+        __syncthreads();
+        write_plan_x(jobs, plan, sh_red, shc);
     }
 }
 
@@ -1225,131 +1392,141 @@ __device__ __forceinline__ bool subsets_are_boxes_wide(const Job *J, uint32_t p,
 // were all boxes before this stop was generated at an earlier stop).
 // Work item = (job, chunk of WG (new box, frequent item) pairs); every
 // workgroup derives the per-job prefix of chunks itself.
-__global__ __launch_bounds__(WG) void k_candgen(const Job *__restrict__ jobs, Plan *plan)
+// MakeCandidates for one chunk of WG (new box, frequent item) pairs of job J:
+// for each itemset S promoted at this stop and each frequent item i not in
+// S, C = S | {i} is admitted when every maximal proper subset of C is a box.
+// C is produced by exactly one of its newly promoted subsets C \\ {i}: the one
+// with the largest i, so no candidate is generated twice and no set of
+// already-known itemsets is needed (an itemset whose subsets were all boxes
+// before this stop was generated at an earlier stop).  Every thread of the
+// workgroup calls.
+__device__ __forceinline__ void candgen_chunk(const Job *J, unsigned long long chunk, uint32_t *sh_app)
 {
-    __shared__ unsigned long long pre[MAX_JOBS + 1];
-    __shared__ unsigned long long sh_scan[WG];
-    __shared__ uint32_t sh_app[WG / 64 + 1];
-    const uint32_t njobs = plan->njobs;
-    unsigned long long carry = 0;
-    if (threadIdx.x == 0)
-        pre[0] = 0;
-    for (uint32_t b = 0; b < njobs; b += WG) {
-        const uint32_t j = b + threadIdx.x;
-        unsigned long long v = 0;
-        if (j < njobs) {
-            const JobState *st = jobs[j].st;
-            if (!st->done && !st->overflow)
-                v = ((unsigned long long)st->n_new * st->nL1 + WG - 1u) / WG;
-        }
-        unsigned long long tot;
-        const unsigned long long incl = block_scan_incl<unsigned long long>(v, sh_scan, &tot);
-        if (j < njobs)
-            pre[j + 1] = carry + incl;
-        carry += tot;
-    }
-    __syncthreads();
-    const unsigned long long total = pre[njobs];
-    for (unsigned long long it = blockIdx.x; it < total; it += gridDim.x) {
-        const uint32_t j = find_job(pre, njobs, it);
-        const Job *J = jobs + j;
-        JobState *st = J->st;
-        const uint32_t W = J->W;
-        const uint32_t nL1 = st->nL1;
-        const uint32_t base = st->pool_base;
-        const unsigned long long x = (it - pre[j]) * WG + threadIdx.x;
-        const bool valid = x < (unsigned long long)st->n_new * nL1;
-        bool gen = false;
-        uint32_t p = 0, a = 0, k = 0;
-        unsigned long long hC = 0;
-        uint32_t sw[KD / 2];  // S's frequent-item indices, ascending (k <= KD)
-        uint32_t pos = 0;     // a's place in C = S | {a}
-        if (valid) {
-            const uint32_t q = (uint32_t)(x / nL1);
-            a = (uint32_t)(x % nL1);  // the new item, as a frequent-item index
-            p = J->newbox[q];
-            k = J->pk[p];
-            const unsigned long long hS = J->phash[p];
-            if (k <= (uint32_t)KD) {
-                load_items(J->pitems + (uint64_t)p * KD, sw);
-                // a's place in S's ascending list; a already in S: no extension
-                bool in = false;
+    JobState *st = J->st;
+    const uint32_t W = J->W;
+    const uint32_t nL1 = st->nL1;
+    const uint32_t base = st->pool_base;
+    const unsigned long long x = chunk * WG + threadIdx.x;
+    const bool valid = x < (unsigned long long)st->n_new * nL1;
+    bool gen = false;
+    uint32_t p = 0, a = 0, k = 0;
+    unsigned long long hC = 0;
+    uint32_t sw[KD / 2];  // S's frequent-item indices, ascending (k <= KD)
+    uint32_t pos = 0;     // a's place in C = S | {a}
+    if (valid) {
+        const uint32_t q = (uint32_t)(x / nL1);
+        a = (uint32_t)(x % nL1);  // the new item, as a frequent-item index
+        p = J->newbox[q];
+        k = J->pk[p];
+        const unsigned long long hS = J->phash[p];
+        if (k <= (uint32_t)KD) {
+            load_items(J->pitems + (uint64_t)p * KD, sw);
+            // a's place in S's ascending list; a already in S: no extension
+            bool in = false;
 #pragma unroll
-                for (int t = 0; t < KD; ++t)
-                    if ((uint32_t)t < k) {
-                        const uint32_t v = item_at(sw, t);
-                        pos += v < a ? 1u : 0u;
-                        in |= v == a;
-                    }
-                hC = hS ^ zob(a);
-                if (!in && k == 2u && !J->classic) {
-                    // C's other maximal subsets {s0, a} and {s1, a} are pair
-                    // candidates found at their lexicographic index (pairs
-                    // are created up front, except in classic mode)
-                    const uint32_t s0 = item_at(sw, 0), s1 = item_at(sw, 1);
-                    const uint32_t lo0 = s0 < a ? s0 : a, hi0 = s0 < a ? a : s0;
-                    const uint32_t lo1 = s1 < a ? s1 : a, hi1 = s1 < a ? a : s1;
-                    const uint32_t sub0 = lo0 * nL1 - lo0 * (lo0 + 1u) / 2u + (hi0 - lo0 - 1u);
-                    const uint32_t sub1 = lo1 * nL1 - lo1 * (lo1 + 1u) / 2u + (hi1 - lo1 - 1u);
-                    const uint32_t st0 = J->pstate[sub0], st1 = J->pstate[sub1];
-                    const uint32_t pr0 = J->ppromo[sub0], pr1 = J->ppromo[sub1];
-                    gen = (st0 == ST_DASHED_BOX || st0 == ST_SOLID_BOX) &&
-                          (st1 == ST_DASHED_BOX || st1 == ST_SOLID_BOX) &&
-                          // a subset dropping a larger item than a, promoted
-                          // at this stop, generates C instead
-                          !(s1 > a && pr0 == st->epoch) && !(s0 > a && pr1 == st->epoch);
-                } else if (!in) {
-                    gen = subsets_are_boxes(J, sw, k, a, pos, hC, base, st->epoch);
+            for (int t = 0; t < KD; ++t)
+                if ((uint32_t)t < k) {
+                    const uint32_t v = item_at(sw, t);
+                    pos += v < a ? 1u : 0u;
+                    in |= v == a;
                 }
-            } else {
-                hC = hS ^ zob(a);
-                gen = subsets_are_boxes_wide(J, p, k, a, hC, base, st->epoch);
+            hC = hS ^ zob(a);
+            if (!in && k == 2u && !J->classic) {
+                // C's other maximal subsets {s0, a} and {s1, a} are pair
+                // candidates found at their lexicographic index (pairs
+                // are created up front, except in classic mode)
+                const uint32_t s0 = item_at(sw, 0), s1 = item_at(sw, 1);
+                const uint32_t lo0 = s0 < a ? s0 : a, hi0 = s0 < a ? a : s0;
+                const uint32_t lo1 = s1 < a ? s1 : a, hi1 = s1 < a ? a : s1;
+                const uint32_t sub0 = lo0 * nL1 - lo0 * (lo0 + 1u) / 2u + (hi0 - lo0 - 1u);
+                const uint32_t sub1 = lo1 * nL1 - lo1 * (lo1 + 1u) / 2u + (hi1 - lo1 - 1u);
+                const uint32_t st0 = J->pstate[sub0], st1 = J->pstate[sub1];
+                const uint32_t pr0 = J->ppromo[sub0], pr1 = J->ppromo[sub1];
+                gen = (st0 == ST_DASHED_BOX || st0 == ST_SOLID_BOX) &&
+                      (st1 == ST_DASHED_BOX || st1 == ST_SOLID_BOX) &&
+                      // a subset dropping a larger item than a, promoted
+                      // at this stop, generates C instead
+                      !(s1 > a && pr0 == st->epoch) && !(s0 > a && pr1 == st->epoch);
+            } else if (!in) {
+                gen = subsets_are_boxes(J, sw, k, a, pos, hC, base, st->epoch);
             }
-        }
-        // New entries are pool slots [pool_base, pool_n); in the next live
-        // list they follow the survivors, at k_next + (slot - pool_base).
-        // Lookups in this launch never read them (see probe_list), so no
-        // fence is needed before publishing them in the hash table.
-        const uint32_t np = block_append(&st->pool_n, gen, sh_app);
-        const bool stored = gen && np < J->cap;
-        if (gen && !stored)
-            st->overflow = 1u;
-        if (stored) {
-            const uint32_t i = J->l1[a];
-            copy_words(J->pmask + (uint64_t)np * W, J->pmask + (uint64_t)p * W, W);
-            J->pmask[(uint64_t)np * W + (i >> 6)] |= 1ull << (i & 63u);
-            J->phash[np] = hC;
-            J->pnz[np] = J->pnz[p] | (1ull << (i >> 6));
-            J->pk[np] = k + 1u;
-            J->psupp[np] = 0;
-            J->pstop[np] = 0;
-            J->pstate[np] = ST_DASHED_CIRCLE;
-            J->ppromo[np] = NO_EPOCH;
-            if (k + 1u <= (uint32_t)KD) {
-                uint32_t w[KD / 2];
-#pragma unroll
-                for (int u = 0; u < KD / 2; ++u)
-                    w[u] = ((uint32_t)(2 * u) <= k ? c_item(sw, pos, a, 2 * u) : 0u) |
-                           (((uint32_t)(2 * u + 1) <= k ? c_item(sw, pos, a, 2 * u + 1) : 0u) << 16);
-                uint4 *ci = (uint4 *)(J->pitems + (uint64_t)np * KD);
-                ci[0] = make_uint4(w[0], w[1], w[2], w[3]);
-                ci[1] = make_uint4(w[4], w[5], w[6], w[7]);
-            }
-            hash_insert(J, hC, k + 1u, np);
-            uint32_t *next = st->parity ? J->live0 : J->live1;
-            next[st->k_next + (np - st->pool_base)] = np;
+        } else {
+            hC = hS ^ zob(a);
+            gen = subsets_are_boxes_wide(J, p, k, a, hC, base, st->epoch);
         }
     }
-    // The last workgroup to finish begins the next stop for every job (the
-    // state it needs was written by earlier kernels, except pool_n, which it
-    // reads atomically after all other workgroups took their ticket).
+    // New entries are pool slots [pool_base, pool_n); in the next live
+    // list they follow the survivors, at k_next + (slot - pool_base).
+    // Lookups in this launch never read them (see probe_list), so no
+    // fence is needed before publishing them in the hash table.
+    const uint32_t np = block_append(&st->pool_n, gen, sh_app);
+    const bool stored = gen && np < J->cap;
+    if (gen && !stored)
+        st->overflow = 1u;
+    if (stored) {
+        const uint32_t i = J->l1[a];
+        copy_words(J->pmask + (uint64_t)np * W, J->pmask + (uint64_t)p * W, W);
+        J->pmask[(uint64_t)np * W + (i >> 6)] |= 1ull << (i & 63u);
+        J->phash[np] = hC;
+        J->pnz[np] = J->pnz[p] | (1ull << (i >> 6));
+        J->pk[np] = k + 1u;
+        J->psupp[np] = 0;
+        J->pstop[np] = 0;
+        J->pstate[np] = ST_DASHED_CIRCLE;
+        J->ppromo[np] = NO_EPOCH;
+        if (k + 1u <= (uint32_t)KD) {
+            uint32_t w[KD / 2];
+#pragma unroll
+            for (int u = 0; u < KD / 2; ++u)
+                w[u] = ((uint32_t)(2 * u) <= k ? c_item(sw, pos, a, 2 * u) : 0u) |
+                       (((uint32_t)(2 * u + 1) <= k ? c_item(sw, pos, a, 2 * u + 1) : 0u) << 16);
+            uint4 *ci = (uint4 *)(J->pitems + (uint64_t)np * KD);
+            ci[0] = make_uint4(w[0], w[1], w[2], w[3]);
+            ci[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        }
+        hash_insert(J, hC, k + 1u, np);
+        uint32_t *next = st->parity ? J->live0 : J->live1;
+        next[st->k_next + (np - st->pool_base)] = np;
+    }
+}
+
+// X: MakeCandidates chunks of every job, then the bitset CountSupport work
+// items of every job's survivors (row-bitmap jobs are counted by k_count,
+// launched just before).  The last workgroup to finish completes the stop
+// for every job and plans Z.
+__global__ __launch_bounds__(WG) void k_stepx(const Job *__restrict__ jobs, Plan *plan)
+{
+    __shared__ uint64_t tile[VT_WORDS];
+    __shared__ uint32_t sh_app[WG / 64 + 1];
     __shared__ uint32_t sh_last;
+    const uint32_t njobs = plan->njobs;
+    const unsigned long long ncg = plan->pre_cg[njobs];
+    const unsigned long long total = ncg + plan->pre_countv[njobs];
+    for (unsigned long long it = blockIdx.x; it < total; it += gridDim.x) {
+        if (it < ncg) {
+            const uint32_t j = find_job(plan->pre_cg, njobs, it);
+            candgen_chunk(jobs + j, it - plan->pre_cg[j], sh_app);
+        } else {
+            const uint32_t v = (uint32_t)(it - ncg);
+            const uint32_t j = find_job(plan->pre_countv, njobs, v);
+            count_vert_item(jobs + j, jobs[j].st, v - plan->pre_countv[j], tile);
+        }
+    }
     __syncthreads();
     if (threadIdx.x == 0)
         sh_last = arrive_last(plan->tickets);
     __syncthreads();
-    if (sh_last)
-        begin_jobs(jobs, plan, (uint32_t *)sh_scan, true);
+    if (sh_last) {
+        for (uint32_t j = threadIdx.x; j < njobs; j += WG) {
+            JobState *st = jobs[j].st;
+            if (!st->done && !st->overflow)
+                finish_stop(jobs + j, st,
+                            __hip_atomic_load(&st->pool_n, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT));
+        }
+        __syncthreads();
+        write_plan_z(jobs, plan, (uint32_t *)tile);
+    }
 }
 
 // Gather solid boxes (the output L without its 1-itemsets).
@@ -1403,7 +1580,6 @@ __global__ __launch_bounds__(WG) void k_check_padding(const uint64_t *__restrict
 // ---------------------------------------------------------------------------
 namespace {
 constexpr uint32_t GRID_EPI = 512;
-constexpr uint32_t GRID_CG = 1024;
 
 uint32_t grid_for(unsigned long long work, uint32_t per, uint32_t cap)
 {
@@ -1455,16 +1631,15 @@ void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, bool rows, bo
                  uint32_t count_grid, hipEvent_t before, hipEvent_t after)
 {
     Plan *pl = const_cast<Plan *>(plan);
+    (void)vert;  // bitset counting is part of X; X runs for every table
     if (before)
         (void)hipEventRecord(before, s);
     if (rows)
         hipLaunchKernelGGL(k_count, dim3(count_grid), dim3(WG), 0, s, jobs, plan);
-    if (vert)
-        hipLaunchKernelGGL(k_count_vert, dim3(count_grid), dim3(WG), 0, s, jobs, plan);
+    hipLaunchKernelGGL(k_stepx, dim3(count_grid), dim3(WG), 0, s, jobs, pl);
     if (after)
         (void)hipEventRecord(after, s);
-    hipLaunchKernelGGL(k_epilogue, dim3(GRID_EPI), dim3(WG), 0, s, jobs, plan);
-    hipLaunchKernelGGL(k_candgen, dim3(GRID_CG), dim3(WG), 0, s, jobs, pl);
+    hipLaunchKernelGGL(k_stepz, dim3(GRID_EPI), dim3(WG), 0, s, jobs, pl);
 }
 
 void launch_collect(const Job *jobs, const Plan *, uint32_t njobs, hipStream_t s)
