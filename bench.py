@@ -96,12 +96,12 @@ def count_work(results, W, n_frequent_items, layout):
     return byt, ops, ms, launches
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_count_vert_quest_zipf_n1M_m1000_pmc.txt")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_stepx_quest_zipf_n1M_m1000_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1812_10959_amd", "csrc", "dic_kernels.hip")
 
 
 def measured_traffic():
-    """HBM bytes per k_count_vert launch from the committed rocprofv3 counter
+    """HBM bytes per k_stepx launch from the committed rocprofv3 counter
     runs (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None
     when the kernel source changed since the counters were taken."""
     import hashlib
@@ -113,7 +113,7 @@ def measured_traffic():
     if sha not in txt:
         return None
     for ln in txt.splitlines():
-        if ln.startswith("k_count_vert traffic_bytes_per_launch:"):
+        if ln.startswith("k_stepx traffic_bytes_per_launch:"):
             return float(ln.split(":")[1])
     return None
 
@@ -122,7 +122,7 @@ def roofline_entry(byt, ops, ms, launches):
     achieved_tops = ops / (ms * 1e-3) / 1e12 if ms else 0.0
     achieved_gbs = byt / (ms * 1e-3) / 1e9 if ms else 0.0
     return {
-        "kernel": "k_count_vert", "bound": "alu", "achieved": achieved_tops,
+        "kernel": "k_stepx", "bound": "alu", "achieved": achieved_tops,
         "peak": ALU_PEAK_TOPS, "unit": "Tops/s (int32 VALU lane-ops)",
         "frac": achieved_tops / ALU_PEAK_TOPS, "traffic": None,
         "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -179,7 +179,9 @@ def headline(dic, args, c):
         dic.dic_set_option("profile", 0)
         byt, ops, cms, launches = count_work(prof, W, n_freq_items, layout)
         entry = roofline_entry(byt, ops, cms, launches)
-        entry["kernel"] = "k_count_vert" if layout == 1 else "k_count"
+        # the timed launches: k_stepx (MakeCandidates + bitset CountSupport);
+        # with row bitmaps k_count runs first, between the same events
+        entry["kernel"] = "k_stepx" if layout == 1 else "k_count + k_stepx"
         entry["count_ms_per_step"] = cms / reps
         entry["mine_ms_per_step_profiled"] = pdt * 1e3
         entry["count_G_tests_per_s"] = st["tests"] / (cms / reps * 1e-3) / 1e9 if cms else 0.0

@@ -38,7 +38,7 @@ TUNING_JSON = os.path.join(HERE, "tuning.json")
 
 DEFAULTS = {"vt_target": 768, "vt_wave_k": 2048, "vt_tile_words": 16, "count_grid": 2048}
 GRID = {
-    "vt_target": (512, 768, 1024, 1536),
+    "vt_target": (384, 512, 640, 768, 1024),
     "vt_wave_k": (2048, 8192, 16384),
     "vt_tile_words": (8, 16),
     "count_grid": (1024, 2048),
