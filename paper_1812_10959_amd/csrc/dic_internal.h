@@ -43,9 +43,10 @@ enum : uint32_t { LAYOUT_ROWS = 0, LAYOUT_VERTICAL = 1 };
 // Words per frequent item in a vertical tile (the tile holds every frequent
 // item's bitset over those words) and the odd row stride that spreads the
 // items' words over the LDS banks.
-__host__ __device__ inline uint32_t vert_tile_words(uint32_t nL1, uint32_t max_words)
+__host__ __device__ inline uint32_t vert_tile_words(uint32_t nL1, uint32_t max_words,
+                                                    uint32_t capacity = VT_WORDS)
 {
-    uint32_t t = nL1 ? (uint32_t)VT_WORDS / nL1 : (uint32_t)VT_MAXW + 1u;
+    uint32_t t = nL1 ? capacity / nL1 : (uint32_t)VT_MAXW + 1u;
     t = t > 1u ? t - 1u : 1u;
     const uint32_t cap = max_words < (uint32_t)VT_MAXW ? max_words : (uint32_t)VT_MAXW;
     return t > cap ? cap : t;
@@ -63,6 +64,9 @@ struct Knobs {
 Knobs knobs();
 int set_knob(const char *name, int64_t value);
 __host__ __device__ inline uint32_t vert_tile_stride(uint32_t tw) { return tw | 1u; }
+// a tile of capacity c holds nL1 rows of stride vert_tile_stride(vert_tile_words(nL1, ., c))
+// whenever nL1 <= c: the count kernels' tile therefore covers any frequent-item count
+static_assert(VT_WORDS >= MAX_ITEMS, "the count tile must hold one word of every item");
 
 __host__ __device__ inline uint32_t row_tile_rows(uint32_t W)
 {
@@ -107,7 +111,9 @@ struct JobState {
     uint32_t pending;   // added, not yet moved to its first block
     uint32_t need;      // stops the current live set certainly still needs
     uint32_t ks;        // candidates at the head of the current list counted by X
-    uint32_t pad[3];
+    uint32_t zlane;     // the new candidates are many: Z counts them on LDS tiles
+    uint32_t ztw;       // words per item in those tiles
+    uint32_t pad[1];
 };
 static_assert(sizeof(JobState) == 128, "JobState is read back as 128-byte records");
 static_assert(offsetof(JobState, k_next) % 8 == 0, "k_next/n_new form one 64-bit word");

@@ -28,6 +28,9 @@ constexpr uint32_t FP_ROWS = 4096;       // first pass rows per workgroup item
 constexpr uint32_t FPV_WORDS = 4096;     // first pass (bitsets): words per work item
 constexpr int VT_CPT = 8;                // bitset count: candidates per thread at most
 constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr uint32_t Z_TILE_MIN = 1024;   // new candidates from which Z counts them on LDS tiles
+constexpr uint32_t Z_TILE_WORDS = 1536;  // 64-bit words of Z's tile (12 KiB): one word of
+                                         // every frequent item at least, when nL1 fits
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
@@ -552,7 +555,7 @@ __device__ void to_next_block(const Job *J, JobState *st)
 // Finish stop e after MakeCandidates: the created pool entries follow the
 // survivors in the list, which becomes the current list of stop e + 1.
 // pool_n is read atomically (other workgroups of the launch added to it).
-__device__ void finish_stop(const Job *J, JobState *st, uint32_t pool_n)
+__device__ void finish_stop(const Job *J, JobState *st, uint32_t pool_n, uint32_t tile_words)
 {
     const uint32_t pn = pool_n < J->cap ? pool_n : J->cap;
     const uint32_t gen = pn > st->pool_base ? pn - st->pool_base : 0u;
@@ -573,6 +576,11 @@ __device__ void finish_stop(const Job *J, JobState *st, uint32_t pool_n)
     // candidate, else the survivors' remaining stops (from the last Prune)
     st->need = gen ? J->stop_max : st->max_rem;
     st->ks = st->k_next;  // counted already, by X
+    // many new candidates: Z counts them one per thread on LDS tiles of the
+    // block (a wave each would read every item row from L2 per candidate)
+    st->zlane = (J->layout == LAYOUT_VERTICAL && gen >= Z_TILE_MIN &&
+                 st->nL1 <= Z_TILE_WORDS) ? 1u : 0u;
+    st->ztw = vert_tile_words(st->nL1, tile_words, Z_TILE_WORDS);
     st->pool_base = pn;
     st->k_next = 0;
     st->n_new = 0;
@@ -656,12 +664,14 @@ __device__ void plan_x(const Job *J, JobState *st, const Plan *plan, uint32_t *i
 }
 
 // Work of Z for one job: chunks of WG survivors (counted by X), then groups
-// of WG/64 new candidates, one wave each.
+// of new candidates: WG/64 of them, one wave each, or WG of them, one
+// thread each on LDS tiles, when there are at least Z_TILE_MIN.
 __device__ uint32_t plan_z(const JobState *st)
 {
     if (st->done || st->overflow || st->K == 0)
         return 0;
-    return (st->ks + WG - 1u) / WG + (st->K - st->ks + WG / 64 - 1u) / (WG / 64);
+    const uint32_t per = st->zlane ? WG : WG / 64;  // new candidates per work item
+    return (st->ks + WG - 1u) / WG + (st->K - st->ks + per - 1u) / per;
 }
 
 // Arrival counter of a launch, called by one thread per workgroup after the
@@ -931,6 +941,82 @@ __device__ __forceinline__ uint32_t count_wave_bitsets(const Job *J, const JobSt
     return cnt;
 }
 
+// Stage the tile of words [w0, w0 + nwt) of the current block: for every
+// frequent item a, its bitset words at tile[a * ts ...] (edge words masked to
+// the block).  Every thread of the workgroup calls; the barriers on both
+// sides keep the previous tile's readers and this tile's readers apart.
+__device__ __forceinline__ void stage_tile(const Job *J, const JobState *st, uint32_t w0,
+                                           uint32_t nwt, uint32_t ts, uint64_t *tile)
+{
+    const uint32_t fw = st->fw, lw = st->lw, nL1 = st->nL1;
+    const uint64_t lo_mask = ~0ull << (st->first & 63u);
+    const uint64_t hi_mask = (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
+    __syncthreads();
+    // thread (q, r) loads word r of items q, q + per, q + 2 per, ...
+    const uint32_t per = WG / nwt;
+    const uint32_t q = threadIdx.x / nwt, r = threadIdx.x - q * nwt;
+    if (q < per) {
+        const uint32_t g = w0 + r;
+        const uint64_t mask = (g == fw ? lo_mask : ~0ull) & (g == lw ? hi_mask : ~0ull);
+#pragma unroll 4
+        for (uint32_t a = q; a < nL1; a += per)
+            tile[a * ts + r] = J->vert[(uint64_t)J->l1[a] * J->nw + g] & mask;
+    }
+    __syncthreads();
+}
+
+// Transactions of a staged tile (nwt words) that contain candidate p: the
+// AND of its items' tile rows, popcounted.
+__device__ __forceinline__ uint32_t and_tile(const Job *J, uint32_t p, const uint64_t *tile,
+                                             uint32_t ts, uint32_t nwt)
+{
+    uint64_t acc[VT_MAXW];
+#pragma unroll
+    for (int w = 0; w < VT_MAXW; ++w)
+        acc[w] = ~0ull;
+    const uint32_t k = J->pk[p];
+    if (k <= (uint32_t)KD) {
+        // the candidate's frequent-item indices, 16 x u16
+        const uint4 *ip = (const uint4 *)(J->pitems + (uint64_t)p * KD);
+        const uint4 h0 = ip[0], h1 = ip[1];
+        const uint32_t pk32[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+#pragma unroll
+        for (int t = 0; t < KD; ++t) {
+            if ((uint32_t)t < k) {
+                const uint32_t idx = (pk32[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
+                const uint64_t *row = tile + idx * ts;
+#pragma unroll
+                for (int w = 0; w < VT_MAXW; ++w)
+                    if ((uint32_t)w < nwt)
+                        acc[w] &= row[w];
+            }
+        }
+    } else {
+        uint64_t nzw = J->pnz[p];
+        const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+        while (nzw) {
+            const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
+            nzw &= nzw - 1;
+            uint64_t bits = cm[wd];
+            while (bits) {
+                const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
+                bits &= bits - 1;
+                const uint64_t *row = tile + J->l1pos[item] * ts;
+#pragma unroll
+                for (int w = 0; w < VT_MAXW; ++w)
+                    if ((uint32_t)w < nwt)
+                        acc[w] &= row[w];
+            }
+        }
+    }
+    uint32_t sum = 0;
+#pragma unroll
+    for (int w = 0; w < VT_MAXW; ++w)
+        if ((uint32_t)w < nwt)
+            sum += (uint32_t)__popcll(acc[w]);
+    return sum;
+}
+
 // CountSupport (Algorithm 3) on item bitsets, one work item of X: the
 // survivors of the last stop (head of the next live list) on the current
 // block.  Work item = (group of WG candidates, chunk of tiles).  A tile
@@ -957,12 +1043,10 @@ __device__ __forceinline__ void count_vert_item(const Job *J, const JobState *st
     const uint32_t rc = local / n_cg;
     const uint32_t cg = local - rc * n_cg;
     const uint32_t tw = st->tw, ts = vert_tile_stride(tw);
-    const uint32_t fw = st->fw, lw = st->lw, nL1 = st->nL1;
+    const uint32_t fw = st->fw, lw = st->lw;
     const uint32_t ntile = (lw - fw + tw) / tw;
     const uint32_t t0 = rc * st->rpi;
     const uint32_t t1 = t0 + st->rpi < ntile ? t0 + st->rpi : ntile;
-    const uint64_t lo_mask = ~0ull << (st->first & 63u);
-    const uint64_t hi_mask = (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
     const uint32_t K = st->k_next;  // survivors, at the head of the next list
     const uint32_t cpt = st->cpt;
     const uint32_t *live = st->parity ? J->live0 : J->live1;
@@ -976,69 +1060,11 @@ __device__ __forceinline__ void count_vert_item(const Job *J, const JobState *st
     for (uint32_t t = t0; t < t1; ++t) {
         const uint32_t w0 = fw + t * tw;
         const uint32_t nwt = (lw + 1u - w0) < tw ? (lw + 1u - w0) : tw;
-        __syncthreads();
-        // thread (q, r) loads word r of items q, q + per, q + 2 per, ...
-        const uint32_t per = WG / nwt;
-        const uint32_t q = threadIdx.x / nwt, r = threadIdx.x - q * nwt;
-        if (q < per) {
-            const uint32_t g = w0 + r;
-            const uint64_t mask = (g == fw ? lo_mask : ~0ull) & (g == lw ? hi_mask : ~0ull);
-#pragma unroll 4
-            for (uint32_t a = q; a < nL1; a += per)
-                tile[a * ts + r] = J->vert[(uint64_t)J->l1[a] * J->nw + g] & mask;
-        }
-        __syncthreads();
+        stage_tile(J, st, w0, nwt, ts, tile);
 #pragma unroll
-        for (int q = 0; q < VT_CPT; ++q) {
-            const uint32_t p = pidx[q];
-            if (p == NONE)
-                continue;
-            uint64_t acc[VT_MAXW];
-#pragma unroll
-            for (int w = 0; w < VT_MAXW; ++w)
-                acc[w] = ~0ull;
-            const uint32_t k = J->pk[p];
-            if (k <= (uint32_t)KD) {
-                // the candidate's frequent-item indices, 16 x u16
-                const uint4 *ip = (const uint4 *)(J->pitems + (uint64_t)p * KD);
-                const uint4 h0 = ip[0], h1 = ip[1];
-                const uint32_t pk32[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
-#pragma unroll
-                for (int t = 0; t < KD; ++t) {
-                    if ((uint32_t)t < k) {
-                        const uint32_t idx = (pk32[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
-                        const uint64_t *row = tile + idx * ts;
-#pragma unroll
-                        for (int w = 0; w < VT_MAXW; ++w)
-                            if ((uint32_t)w < nwt)
-                                acc[w] &= row[w];
-                    }
-                }
-            } else {
-                uint64_t nzw = J->pnz[p];
-                const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
-                while (nzw) {
-                    const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
-                    nzw &= nzw - 1;
-                    uint64_t bits = cm[wd];
-                    while (bits) {
-                        const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
-                        bits &= bits - 1;
-                        const uint64_t *row = tile + J->l1pos[item] * ts;
-#pragma unroll
-                        for (int w = 0; w < VT_MAXW; ++w)
-                            if ((uint32_t)w < nwt)
-                                acc[w] &= row[w];
-                    }
-                }
-            }
-            uint32_t sum = 0;
-#pragma unroll
-            for (int w = 0; w < VT_MAXW; ++w)
-                if ((uint32_t)w < nwt)
-                    sum += (uint32_t)__popcll(acc[w]);
-            cnt[q] += sum;
-        }
+        for (int q = 0; q < VT_CPT; ++q)
+            if (pidx[q] != NONE)
+                cnt[q] += and_tile(J, pidx[q], tile, ts, nwt);
     }
 #pragma unroll
     for (int q = 0; q < VT_CPT; ++q)
@@ -1153,6 +1179,7 @@ __global__ __launch_bounds__(WG) void k_stepz(const Job *__restrict__ jobs, Plan
     __shared__ uint32_t sh_app[2 * (WG / 64) + 2];
     __shared__ uint32_t sh_red[6 * (WG / 64)];
     __shared__ uint32_t sh_supp[WG / 64];
+    __shared__ uint64_t tile[Z_TILE_WORDS];
     __shared__ unsigned long long shc[WG / 64];
     __shared__ uint32_t sh_last;
     const uint32_t total = plan->pre_epi[plan->njobs];
@@ -1169,6 +1196,26 @@ __global__ __launch_bounds__(WG) void k_stepz(const Job *__restrict__ jobs, Plan
             const bool valid = c < ks;
             const uint32_t p = valid ? cur[c] : 0u;
             prune_and_check(J, st, valid, p, valid ? J->psupp[p] : 0u, sh_app, sh_red);
+        } else if (st->zlane) {
+            // many new candidates: WG of them per work item, one per thread,
+            // counted over the block's tiles staged in LDS, then pruned
+            const uint32_t c = ks + (local - nsc) * WG + threadIdx.x;
+            const bool valid = c < K;
+            const uint32_t p = valid ? cur[c] : 0u;
+            const uint32_t tw = st->ztw, ts = vert_tile_stride(tw);
+            uint32_t cnt = 0;
+            for (uint32_t w0 = st->fw; w0 <= st->lw; w0 += tw) {
+                const uint32_t nwt = (st->lw + 1u - w0) < tw ? (st->lw + 1u - w0) : tw;
+                stage_tile(J, st, w0, nwt, ts, tile);
+                if (valid)
+                    cnt += and_tile(J, p, tile, ts, nwt);
+            }
+            uint32_t supp = 0;
+            if (valid) {
+                supp = J->psupp[p] + cnt;
+                J->psupp[p] = supp;  // the only writer of this candidate's count
+            }
+            prune_and_check(J, st, valid, p, supp, sh_app, sh_red);
         } else {
             const uint32_t c0 = ks + (local - nsc) * (WG / 64);
             const uint32_t wave = threadIdx.x >> 6;
@@ -1522,7 +1569,8 @@ __global__ __launch_bounds__(WG) void k_stepx(const Job *__restrict__ jobs, Plan
             if (!st->done && !st->overflow)
                 finish_stop(jobs + j, st,
                             __hip_atomic_load(&st->pool_n, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT));
+                                              __HIP_MEMORY_SCOPE_AGENT),
+                            plan->vt_tile_words);
         }
         __syncthreads();
         write_plan_z(jobs, plan, (uint32_t *)tile);

@@ -101,6 +101,22 @@ def test_quest_small(dic, orc):
             mine_both(dic, orc, rows, m, minsup, M, f"quest{i} ms={minsup}")
 
 
+def test_many_new_candidates_at_one_stop(dic, orc):
+    """Stops that create thousands of candidates at once.
+
+    The candidates created at a stop are counted on the next block right
+    after their creation; from 1024 of them the item-bitset layout counts
+    them on LDS tiles of the block instead of one wave each.  This database
+    (Quest, 256 items, long baskets) creates over 4000 at its busiest stop,
+    with an even and a ragged block size.
+    """
+    rows, _ = synth.quest(20000, 256, n_patterns=512, pat_len_mean=4, txn_len_mean=16, seed=7)
+    for M in (1000, 997):
+        g = mine_both(dic, orc, rows, 256, 0.01, M, f"many-new M={M}")
+        gen = g.trace[:, 5].astype(np.int64)
+        assert (gen >= 1024).sum() >= 3, gen.max()
+
+
 def test_workload_one_full(dic, orc):
     c = synth.config(1)
     g = mine_both(dic, orc, c["rows"], c["m"], c["minsup"], c["M"], "config n10k m64")
