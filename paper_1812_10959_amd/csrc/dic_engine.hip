@@ -82,10 +82,10 @@ uint64_t pool_cap_for(uint32_t nL1, uint32_t mult)
 
 // Layout of a job's candidate pool buffer.
 struct PoolLayout {
-    size_t mask, items, hash, nz, supp, stop, state, promo, k, slots, live0, live1, newbox, omask,
-        ocnt;
+    size_t mask, items, hash, nz, supp, stop, state, promo, k, slots, live0, live1, newbox, zarr,
+        omask, ocnt;
     size_t bytes;
-    uint64_t hslots;
+    uint64_t hslots, zarr_n;
     PoolLayout(uint64_t cap, uint32_t W)
     {
         hslots = next_pow2(2 * cap);
@@ -103,6 +103,8 @@ struct PoolLayout {
         live0 = c.take(cap * 4);
         live1 = c.take(cap * 4);
         newbox = c.take(cap * 4);
+        zarr_n = cap / WG + 1;
+        zarr = c.take(zarr_n * 4);
         omask = c.take(cap * W * 8);
         ocnt = c.take(cap * 4);
         bytes = c.off;
@@ -556,9 +558,11 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         J.live0 = (uint32_t *)(b + L.live0);
         J.live1 = (uint32_t *)(b + L.live1);
         J.newbox = (uint32_t *)(b + L.newbox);
+        J.zarr = (uint32_t *)(b + L.zarr);
         J.out_mask = (uint64_t *)(b + L.omask);
         J.out_cnt = (uint32_t *)(b + L.ocnt);
         HIP_TRY(hipMemsetAsync(J.slots, 0xFF, L.hslots * 8, s_));
+        HIP_TRY(hipMemsetAsync(J.zarr, 0, (L.zarr_n) * 4, s_));
         aux_host_[i] = J;
     }
     // first candidates: pairs of frequent items (nL1 x nL1 work), or every

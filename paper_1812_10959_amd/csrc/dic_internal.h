@@ -111,9 +111,9 @@ struct JobState {
     uint32_t pending;   // added, not yet moved to its first block
     uint32_t need;      // stops the current live set certainly still needs
     uint32_t ks;        // candidates at the head of the current list counted by X
-    uint32_t zlane;     // the new candidates are many: Z counts them on LDS tiles
-    uint32_t ztw;       // words per item in those tiles
-    uint32_t pad[1];
+    uint32_t znc;       // Z tile mode: tile chunks per group of new candidates (0: wave mode)
+    uint32_t ztw;       //              words per item in a tile
+    uint32_t zrpi;      //              tiles per chunk
 };
 static_assert(sizeof(JobState) == 128, "JobState is read back as 128-byte records");
 static_assert(offsetof(JobState, k_next) % 8 == 0, "k_next/n_new form one 64-bit word");
@@ -186,6 +186,7 @@ struct Job {
     unsigned long long *slots;  // open addressing: idx<<32 | fp24<<8 | k8
     uint32_t *live0, *live1;    // cap each
     uint32_t *newbox;           // cap
+    uint32_t *zarr;             // cap / WG + 1 arrival counters of Z's tile chunks (zero between uses)
     uint32_t *l1;               // m
     uint32_t *item_cnt;         // m
     dic_stop_trace *trace;

@@ -28,9 +28,9 @@ constexpr uint32_t FP_ROWS = 4096;       // first pass rows per workgroup item
 constexpr uint32_t FPV_WORDS = 4096;     // first pass (bitsets): words per work item
 constexpr int VT_CPT = 8;                // bitset count: candidates per thread at most
 constexpr uint32_t NONE = 0xFFFFFFFFu;
-constexpr uint32_t Z_TILE_MIN = 1024;   // new candidates from which Z counts them on LDS tiles
-constexpr uint32_t Z_TILE_WORDS = 1536;  // 64-bit words of Z's tile (12 KiB): one word of
-                                         // every frequent item at least, when nL1 fits
+constexpr uint32_t Z_TILE_MIN = 1024;    // new candidates from which Z counts on LDS tiles
+constexpr uint32_t Z_TILE_WORDS = VT_WORDS;  // 64-bit words of Z's tile
+constexpr uint32_t Z_TARGET = 512;       // Z tile-mode work items aimed at per job
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
@@ -576,11 +576,21 @@ __device__ void finish_stop(const Job *J, JobState *st, uint32_t pool_n, uint32_
     // candidate, else the survivors' remaining stops (from the last Prune)
     st->need = gen ? J->stop_max : st->max_rem;
     st->ks = st->k_next;  // counted already, by X
-    // many new candidates: Z counts them one per thread on LDS tiles of the
-    // block (a wave each would read every item row from L2 per candidate)
-    st->zlane = (J->layout == LAYOUT_VERTICAL && gen >= Z_TILE_MIN &&
-                 st->nL1 <= Z_TILE_WORDS) ? 1u : 0u;
-    st->ztw = vert_tile_words(st->nL1, tile_words, Z_TILE_WORDS);
+    // Z counts the new candidates one wave each unless they are many: then
+    // one thread each on LDS tiles, the tiles split in chunks over workgroups
+    st->znc = 0;
+    const uint32_t nwords = st->lw - st->fw + 1u;
+    if (J->layout == LAYOUT_VERTICAL && gen >= Z_TILE_MIN && st->nL1 <= Z_TILE_WORDS) {
+        const uint32_t tw = vert_tile_words(st->nL1, tile_words, Z_TILE_WORDS);
+        const uint32_t ntile = (nwords + tw - 1u) / tw;
+        const uint32_t groups = (gen + WG - 1u) / WG;
+        uint32_t want = (Z_TARGET + groups - 1u) / groups;  // chunks per group
+        want = want < 1u ? 1u : (want > ntile ? ntile : want);
+        const uint32_t tpc = (ntile + want - 1u) / want;
+        st->ztw = tw;
+        st->zrpi = tpc;
+        st->znc = (ntile + tpc - 1u) / tpc;
+    }
     st->pool_base = pn;
     st->k_next = 0;
     st->n_new = 0;
@@ -663,15 +673,17 @@ __device__ void plan_x(const Job *J, JobState *st, const Plan *plan, uint32_t *i
     }
 }
 
-// Work of Z for one job: chunks of WG survivors (counted by X), then groups
-// of new candidates: WG/64 of them, one wave each, or WG of them, one
-// thread each on LDS tiles, when there are at least Z_TILE_MIN.
+// Work of Z for one job: chunks of WG survivors (counted by X), then the new
+// candidates: groups of WG/64, one wave each (wave mode), or groups of WG, one
+// thread each, times chunks of LDS tiles of the block (tile mode, znc > 0).
 __device__ uint32_t plan_z(const JobState *st)
 {
     if (st->done || st->overflow || st->K == 0)
         return 0;
-    const uint32_t per = st->zlane ? WG : WG / 64;  // new candidates per work item
-    return (st->ks + WG - 1u) / WG + (st->K - st->ks + per - 1u) / per;
+    const uint32_t nsc = (st->ks + WG - 1u) / WG;
+    if (st->znc)
+        return nsc + (st->K - st->ks + WG - 1u) / WG * st->znc;
+    return nsc + (st->K - st->ks + WG / 64 - 1u) / (WG / 64);
 }
 
 // Arrival counter of a launch, called by one thread per workgroup after the
@@ -965,25 +977,44 @@ __device__ __forceinline__ void stage_tile(const Job *J, const JobState *st, uin
     __syncthreads();
 }
 
-// Transactions of a staged tile (nwt words) that contain candidate p: the
-// AND of its items' tile rows, popcounted.
-__device__ __forceinline__ uint32_t and_tile(const Job *J, uint32_t p, const uint64_t *tile,
-                                             uint32_t ts, uint32_t nwt)
+// A candidate's size and, when it has at most KD items, its frequent-item
+// indices (16 x u16, ascending), read once for several tiles.
+struct CandItems {
+    uint32_t k;
+    uint32_t pk32[KD / 2];
+};
+
+__device__ __forceinline__ CandItems cand_items(const Job *J, uint32_t p)
+{
+    CandItems ci;
+    ci.k = J->pk[p];
+    if (ci.k <= (uint32_t)KD) {
+        const uint4 *ip = (const uint4 *)(J->pitems + (uint64_t)p * KD);
+        const uint4 h0 = ip[0], h1 = ip[1];
+        ci.pk32[0] = h0.x; ci.pk32[1] = h0.y; ci.pk32[2] = h0.z; ci.pk32[3] = h0.w;
+        ci.pk32[4] = h1.x; ci.pk32[5] = h1.y; ci.pk32[6] = h1.z; ci.pk32[7] = h1.w;
+    } else {
+#pragma unroll
+        for (int t = 0; t < KD / 2; ++t)
+            ci.pk32[t] = 0u;
+    }
+    return ci;
+}
+
+// Transactions of a staged tile (nwt words) that contain candidate p (items
+// ci): the AND of its items' tile rows, popcounted.
+__device__ __forceinline__ uint32_t and_tile_items(const Job *J, uint32_t p, const CandItems &ci,
+                                                   const uint64_t *tile, uint32_t ts, uint32_t nwt)
 {
     uint64_t acc[VT_MAXW];
 #pragma unroll
     for (int w = 0; w < VT_MAXW; ++w)
         acc[w] = ~0ull;
-    const uint32_t k = J->pk[p];
-    if (k <= (uint32_t)KD) {
-        // the candidate's frequent-item indices, 16 x u16
-        const uint4 *ip = (const uint4 *)(J->pitems + (uint64_t)p * KD);
-        const uint4 h0 = ip[0], h1 = ip[1];
-        const uint32_t pk32[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+    if (ci.k <= (uint32_t)KD) {
 #pragma unroll
         for (int t = 0; t < KD; ++t) {
-            if ((uint32_t)t < k) {
-                const uint32_t idx = (pk32[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
+            if ((uint32_t)t < ci.k) {
+                const uint32_t idx = (ci.pk32[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
                 const uint64_t *row = tile + idx * ts;
 #pragma unroll
                 for (int w = 0; w < VT_MAXW; ++w)
@@ -1015,6 +1046,12 @@ __device__ __forceinline__ uint32_t and_tile(const Job *J, uint32_t p, const uin
         if ((uint32_t)w < nwt)
             sum += (uint32_t)__popcll(acc[w]);
     return sum;
+}
+
+__device__ __forceinline__ uint32_t and_tile(const Job *J, uint32_t p, const uint64_t *tile,
+                                             uint32_t ts, uint32_t nwt)
+{
+    return and_tile_items(J, p, cand_items(J, p), tile, ts, nwt);
 }
 
 // CountSupport (Algorithm 3) on item bitsets, one work item of X: the
@@ -1196,24 +1233,55 @@ __global__ __launch_bounds__(WG) void k_stepz(const Job *__restrict__ jobs, Plan
             const bool valid = c < ks;
             const uint32_t p = valid ? cur[c] : 0u;
             prune_and_check(J, st, valid, p, valid ? J->psupp[p] : 0u, sh_app, sh_red);
-        } else if (st->zlane) {
-            // many new candidates: WG of them per work item, one per thread,
-            // counted over the block's tiles staged in LDS, then pruned
-            const uint32_t c = ks + (local - nsc) * WG + threadIdx.x;
+        } else if (st->znc) {
+            // tile mode: work item = (group of WG new candidates, one per
+            // thread) x (chunk of zrpi tiles of the block, staged in LDS)
+            const uint32_t wi = local - nsc;
+            const uint32_t g = wi / st->znc, r = wi - g * st->znc;
+            const uint32_t c = ks + g * WG + threadIdx.x;
             const bool valid = c < K;
             const uint32_t p = valid ? cur[c] : 0u;
+            const CandItems ci = valid ? cand_items(J, p) : CandItems{};
             const uint32_t tw = st->ztw, ts = vert_tile_stride(tw);
+            const uint32_t ntile = (st->lw - st->fw + tw) / tw;
+            const uint32_t t0 = r * st->zrpi;
+            const uint32_t t1 = t0 + st->zrpi < ntile ? t0 + st->zrpi : ntile;
             uint32_t cnt = 0;
-            for (uint32_t w0 = st->fw; w0 <= st->lw; w0 += tw) {
+            for (uint32_t t = t0; t < t1; ++t) {
+                const uint32_t w0 = st->fw + t * tw;
                 const uint32_t nwt = (st->lw + 1u - w0) < tw ? (st->lw + 1u - w0) : tw;
                 stage_tile(J, st, w0, nwt, ts, tile);
                 if (valid)
-                    cnt += and_tile(J, p, tile, ts, nwt);
+                    cnt += and_tile_items(J, p, ci, tile, ts, nwt);
             }
             uint32_t supp = 0;
-            if (valid) {
-                supp = J->psupp[p] + cnt;
-                J->psupp[p] = supp;  // the only writer of this candidate's count
+            if (st->znc == 1u) {
+                if (valid) {
+                    supp = J->psupp[p] + cnt;
+                    J->psupp[p] = supp;  // the only writer of this candidate's count
+                }
+            } else {
+                // partial count of this chunk; the group's last chunk to
+                // arrive prunes.  The add returns its old value, so this
+                // thread has waited for it before the barrier below (a
+                // barrier alone does not wait for other waves' atomics).
+                if (valid && cnt) {
+                    const uint32_t before = atomicAdd(J->psupp + p, cnt);
+                    if (before + cnt > J->n)  // a support never exceeds n
+                        atomicAdd(&st->asserts, 1u);
+                }
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    sh_last = atomicAdd(J->zarr + g, 1u) == st->znc - 1u;
+                __syncthreads();
+                if (!sh_last)
+                    continue;
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(J->zarr + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // every chunk's add is complete: read the totals at device scope
+                supp = valid ? __hip_atomic_load(J->psupp + p, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                             : 0u;
             }
             prune_and_check(J, st, valid, p, supp, sh_app, sh_red);
         } else {

@@ -102,19 +102,25 @@ def test_quest_small(dic, orc):
 
 
 def test_many_new_candidates_at_one_stop(dic, orc):
-    """Stops that create thousands of candidates at once.
+    """Stops that create thousands of candidates at once, and long blocks.
 
     The candidates created at a stop are counted on the next block right
-    after their creation; from 1024 of them the item-bitset layout counts
-    them on LDS tiles of the block instead of one wave each.  This database
-    (Quest, 256 items, long baskets) creates over 4000 at its busiest stop,
-    with an even and a ragged block size.
+    after their creation.  From 1024 of them the item-bitset layout counts
+    them on LDS tiles of the block, split in chunks over workgroups, instead
+    of one wave each.  This database (Quest, 256 items, long baskets)
+    creates over 4000 at its busiest stop with short blocks (even and ragged
+    sizes).  With M = 16,500 the blocks alternate between 16,500 rows (258
+    words, many chunks) and a ragged 3,500, and over 11,000 candidates
+    created at a short block's stop are counted on a long block.
     """
     rows, _ = synth.quest(20000, 256, n_patterns=512, pat_len_mean=4, txn_len_mean=16, seed=7)
-    for M in (1000, 997):
+    for M in (1000, 997, 16500):
         g = mine_both(dic, orc, rows, 256, 0.01, M, f"many-new M={M}")
         gen = g.trace[:, 5].astype(np.int64)
-        assert (gen >= 1024).sum() >= 3, gen.max()
+        if M < 16500:
+            assert (gen >= 1024).sum() >= 3, gen.max()
+        else:
+            assert gen[g.trace[:, 1] == 3500].max() >= 1024
 
 
 def test_workload_one_full(dic, orc):
