@@ -202,6 +202,7 @@ struct ActiveJob {
     int slot = -1;
     void *small = nullptr;  // item counts, frequent items
     void *pool = nullptr;   // candidate pool
+    void *fvert = nullptr;  // frequent items' bitsets (item-bitset jobs with an infrequent item)
     void *trace = nullptr;
     Job job{};
     uint32_t layout = LAYOUT_VERTICAL;
@@ -215,8 +216,9 @@ struct ActiveJob {
     {
         dev_free(small);
         dev_free(pool);
+        dev_free(fvert);
         dev_free(trace);
-        small = pool = trace = nullptr;
+        small = pool = fvert = trace = nullptr;
     }
     ~ActiveJob() { release(); }
 };
@@ -561,6 +563,18 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         J.zarr = (uint32_t *)(b + L.zarr);
         J.out_mask = (uint64_t *)(b + L.omask);
         J.out_cnt = (uint32_t *)(b + L.ocnt);
+        // the counts read item rows by frequent-item index: gather those rows
+        // unless every item is frequent (classic start: all items, in order)
+        J.fvert = (uint64_t *)a->req.vert;
+        if (a->layout == LAYOUT_VERTICAL && a->nL1 < a->req.m && a->nL1 >= 2) {
+            if (!a->fvert)
+                a->fvert = dev_alloc(8ull * a->nL1 * J.nw);
+            if (!a->fvert) {
+                set_error("device allocation failed (frequent-item bitsets)");
+                return DIC_E_NOMEM;
+            }
+            J.fvert = (uint64_t *)a->fvert;
+        }
         HIP_TRY(hipMemsetAsync(J.slots, 0xFF, L.hslots * 8, s_));
         HIP_TRY(hipMemsetAsync(J.zarr, 0, (L.zarr_n) * 4, s_));
         aux_host_[i] = J;
@@ -577,6 +591,17 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
                            hipMemcpyHostToDevice, s_));
     if (pre_host_[nf])
         launch_init_pairs((const Job *)table_aux_, d_plan_aux_, pre_host_[nf], s_);
+    // frequent items' bitsets (the first pass is done with pre_fp)
+    fp_host_.assign(nf + 1, 0);
+    for (uint32_t i = 0; i < nf; ++i)
+        fp_host_[i + 1] = fp_host_[i] + (aux_host_[i].fvert != aux_host_[i].vert
+                                             ? (unsigned long long)fresh[i]->nL1 * aux_host_[i].nw
+                                             : 0ull);
+    if (fp_host_[nf]) {
+        HIP_TRY(hipMemcpyAsync(plan_aux_.pre_fp, fp_host_.data(), 8ull * (nf + 1),
+                               hipMemcpyHostToDevice, s_));
+        launch_gather_vert((const Job *)table_aux_, d_plan_aux_, fp_host_[nf], s_);
+    }
     HIP_TRY(hipGetLastError());
     // the host buffers above must outlive the copies: settle before returning
     HIP_TRY(hipStreamSynchronize(s_));

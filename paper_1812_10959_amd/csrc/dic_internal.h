@@ -171,6 +171,8 @@ __device__ __forceinline__ uint32_t slot_tag(unsigned long long h, uint32_t k)
 struct Job {
     const uint64_t *rows;  // n * W, row-major
     const uint64_t *vert;  // m * nw: bit r of vert[i * nw + g] = item i in row 64g + r
+    uint64_t *fvert;       // nL1 * nw: the frequent items' rows of vert, in frequent-item
+                           // order (vert itself when every item is frequent)
     uint32_t nw;           // 64-row words per item
     uint32_t layout;       // LAYOUT_ROWS or LAYOUT_VERTICAL counting
     uint32_t *l1pos;       // m: index of an item among the frequent items (or ~0)
@@ -225,6 +227,7 @@ void launch_transpose(const uint64_t *rows, uint64_t n, uint32_t m, uint64_t *ve
                       hipStream_t s);
 void launch_l1_and_pairs_prepare(const Job *jobs, const Plan *plan, uint32_t njobs, hipStream_t s);
 void launch_init_pairs(const Job *jobs, const Plan *plan, unsigned long long total, hipStream_t s);
+void launch_gather_vert(const Job *jobs, const Plan *plan, unsigned long long total, hipStream_t s);
 // Begin the next stop for newly added jobs and plan every job's work (once
 // per chunk of stops; later stops are begun by candidate generation).
 void launch_begin(const Job *jobs, Plan *plan, hipStream_t s);
@@ -337,6 +340,7 @@ class Engine {
     std::vector<JobState> st_;   // host copy of the slab
     std::vector<Job> table_host_, aux_host_;
     std::vector<unsigned long long> pre_host_;
+    std::vector<unsigned long long> fp_host_;  // prefix of the frequent-item bitset gather
     bool table_dirty_ = true;
     std::vector<hipEvent_t> events_;
 };

@@ -758,6 +758,26 @@ __device__ void write_plan_z(const Job *__restrict__ jobs, Plan *plan, uint32_t 
     }
 }
 
+// The frequent items' bitsets in frequent-item order (item-bitset jobs with
+// some infrequent item): fvert[a * nw + g] = vert[l1[a] * nw + g].  The counts
+// then index an item's row by its frequent-item index, one dependent load
+// fewer per tile and per wave.  Work: every (job, a, g), by prefix sums.
+__global__ __launch_bounds__(WG) void k_gather_vert(const Job *__restrict__ jobs,
+                                                    const Plan *__restrict__ plan,
+                                                    unsigned long long total)
+{
+    const unsigned long long stride = (unsigned long long)gridDim.x * WG;
+    for (unsigned long long x = (unsigned long long)blockIdx.x * WG + threadIdx.x; x < total;
+         x += stride) {
+        const uint32_t j = find_job(plan->pre_fp, plan->njobs, x);
+        const Job *J = jobs + j;
+        const unsigned long long local = x - plan->pre_fp[j];
+        const uint32_t a = (uint32_t)(local / J->nw);
+        const uint32_t g = (uint32_t)(local - (unsigned long long)a * J->nw);
+        J->fvert[local] = J->vert[(uint64_t)J->l1[a] * J->nw + g];
+    }
+}
+
 // Start of a chunk of stops (one workgroup).  A job added since the last
 // chunk has its first candidates in the next live list: they become its
 // survivors (counted by X like any), and it moves to its first block.  Every
@@ -918,14 +938,14 @@ __device__ __forceinline__ uint32_t count_wave_bitsets(const Job *J, const JobSt
         uint32_t row[KD];
 #pragma unroll
         for (int t = 0; t < KD; ++t)
-            row[t] = (uint32_t)t < k ? J->l1[item_at(iw, t)] : 0u;
+            row[t] = (uint32_t)t < k ? item_at(iw, t) : 0u;
         for (uint32_t w = st->fw + lane; w <= st->lw; w += 64) {
             uint64_t acc =
                 (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull);
 #pragma unroll
             for (int t = 0; t < KD; ++t)
                 if ((uint32_t)t < k)
-                    acc &= J->vert[(uint64_t)row[t] * nw + w];
+                    acc &= J->fvert[(uint64_t)row[t] * nw + w];
             cnt += (uint32_t)__popcll(acc);
         }
     } else {
@@ -942,7 +962,7 @@ __device__ __forceinline__ uint32_t count_wave_bitsets(const Job *J, const JobSt
                 while (bits) {
                     const uint32_t item = wd * 64u + (uint32_t)__builtin_ctzll(bits);
                     bits &= bits - 1;
-                    acc &= J->vert[(uint64_t)item * nw + w];
+                    acc &= J->fvert[(uint64_t)J->l1pos[item] * nw + w];
                 }
             }
             cnt += (uint32_t)__popcll(acc);
@@ -972,7 +992,7 @@ __device__ __forceinline__ void stage_tile(const Job *J, const JobState *st, uin
         const uint64_t mask = (g == fw ? lo_mask : ~0ull) & (g == lw ? hi_mask : ~0ull);
 #pragma unroll 4
         for (uint32_t a = q; a < nL1; a += per)
-            tile[a * ts + r] = J->vert[(uint64_t)J->l1[a] * J->nw + g] & mask;
+            tile[a * ts + r] = J->fvert[(uint64_t)a * J->nw + g] & mask;
     }
     __syncthreads();
 }
@@ -1736,6 +1756,12 @@ void launch_init_pairs(const Job *jobs, const Plan *plan, unsigned long long tot
 {
     hipLaunchKernelGGL(k_init_pairs, dim3(grid_for(total, WG, 8192)), dim3(WG), 0, s, jobs, plan,
                        total);
+}
+
+void launch_gather_vert(const Job *jobs, const Plan *plan, unsigned long long total, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_vert, dim3(grid_for(total, WG, 16384)), dim3(WG), 0, s, jobs,
+                       plan, total);
 }
 
 void launch_begin(const Job *jobs, Plan *plan, hipStream_t s)
