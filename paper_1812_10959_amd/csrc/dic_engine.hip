@@ -83,7 +83,7 @@ uint64_t pool_cap_for(uint32_t nL1, uint32_t mult)
 // Layout of a job's candidate pool buffer.
 struct PoolLayout {
     size_t mask, items, hash, nz, supp, stop, state, promo, k, slots, live0, live1, newbox, zarr,
-        omask, ocnt;
+        omask, ocnt, okey;
     size_t bytes;
     uint64_t hslots, zarr_n;
     PoolLayout(uint64_t cap, uint32_t W)
@@ -107,6 +107,7 @@ struct PoolLayout {
         zarr = c.take(zarr_n * 4);
         omask = c.take(cap * W * 8);
         ocnt = c.take(cap * 4);
+        okey = c.take(cap * 16);
         bytes = c.off;
     }
 };
@@ -250,6 +251,8 @@ Engine::~Engine()
     dev_free(table_);
     dev_free(table_aux_);
     dev_free(plan_buf_);
+    if (pinned_)
+        (void)hipHostFree(pinned_);
     for (hipEvent_t e : events_)
         (void)hipEventDestroy(e);
     for (auto &a : graphs_)
@@ -563,6 +566,7 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         J.zarr = (uint32_t *)(b + L.zarr);
         J.out_mask = (uint64_t *)(b + L.omask);
         J.out_cnt = (uint32_t *)(b + L.ocnt);
+        J.out_key = (unsigned long long *)(b + L.okey);
         // the counts read item rows by frequent-item index: gather those rows
         // unless every item is frequent (classic start: all items, in order)
         J.fvert = (uint64_t *)a->req.vert;
@@ -733,68 +737,124 @@ int Engine::collect(std::vector<ActiveJob *> &fin,
     HIP_TRY(hipMemcpyAsync(outn.data(), outn_d, 4ull * max_jobs_, hipMemcpyDeviceToHost, s_));
     HIP_TRY(hipStreamSynchronize(s_));
 
-    std::vector<std::vector<uint64_t>> om(nf);
-    std::vector<std::vector<uint32_t>> oc(nf), icnt(nf);
-    std::vector<MineOutput> res(nf);
+    // every finished job's boxes (masks, counts, sort keys), item counts and
+    // trace, staged in pinned host memory by one copy each
+    struct Part {
+        size_t mask, cnt, key, icnt, trace;
+        uint32_t q, ntr;
+    };
+    std::vector<Part> part(nf);
+    size_t total = 0;
+    auto take = [&total](size_t bytes) {
+        const size_t at = total;
+        total += (bytes + 255) & ~(size_t)255;
+        return at;
+    };
     for (uint32_t i = 0; i < nf; ++i) {
         ActiveJob *a = fin[i];
-        const uint32_t q = outn[a->slot];
-        om[i].resize((size_t)q * a->W);
-        oc[i].resize(q);
-        icnt[i].resize(a->req.m);
-        if (q) {
-            HIP_TRY(hipMemcpyAsync(om[i].data(), a->job.out_mask, 8ull * q * a->W,
+        Part &P = part[i];
+        P.q = outn[a->slot];
+        P.ntr = std::min(st_[a->slot].epoch, a->trace_cap);
+        P.mask = take(8ull * P.q * a->W);
+        P.cnt = take(4ull * P.q);
+        P.key = take(16ull * P.q);
+        P.icnt = take(4ull * a->req.m);
+        P.trace = take(sizeof(dic_stop_trace) * P.ntr);
+    }
+    if (total > pinned_cap_) {
+        if (pinned_)
+            (void)hipHostFree(pinned_);
+        pinned_ = nullptr;
+        pinned_cap_ = 0;
+        HIP_TRY(hipHostMalloc(&pinned_, total, hipHostMallocDefault));
+        pinned_cap_ = total;
+    }
+    char *pin = (char *)pinned_;
+    for (uint32_t i = 0; i < nf; ++i) {
+        ActiveJob *a = fin[i];
+        const Part &P = part[i];
+        if (P.q) {
+            HIP_TRY(hipMemcpyAsync(pin + P.mask, a->job.out_mask, 8ull * P.q * a->W,
                                    hipMemcpyDeviceToHost, s_));
-            HIP_TRY(hipMemcpyAsync(oc[i].data(), a->job.out_cnt, 4ull * q, hipMemcpyDeviceToHost,
+            HIP_TRY(hipMemcpyAsync(pin + P.cnt, a->job.out_cnt, 4ull * P.q, hipMemcpyDeviceToHost,
                                    s_));
+            HIP_TRY(hipMemcpyAsync(pin + P.key, a->job.out_key, 16ull * P.q,
+                                   hipMemcpyDeviceToHost, s_));
         }
-        HIP_TRY(hipMemcpyAsync(icnt[i].data(), a->job.item_cnt, 4ull * a->req.m,
+        HIP_TRY(hipMemcpyAsync(pin + P.icnt, a->job.item_cnt, 4ull * a->req.m,
                                hipMemcpyDeviceToHost, s_));
-        const uint32_t ntr = std::min(st_[a->slot].epoch, a->trace_cap);
-        res[i].trace.resize(ntr);
-        if (ntr)
-            HIP_TRY(hipMemcpyAsync(res[i].trace.data(), a->trace, sizeof(dic_stop_trace) * ntr,
+        if (P.ntr)
+            HIP_TRY(hipMemcpyAsync(pin + P.trace, a->trace, sizeof(dic_stop_trace) * P.ntr,
                                    hipMemcpyDeviceToHost, s_));
     }
     HIP_TRY(hipStreamSynchronize(s_));
     const auto now = std::chrono::steady_clock::now();
 
+    std::vector<MineOutput> res(nf);
     for (uint32_t i = 0; i < nf; ++i) {
         ActiveJob *a = fin[i];
         const JobState &s = st_[a->slot];
+        const Part &P = part[i];
         MineOutput &o = res[i];
         const uint32_t W = a->W;
-        // L = frequent items followed by the collected solid boxes
-        std::vector<uint64_t> masks;
-        std::vector<uint32_t> counts;
+        const uint64_t *bm = (const uint64_t *)(pin + P.mask);
+        const uint32_t *bc = (const uint32_t *)(pin + P.cnt);
+        const unsigned long long *bk = (const unsigned long long *)(pin + P.key);
+        const uint32_t *ic = (const uint32_t *)(pin + P.icnt);
+        o.trace.assign((const dic_stop_trace *)(pin + P.trace),
+                       (const dic_stop_trace *)(pin + P.trace) + P.ntr);
+        // L = the frequent items (src < 0) and the collected boxes (src >= 0),
+        // in canonical order: by key, then in full where keys tie
+        struct Entry {
+            unsigned long long hi, lo;
+            int64_t src;
+        };
+        std::vector<Entry> e;
+        e.reserve(P.q + 64);
         for (uint32_t it = 0; it < a->req.m; ++it)
-            if (icnt[i][it] >= a->tau) {
-                const size_t b = masks.size();
-                masks.resize(b + W, 0);
-                masks[b + (it >> 6)] = 1ull << (it & 63);
-                counts.push_back(icnt[i][it]);
-            }
-        masks.insert(masks.end(), om[i].begin(), om[i].end());
-        counts.insert(counts.end(), oc[i].begin(), oc[i].end());
-        const size_t q = counts.size();
-        std::vector<uint32_t> k(q), idx(q);
-        for (size_t t = 0; t < q; ++t) {
+            if (ic[it] >= a->tau)
+                e.push_back({(1ull << 59) | ((unsigned long long)it << 47), 0ull, -1 - (int64_t)it});
+        for (uint32_t t = 0; t < P.q; ++t)
+            e.push_back({bk[2 * (size_t)t], bk[2 * (size_t)t + 1], (int64_t)t});
+        auto size_of = [&](const uint64_t *m) {
             uint32_t c = 0;
             for (uint32_t w = 0; w < W; ++w)
-                c += (uint32_t)__builtin_popcountll(masks[t * W + w]);
-            k[t] = c;
-        }
-        std::iota(idx.begin(), idx.end(), 0u);
-        std::sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) {
-            return canon_less(&masks[(size_t)x * W], &masks[(size_t)y * W], W, k[x], k[y]);
+                c += (uint32_t)__builtin_popcountll(m[w]);
+            return c;
+        };
+        std::sort(e.begin(), e.end(), [&](const Entry &x, const Entry &y) {
+            if (x.hi != y.hi)
+                return x.hi < y.hi;
+            if (x.lo != y.lo)
+                return x.lo < y.lo;
+            if (x.src < 0 || y.src < 0)  // single items never tie
+                return false;
+            const uint64_t *mx = bm + (size_t)x.src * W, *my = bm + (size_t)y.src * W;
+            return canon_less(mx, my, W, size_of(mx), size_of(my));
         });
-        o.masks.resize(q * W);
+        const size_t q = e.size();
+        o.masks.assign(q * W, 0ull);
         o.counts.resize(q);
         uint64_t kmax = 0;
         for (size_t t = 0; t < q; ++t) {
-            std::memcpy(&o.masks[t * W], &masks[(size_t)idx[t] * W], 8 * W);
-            o.counts[t] = counts[idx[t]];
-            kmax = std::max<uint64_t>(kmax, k[idx[t]]);
+            const Entry &x = e[t];
+            uint64_t *dst = &o.masks[t * W];
+            if (x.src < 0) {
+                const uint32_t it = (uint32_t)(-1 - x.src);
+                dst[it >> 6] = 1ull << (it & 63);
+                o.counts[t] = ic[it];
+            } else {
+                std::memcpy(dst, bm + (size_t)x.src * W, 8 * W);
+                o.counts[t] = bc[x.src];
+            }
+        }
+        if (q) {
+            // sizes ascend: the last itemset is a largest one
+            const unsigned long long kf = e[q - 1].hi >> 59;
+            kmax = kf < 31 ? kf : size_of(&o.masks[(q - 1) * W]);
+            if (kf == 31)  // 31 or more: any of the trailing ones may be larger
+                for (size_t t = q; t-- > 0 && (e[t].hi >> 59) == 31;)
+                    kmax = std::max<uint64_t>(kmax, size_of(&o.masks[t * W]));
         }
         dic_stats &S = o.stats;
         S.tau = a->tau;

@@ -64,6 +64,34 @@ struct Knobs {
 Knobs knobs();
 int set_knob(const char *name, int64_t value);
 __host__ __device__ inline uint32_t vert_tile_stride(uint32_t tw) { return tw | 1u; }
+
+// Sort key of an itemset for the canonical result order (size, then the
+// ascending item list, compared item by item): the size (31 standing for 31
+// or more) in the top 5 bits of hi, then its first nine items, 12 bits each
+// (items < MAX_ITEMS), four in hi and five in lo.  Keys compare as (hi, lo);
+// two different itemsets with equal keys have 31 or more items or agree on
+// their first nine, and need the full comparison.
+__host__ __device__ inline void canon_key(const uint64_t *mask, uint32_t W, uint32_t k,
+                                          unsigned long long *hi, unsigned long long *lo)
+{
+    unsigned long long h = (unsigned long long)(k < 31u ? k : 31u) << 59, l = 0;
+    uint32_t n = 0;
+    for (uint32_t w = 0; w < W && n < 9u; ++w) {
+        uint64_t b = mask[w];
+        while (b && n < 9u) {
+            const unsigned long long item = w * 64u + (uint32_t)__builtin_ctzll(b);
+            b &= b - 1;
+            if (n < 4u)
+                h |= item << (47u - 12u * n);
+            else
+                l |= item << (52u - 12u * (n - 4u));
+            ++n;
+        }
+    }
+    *hi = h;
+    *lo = l;
+}
+static_assert(MAX_ITEMS <= 4096, "canon_key holds an item in 12 bits");
 // a tile of capacity c holds nL1 rows of stride vert_tile_stride(vert_tile_words(nL1, ., c))
 // whenever nL1 <= c: the count kernels' tile therefore covers any frequent-item count
 static_assert(VT_WORDS >= MAX_ITEMS, "the count tile must hold one word of every item");
@@ -197,6 +225,7 @@ struct Job {
     JobState *st;
     uint64_t *out_mask;   // collect: cap * W
     uint32_t *out_cnt;    // cap
+    unsigned long long *out_key;  // cap * 2: canon_key of each collected itemset
     uint32_t *out_n;      // 1
 };
 
@@ -341,6 +370,8 @@ class Engine {
     std::vector<Job> table_host_, aux_host_;
     std::vector<unsigned long long> pre_host_;
     std::vector<unsigned long long> fp_host_;  // prefix of the frequent-item bitset gather
+    void *pinned_ = nullptr;  // pinned host staging of finished jobs' outputs
+    size_t pinned_cap_ = 0;
     bool table_dirty_ = true;
     std::vector<hipEvent_t> events_;
 };

@@ -1665,7 +1665,8 @@ __global__ __launch_bounds__(WG) void k_stepx(const Job *__restrict__ jobs, Plan
     }
 }
 
-// Gather solid boxes (the output L without its 1-itemsets).
+// Gather solid boxes (the output L without its 1-itemsets), each with its
+// canonical sort key.
 __global__ __launch_bounds__(WG) void k_collect(const Job *__restrict__ jobs)
 {
     const Job *J = jobs + blockIdx.y;
@@ -1676,9 +1677,14 @@ __global__ __launch_bounds__(WG) void k_collect(const Job *__restrict__ jobs)
         const bool box = p < pool_n && J->pstate[p] == ST_SOLID_BOX;
         const uint32_t pos = wave_append(J->out_n, box, true);
         if (box) {
+            const uint64_t *pm = J->pmask + (uint64_t)p * W;
             for (uint32_t w = 0; w < W; ++w)
-                J->out_mask[(uint64_t)pos * W + w] = J->pmask[(uint64_t)p * W + w];
+                J->out_mask[(uint64_t)pos * W + w] = pm[w];
             J->out_cnt[pos] = J->psupp[p];
+            unsigned long long hi, lo;
+            canon_key(pm, W, J->pk[p], &hi, &lo);
+            J->out_key[2 * (uint64_t)pos] = hi;
+            J->out_key[2 * (uint64_t)pos + 1] = lo;
         }
     }
 }

@@ -137,6 +137,11 @@ def test_edge_cases(dic, orc):
     rows = pack([[1, 4, 5, 9, 11, 70]] * 37, 80)
     g = mine_both(dic, orc, rows, 80, 0.9, 5, "identical rows")
     assert len(g.counts) == 63 and set(g.counts.tolist()) == {37}
+    # twelve items in most rows: all 4,095 subsets frequent; itemsets of 10
+    # to 12 items agree on their first nine (the result sort must break ties)
+    rows = pack([list(range(3, 15))] * 9 + [[0, 1, 70]], 71)
+    g = mine_both(dic, orc, rows, 71, 0.5, 4, "twelve-item rows")
+    assert len(g.counts) == 4095 and g.stats["k_max"] == 12
     # unreachable threshold: empty result, no stops
     rows = synth.uniform_random(50, 20, 0.9, 3)
     g = mine_both(dic, orc, rows, 20, 1.5, 7, "minsup>1")
