@@ -990,9 +990,18 @@ __device__ __forceinline__ void stage_tile(const Job *J, const JobState *st, uin
     if (q < per) {
         const uint32_t g = w0 + r;
         const uint64_t mask = (g == fw ? lo_mask : ~0ull) & (g == lw ? hi_mask : ~0ull);
-#pragma unroll 4
-        for (uint32_t a = q; a < nL1; a += per)
-            tile[a * ts + r] = J->fvert[(uint64_t)a * J->nw + g] & mask;
+        // 16 loads in flight per batch (the tail of the last batch predicated)
+        const uint64_t *src = J->fvert + g;
+        for (uint32_t a = q; a < nL1; a += 16u * per) {
+            uint64_t v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                v[u] = a + u * per < nL1 ? src[(uint64_t)(a + u * per) * J->nw] : 0ull;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (a + u * per < nL1)
+                    tile[(a + u * per) * ts + r] = v[u] & mask;
+        }
     }
     __syncthreads();
 }
