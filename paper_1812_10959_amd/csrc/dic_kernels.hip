@@ -939,14 +939,28 @@ __device__ __forceinline__ uint32_t count_wave_bitsets(const Job *J, const JobSt
 #pragma unroll
         for (int t = 0; t < KD; ++t)
             row[t] = (uint32_t)t < k ? item_at(iw, t) : 0u;
-        for (uint32_t w = st->fw + lane; w <= st->lw; w += 64) {
-            uint64_t acc =
-                (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull);
+        // 3 words per lane per pass: all their loads issued together
+        for (uint32_t w0 = st->fw + lane; w0 <= st->lw; w0 += 192u) {
+            uint64_t acc[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const uint32_t w = w0 + 64u * u;
+                acc[u] = w <= st->lw ? (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull)
+                                     : 0ull;
+            }
 #pragma unroll
             for (int t = 0; t < KD; ++t)
-                if ((uint32_t)t < k)
-                    acc &= J->fvert[(uint64_t)row[t] * nw + w];
-            cnt += (uint32_t)__popcll(acc);
+                if ((uint32_t)t < k) {
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        const uint32_t w = w0 + 64u * u;
+                        if (w <= st->lw)
+                            acc[u] &= J->fvert[(uint64_t)row[t] * nw + w];
+                    }
+                }
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+                cnt += (uint32_t)__popcll(acc[u]);
         }
     } else {
         const uint64_t nz = J->pnz[p];
