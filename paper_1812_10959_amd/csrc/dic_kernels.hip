@@ -1091,12 +1091,6 @@ __device__ __forceinline__ uint32_t and_tile_items(const Job *J, uint32_t p, con
     return sum;
 }
 
-__device__ __forceinline__ uint32_t and_tile(const Job *J, uint32_t p, const uint64_t *tile,
-                                             uint32_t ts, uint32_t nwt)
-{
-    return and_tile_items(J, p, cand_items(J, p), tile, ts, nwt);
-}
-
 // CountSupport (Algorithm 3) on item bitsets, one work item of X: the
 // survivors of the last stop (head of the next live list) on the current
 // block.  Work item = (group of WG candidates, chunk of tiles).  A tile
@@ -1140,11 +1134,19 @@ __device__ __forceinline__ void count_vert_item(const Job *J, const JobState *st
     for (uint32_t t = t0; t < t1; ++t) {
         const uint32_t w0 = fw + t * tw;
         const uint32_t nwt = (lw + 1u - w0) < tw ? (lw + 1u - w0) : tw;
+        // the first candidate's item list loads during the tile fill, and
+        // each next one's while the current one is ANDed
+        CandItems cur = pidx[0] != NONE ? cand_items(J, pidx[0]) : CandItems{};
         stage_tile(J, st, w0, nwt, ts, tile);
 #pragma unroll
-        for (int q = 0; q < VT_CPT; ++q)
+        for (int q = 0; q < VT_CPT; ++q) {
+            CandItems nxt{};
+            if (q + 1 < VT_CPT && pidx[q + 1] != NONE)
+                nxt = cand_items(J, pidx[q + 1]);
             if (pidx[q] != NONE)
-                cnt[q] += and_tile(J, pidx[q], tile, ts, nwt);
+                cnt[q] += and_tile_items(J, pidx[q], cur, tile, ts, nwt);
+            cur = nxt;
+        }
     }
 #pragma unroll
     for (int q = 0; q < VT_CPT; ++q)
@@ -1652,7 +1654,11 @@ __device__ __forceinline__ void candgen_chunk(const Job *J, unsigned long long c
 // items of every job's survivors (row-bitmap jobs are counted by k_count,
 // launched just before).  The last workgroup to finish completes the stop
 // for every job and plans Z.
-__global__ __launch_bounds__(WG) void k_stepx(const Job *__restrict__ jobs, Plan *plan)
+// Three waves per SIMD (what its LDS tile allows) hold the item lists loaded
+// ahead in registers without spilling; left to itself the compiler took more
+// registers and ran two.
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_stepx(
+    const Job *__restrict__ jobs, Plan *plan)
 {
     __shared__ uint64_t tile[VT_WORDS];
     __shared__ uint32_t sh_app[WG / 64 + 1];
