@@ -31,6 +31,7 @@ constexpr uint32_t NONE = 0xFFFFFFFFu;
 constexpr uint32_t Z_TILE_MIN = 1024;    // new candidates from which Z counts on LDS tiles
 constexpr uint32_t Z_TILE_WORDS = VT_WORDS;  // 64-bit words of Z's tile
 constexpr uint32_t Z_TARGET = 512;       // Z tile-mode work items aimed at per job
+constexpr int ZP = 2;                    // survivors pruned per thread in a Z work item
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
@@ -282,6 +283,52 @@ __device__ void block_append2(uint32_t *ctr, bool a, bool b, uint32_t *sh, uint3
     const unsigned long long lt = lanemask_lt();
     *pa = sh[2 * NW] + sh[wave] + (uint32_t)__popcll(ba & lt);
     *pb = sh[2 * NW + 1] + sh[NW + wave] + (uint32_t)__popcll(bb & lt);
+    __syncthreads();
+}
+
+// NQ rounds of two appends (as NQ calls of block_append2, in round order)
+// with one 64-bit atomic for the workgroup.  sh holds 2 * NQ * (WG/64) + 2
+// words.
+template <int NQ>
+__device__ void block_append2_rounds(uint32_t *ctr, const bool (&a)[NQ], const bool (&b)[NQ],
+                                     uint32_t *sh, uint32_t (&pa)[NQ], uint32_t (&pb)[NQ])
+{
+    constexpr int NW = WG / 64;
+    const uint32_t wave = threadIdx.x >> 6;
+    unsigned long long ba[NQ], bb[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        ba[q] = __ballot(a[q]);
+        bb[q] = __ballot(b[q]);
+        if (lane_id() == 0) {
+            sh[q * NW + wave] = (uint32_t)__popcll(ba[q]);
+            sh[(NQ + q) * NW + wave] = (uint32_t)__popcll(bb[q]);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t ta = 0, tb = 0;
+        for (int i = 0; i < NQ * NW; ++i) {
+            const uint32_t ca = sh[i], cb = sh[NQ * NW + i];
+            sh[i] = ta;
+            sh[NQ * NW + i] = tb;
+            ta += ca;
+            tb += cb;
+        }
+        unsigned long long old = 0;
+        if (ta | tb)
+            old = atomicAdd((unsigned long long *)ctr,
+                            ((unsigned long long)tb << 32) | (unsigned long long)ta);
+        sh[2 * NQ * NW] = (uint32_t)old;
+        sh[2 * NQ * NW + 1] = (uint32_t)(old >> 32);
+    }
+    __syncthreads();
+    const unsigned long long lt = lanemask_lt();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        pa[q] = sh[2 * NQ * NW] + sh[q * NW + wave] + (uint32_t)__popcll(ba[q] & lt);
+        pb[q] = sh[2 * NQ * NW + 1] + sh[(NQ + q) * NW + wave] + (uint32_t)__popcll(bb[q] & lt);
+    }
     __syncthreads();
 }
 
@@ -673,14 +720,14 @@ __device__ void plan_x(const Job *J, JobState *st, const Plan *plan, uint32_t *i
     }
 }
 
-// Work of Z for one job: chunks of WG survivors (counted by X), then the new
+// Work of Z for one job: chunks of ZP * WG survivors (counted by X), then the new
 // candidates: groups of WG/64, one wave each (wave mode), or groups of WG, one
 // thread each, times chunks of LDS tiles of the block (tile mode, znc > 0).
 __device__ uint32_t plan_z(const JobState *st)
 {
     if (st->done || st->overflow || st->K == 0)
         return 0;
-    const uint32_t nsc = (st->ks + WG - 1u) / WG;
+    const uint32_t nsc = (st->ks + ZP * WG - 1u) / (ZP * WG);
     if (st->znc)
         return nsc + (st->K - st->ks + WG - 1u) / WG * st->znc;
     return nsc + (st->K - st->ks + WG / 64 - 1u) / (WG / 64);
@@ -1228,6 +1275,105 @@ __device__ void prune_and_check(const Job *J, JobState *st, bool valid, uint32_t
     }
 }
 
+// Prune and CheckFullPass of the survivors at list positions [c0, c0 + ZP*WG)
+// below cend, ZP per thread (position c0 + q*WG + thread), whose counts X has
+// completed: the same decisions as prune_and_check, with every candidate's
+// loads issued together and one append atomic and one set of statistics
+// atomics per workgroup.  Every thread of the workgroup calls.
+template <int NQ>
+__device__ void prune_survivors(const Job *J, JobState *st, const uint32_t *cur, uint32_t c0,
+                                uint32_t cend, uint32_t *sh_app, uint32_t *sh_red)
+{
+    uint32_t p[NQ], supp[NQ], sc[NQ], state[NQ], items[NQ];
+    bool valid[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const uint32_t c = c0 + (uint32_t)q * WG + threadIdx.x;
+        valid[q] = c < cend;
+        p[q] = valid[q] ? cur[c] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        supp[q] = valid[q] ? J->psupp[p[q]] : 0u;
+        sc[q] = valid[q] ? J->pstop[p[q]] + 1u : 0u;
+        state[q] = valid[q] ? J->pstate[p[q]] : 0u;
+        items[q] = valid[q] ? J->pk[p[q]] : 0u;
+    }
+    bool keep[NQ], promoted[NQ];
+    uint32_t words = 0, nitems = 0, npro = 0, npru = 0, nsol = 0, rem = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        keep[q] = promoted[q] = false;
+        if (!valid[q])
+            continue;
+        const uint32_t pq = p[q];
+        if (J->layout == LAYOUT_ROWS) {
+            uint64_t nzw = J->pnz[pq];
+            const uint64_t *cm = J->pmask + (uint64_t)pq * J->W;
+            while (nzw) {
+                const uint64_t v = cm[__builtin_ctzll(nzw)];
+                nzw &= nzw - 1;
+                words += ((uint32_t)v != 0u) + ((uint32_t)(v >> 32) != 0u);
+            }
+        }
+        nitems += items[q];
+        J->pstop[pq] = sc[q];
+        uint32_t stt = state[q];
+        bool pruned = false;
+        if (stt == ST_DASHED_CIRCLE) {
+            if (supp[q] >= J->tau) {
+                stt = ST_DASHED_BOX;
+                J->ppromo[pq] = st->epoch;
+                promoted[q] = true;
+                ++npro;
+            } else if ((uint64_t)supp[q] + (uint64_t)J->Mp * (uint64_t)(J->stop_max - sc[q]) <
+                       (uint64_t)J->tau) {
+                stt = ST_PRUNED;
+                pruned = true;
+                ++npru;
+            }
+        }
+        if (!pruned) {
+            if (sc[q] == J->stop_max) {
+                ++nsol;
+                stt = stt == ST_DASHED_BOX ? ST_SOLID_BOX : ST_SOLID_CIRCLE;
+            } else {
+                keep[q] = true;
+                const uint32_t r = J->stop_max - sc[q];
+                rem = r > rem ? r : rem;
+            }
+        }
+        J->pstate[pq] = stt;
+    }
+    uint32_t *next = st->parity ? J->live0 : J->live1;
+    uint32_t pos[NQ], npos[NQ];
+    block_append2_rounds<NQ>(&st->k_next, keep, promoted, sh_app, pos, npos);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (keep[q])
+            next[pos[q]] = p[q];
+        if (promoted[q])
+            J->newbox[npos[q]] = p[q];
+    }
+    uint32_t v[6] = {words, nitems, npro, npru, nsol, rem};
+    block_reduce<5>(v, sh_red);
+    if (threadIdx.x == 0) {
+        dic_stop_trace *tr = trace_of(J, st);
+        if (tr) {
+            atomicAdd(&tr->words, v[0]);
+            atomicAdd(&tr->items, v[1]);
+            if (v[2])
+                atomicAdd(&tr->promoted, v[2]);
+            if (v[3])
+                atomicAdd(&tr->pruned, v[3]);
+            if (v[4])
+                atomicAdd(&tr->solidified, v[4]);
+        }
+        if (v[5])
+            atomicMax(&st->max_rem, v[5]);
+    }
+}
+
 // CountSupport of a candidate by one wave over the current block in row
 // bitmaps: lanes take rows, each testing (row & I) == I on I's nonzero words.
 __device__ uint32_t count_wave_rows(const Job *J, const JobState *st, uint32_t p)
@@ -1258,7 +1404,7 @@ __device__ uint32_t count_wave_rows(const Job *J, const JobState *st, uint32_t p
 // The last workgroup to finish moves every job to its next block and plans X.
 __global__ __launch_bounds__(WG) void k_stepz(const Job *__restrict__ jobs, Plan *plan)
 {
-    __shared__ uint32_t sh_app[2 * (WG / 64) + 2];
+    __shared__ uint32_t sh_app[2 * ZP * (WG / 64) + 2];
     __shared__ uint32_t sh_red[6 * (WG / 64)];
     __shared__ uint32_t sh_supp[WG / 64];
     __shared__ uint64_t tile[Z_TILE_WORDS];
@@ -1272,12 +1418,9 @@ __global__ __launch_bounds__(WG) void k_stepz(const Job *__restrict__ jobs, Plan
         const uint32_t local = it - plan->pre_epi[j];
         const uint32_t *cur = st->parity ? J->live1 : J->live0;
         const uint32_t ks = st->ks, K = st->K;
-        const uint32_t nsc = (ks + WG - 1u) / WG;
+        const uint32_t nsc = (ks + ZP * WG - 1u) / (ZP * WG);
         if (local < nsc) {
-            const uint32_t c = local * WG + threadIdx.x;
-            const bool valid = c < ks;
-            const uint32_t p = valid ? cur[c] : 0u;
-            prune_and_check(J, st, valid, p, valid ? J->psupp[p] : 0u, sh_app, sh_red);
+            prune_survivors<ZP>(J, st, cur, local * ZP * WG, ks, sh_app, sh_red);
         } else if (st->znc) {
             // tile mode: work item = (group of WG new candidates, one per
             // thread) x (chunk of zrpi tiles of the block, staged in LDS)
