@@ -16,8 +16,9 @@
 // k_begin starts a chunk of stops: newly added jobs move to their first
 // block, and every job is planned for the current job table.
 // Before the loop: k_first_pass and k_l1 (FirstPass: item supports, the
-// frequent items), k_init_pairs (pairs of frequent items as candidates).
-// After it: k_collect gathers the solid boxes.
+// frequent items), k_init_pairs (pairs of frequent items as candidates),
+// k_gather_vert (the frequent items' bitsets in frequent-item order).
+// After it: k_collect gathers the solid boxes with their sort keys.
 #include "dic_internal.h"
 
 namespace dic {
