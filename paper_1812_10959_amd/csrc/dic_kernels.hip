@@ -558,8 +558,9 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
         J->pstate[p] = ST_DASHED_CIRCLE;
         J->ppromo[p] = NO_EPOCH;
         J->live1[p] = p;  // parity starts at 0, so the first stop reads live1
-        __threadfence();
-        hash_insert(J, h, 2, p);
+        // no hash entry: outside the classic start a pair is only ever looked
+        // up by its index (MakeCandidates' 2-subsets); larger itemsets and
+        // the classic start's pairs go through the hash table
     }
 }
 
