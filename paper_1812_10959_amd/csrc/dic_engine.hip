@@ -822,16 +822,40 @@ int Engine::collect(std::vector<ActiveJob *> &fin,
                 c += (uint32_t)__builtin_popcountll(m[w]);
             return c;
         };
-        std::sort(e.begin(), e.end(), [&](const Entry &x, const Entry &y) {
-            if (x.hi != y.hi)
-                return x.hi < y.hi;
-            if (x.lo != y.lo)
-                return x.lo < y.lo;
-            if (x.src < 0 || y.src < 0)  // single items never tie
-                return false;
-            const uint64_t *mx = bm + (size_t)x.src * W, *my = bm + (size_t)y.src * W;
-            return canon_less(mx, my, W, size_of(mx), size_of(my));
-        });
+        // stable LSD radix sort on hi, one byte per pass (a pass whose byte is
+        // the same for every entry is skipped), then each run of equal hi by
+        // (lo, the full comparison)
+        {
+            std::vector<Entry> tmp(e.size());
+            for (int d = 0; d < 8; ++d) {
+                const int sh = 8 * d;
+                size_t cnt[257] = {0};
+                for (const Entry &x : e)
+                    ++cnt[((x.hi >> sh) & 255u) + 1];
+                if (*std::max_element(cnt + 1, cnt + 257) == e.size())
+                    continue;
+                for (int b = 0; b < 256; ++b)
+                    cnt[b + 1] += cnt[b];
+                for (const Entry &x : e)
+                    tmp[cnt[(x.hi >> sh) & 255u]++] = x;
+                e.swap(tmp);
+            }
+        }
+        for (size_t r0 = 0; r0 < e.size();) {
+            size_t r1 = r0 + 1;
+            while (r1 < e.size() && e[r1].hi == e[r0].hi)
+                ++r1;
+            if (r1 - r0 > 1)
+                std::sort(e.begin() + r0, e.begin() + r1, [&](const Entry &x, const Entry &y) {
+                    if (x.lo != y.lo)
+                        return x.lo < y.lo;
+                    if (x.src < 0 || y.src < 0)  // single items never tie
+                        return false;
+                    const uint64_t *mx = bm + (size_t)x.src * W, *my = bm + (size_t)y.src * W;
+                    return canon_less(mx, my, W, size_of(mx), size_of(my));
+                });
+            r0 = r1;
+        }
         const size_t q = e.size();
         o.masks.assign(q * W, 0ull);
         o.counts.resize(q);
