@@ -766,10 +766,17 @@ int Engine::collect(std::vector<ActiveJob *> &fin,
             (void)hipHostFree(pinned_);
         pinned_ = nullptr;
         pinned_cap_ = 0;
-        HIP_TRY(hipHostMalloc(&pinned_, total, hipHostMallocDefault));
-        pinned_cap_ = total;
+        if (hipHostMalloc(&pinned_, total, hipHostMallocDefault) == hipSuccess) {
+            pinned_cap_ = total;
+        } else {
+            (void)hipGetLastError();  // pageable staging instead: slower copies, same results
+            pinned_ = nullptr;
+        }
     }
-    char *pin = (char *)pinned_;
+    std::vector<char> pageable;
+    if (!pinned_)
+        pageable.resize(total);
+    char *pin = pinned_ ? (char *)pinned_ : pageable.data();
     for (uint32_t i = 0; i < nf; ++i) {
         ActiveJob *a = fin[i];
         const Part &P = part[i];
