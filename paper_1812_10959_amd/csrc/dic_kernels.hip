@@ -736,16 +736,20 @@ __device__ uint32_t plan_z(const JobState *st)
 }
 
 // Arrival counter of a launch, called by one thread per workgroup after the
-// workgroup's work: true for the workgroup that arrives last.  Two levels
+// workgroup's work: true for the workgroup that arrives last.  Only the
+// first n workgroups arrive (n = min(grid, work items), at least 1: the
+// others had no work item); the rest return false at once.  Two levels
 // (workgroups of a group of TICKET_GROUPS, then the groups) keep the atomics
 // on any one counter few; the last arrival clears every counter for the
 // next launch.
-__device__ bool arrive_last(uint32_t *tickets)
+__device__ bool arrive_last(uint32_t *tickets, uint32_t n)
 {
+    if (blockIdx.x >= n)
+        return false;
     const uint32_t G = TICKET_GROUPS;
     const uint32_t g = blockIdx.x % G;
-    const uint32_t groups = gridDim.x < G ? gridDim.x : G;
-    const uint32_t members = gridDim.x / G + (g < gridDim.x % G ? 1u : 0u);
+    const uint32_t groups = n < G ? n : G;
+    const uint32_t members = n / G + (g < n % G ? 1u : 0u);
     if (atomicAdd(&tickets[(g + 1u) * TICKET_STRIDE], 1u) != members - 1u)
         return false;
     if (atomicAdd(&tickets[0], 1u) != groups - 1u)
@@ -1495,7 +1499,7 @@ __global__ __launch_bounds__(WG) void k_stepz(const Job *__restrict__ jobs, Plan
     }
     __syncthreads();
     if (threadIdx.x == 0)
-        sh_last = arrive_last(plan->tickets);
+        sh_last = arrive_last(plan->tickets, total < gridDim.x ? (total ? total : 1u) : gridDim.x);
     __syncthreads();
     if (sh_last) {
         for (uint32_t j = threadIdx.x; j < plan->njobs; j += WG) {
@@ -1823,7 +1827,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     }
     __syncthreads();
     if (threadIdx.x == 0)
-        sh_last = arrive_last(plan->tickets);
+        sh_last = arrive_last(plan->tickets, total < gridDim.x ? (total ? (uint32_t)total : 1u)
+                                                             : gridDim.x);
     __syncthreads();
     if (sh_last) {
         for (uint32_t j = threadIdx.x; j < njobs; j += WG) {
