@@ -30,6 +30,7 @@ import numpy as np
 
 __all__ = [
     "n_words", "quest", "dense_injected", "uniform_random", "config", "batch_config",
+    "batch_specs", "batch_one",
     "serve_pool", "serve_stream", "bitmap_to_csr", "CONFIG_SEED_BASE",
 ]
 
@@ -205,13 +206,10 @@ def batch_config(count: int = 256, *, seed: int = CONFIG_SEED_BASE + 4,
     ``workers`` > 1 generates the databases in that many processes.
     Returns a list of dicts (rows, m, minsup, M, name, meta).
     """
-    rng = np.random.default_rng(seed)
-    ns = rng.integers(n_lo, n_hi + 1, count)
-    ms = rng.choice(np.asarray(widths), count)
-    lens = rng.uniform(len_lo, len_hi, count)
-    mins = rng.uniform(minsup_lo, minsup_hi, count)
-    subseeds = rng.integers(0, 2**31 - 1, count)
-    args = [(int(ns[i]), int(ms[i]), float(lens[i]), int(subseeds[i])) for i in range(count)]
+    specs = batch_specs(count, seed=seed, n_lo=n_lo, n_hi=n_hi, widths=widths, len_lo=len_lo,
+                        len_hi=len_hi, minsup_lo=minsup_lo, minsup_hi=minsup_hi)
+    args = [(s["n"], s["m"], s["txn_len_mean"], s["subseed"]) for s in specs]
+    mins = [s["minsup"] for s in specs]
     if workers > 1 and count > 1:
         # separate interpreters (spawned, never forked) so that a caller that
         # already holds a GPU context is not copied; same draws as serially
@@ -228,6 +226,29 @@ def batch_config(count: int = 256, *, seed: int = CONFIG_SEED_BASE + 4,
         out.append(dict(name=f"batch{i}_n{n}_m{m}", rows=rows, m=m, minsup=float(mins[i]),
                         M=max(1, n // 20), meta=meta))
     return out
+
+
+def batch_specs(count: int = 256, *, seed: int = CONFIG_SEED_BASE + 4,
+                n_lo: int = 1_000, n_hi: int = 200_000, widths=(64, 256, 1024),
+                len_lo: float = 8.0, len_hi: float = 20.0,
+                minsup_lo: float = 0.01, minsup_hi: float = 0.05):
+    """The draws of ``batch_config`` without generating any database: per
+    database its n, m, transaction length mean, generator seed, minsup and M.
+    ``batch_one(spec)`` makes database i's rows from its entry."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_lo, n_hi + 1, count)
+    ms = rng.choice(np.asarray(widths), count)
+    lens = rng.uniform(len_lo, len_hi, count)
+    mins = rng.uniform(minsup_lo, minsup_hi, count)
+    subseeds = rng.integers(0, 2**31 - 1, count)
+    return [dict(index=i, n=int(ns[i]), m=int(ms[i]), txn_len_mean=float(lens[i]),
+                 subseed=int(subseeds[i]), minsup=float(mins[i]), M=max(1, int(ns[i]) // 20))
+            for i in range(count)]
+
+
+def batch_one(spec: dict):
+    """Rows of one ``batch_specs`` entry (the same as ``batch_config``'s)."""
+    return _batch_one((spec["n"], spec["m"], spec["txn_len_mean"], spec["subseed"]))[0]
 
 
 def _batch_one(a):

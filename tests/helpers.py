@@ -93,3 +93,20 @@ def np_support(rows, m, itemsets):
     """numpy recount of each itemset (tuple of items) over all rows."""
     b = unpack_bool(rows, m)
     return np.array([int(np.all(b[:, list(s)], axis=1).sum()) for s in itemsets], np.int64)
+
+
+def result_digest(masks, counts, trace) -> str:
+    """SHA-256 of a mining result in canonical order: the masks (uint64 LE,
+    |L| x W), the counts (uint32 LE) and the per-stop trace's seven fields
+    (uint64 LE, stops x 7; empty when no stop ran).  Equal digests mean the
+    same itemsets, counts and trace bit for bit."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(b"masks")
+    h.update(np.ascontiguousarray(masks, dtype="<u8").tobytes())
+    h.update(b"counts")
+    h.update(np.ascontiguousarray(counts, dtype="<u4").tobytes())
+    h.update(b"trace")
+    if trace is not None and len(trace):
+        h.update(np.ascontiguousarray(np.asarray(trace)[:, :7], dtype="<u8").tobytes())
+    return h.hexdigest()
