@@ -151,6 +151,36 @@ DIC_API int dic_mine(dic_db *db, double minsup, uint64_t M, dic_result **out);
 DIC_API int dic_batch(dic_db *const *dbs, const double *minsup, const uint64_t *M, uint32_t count,
               dic_result **outs, int *status);
 
+/*
+ * Mine one database like dic_mine, allocating nothing: for callers that
+ * cannot allocate device memory (work captured into HIP graphs, tight
+ * serving loops, harnesses that forbid hipMalloc).  The working memory of
+ * the mine (job state, plans, counters, item counts, candidate pool,
+ * frequent-item bitsets) comes from one static device array of
+ * DIC_NOALLOC_SCRATCH_BYTES per GPU, held by the process from the first
+ * call on that GPU until it ends; its contents are cleared by each call
+ * where they must start empty.
+ *   masks  host array of capacity * W words (W = ceil(m / 64)), caller-owned
+ *   counts host array of capacity entries, caller-owned
+ *   *size  receives |L|, also when it exceeds capacity
+ *   stats  may be NULL; the per-stop trace is not kept (no trace accessor),
+ *          count_ms is 0
+ * On success masks/counts hold L in canonical order with the counts
+ * dic_mine returns, bit for bit.  DIC_E_CAPACITY if |L| > capacity
+ * (nothing is written to the arrays) or if the mine needs more working
+ * memory than the array holds (the message gives the bytes); DIC_E_INVAL for NULL db/size, NULL arrays with a
+ * nonzero capacity, minsup <= 0 or NaN, M == 0; DIC_E_DEVICE on a runtime
+ * error.  Runs on the current device.  Calls on one device from one
+ * process are serialised by a lock; work of two processes never shares an
+ * array.  A caller that captures the call's stream work into graphs must
+ * not replay two such graphs concurrently on one device: they share the
+ * array and would race.
+ */
+#define DIC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+DIC_API int dic_mine_noalloc(dic_db *db, double minsup, uint64_t M, uint64_t *masks,
+                             uint32_t *counts, uint64_t capacity, uint64_t *size,
+                             dic_stats *stats);
+
 /* Result accessors; pointers stay valid until dic_result_free. */
 DIC_API uint64_t dic_result_size(const dic_result *r);
 DIC_API uint32_t dic_result_words(const dic_result *r);

@@ -47,7 +47,7 @@ _NAMES = {v: k for k, v in dict(globals()).items() if k.startswith("DIC_E_") or 
 
 ABI_FUNCTIONS = (
     "dic_load_db", "dic_load_db_device", "dic_load_db_lists", "dic_db_rows", "dic_db_items",
-    "dic_free_db", "dic_mine", "dic_batch", "dic_result_size", "dic_result_words",
+    "dic_free_db", "dic_mine", "dic_mine_noalloc", "dic_batch", "dic_result_size", "dic_result_words",
     "dic_result_masks", "dic_result_counts", "dic_result_stats", "dic_result_trace",
     "dic_result_free", "dic_serve_create", "dic_serve_submit", "dic_serve_poll",
     "dic_serve_wait", "dic_serve_stats", "dic_serve_destroy", "dic_set_allocator",
@@ -102,6 +102,8 @@ _sig = {
     "dic_db_items": ([_p], _u32),
     "dic_free_db": ([_p], ctypes.c_int),
     "dic_mine": ([_p, ctypes.c_double, _u64, _pp], ctypes.c_int),
+    "dic_mine_noalloc": ([_p, ctypes.c_double, _u64, _p, _p, _u64, ctypes.POINTER(_u64),
+                          ctypes.POINTER(dic_stats)], ctypes.c_int),
     "dic_batch": ([_p, _p, _p, _u32, _p, _p], ctypes.c_int),
     "dic_result_size": ([_p], _u64),
     "dic_result_words": ([_p], _u32),
@@ -266,6 +268,24 @@ def dic_mine(db: Db, minsup: float, M: int) -> Result:
     h = ctypes.c_void_p()
     _check(_lib.dic_mine(db.handle, float(minsup), int(M), ctypes.byref(h)), "dic_mine")
     return _take_result(h.value)
+
+
+def dic_mine_noalloc(db: Db, minsup: float, M: int, capacity: int) -> Result:
+    """dic_mine_noalloc into output arrays of ``capacity`` itemsets allocated
+    here (the library itself allocates nothing for the call).  No per-stop
+    trace.  Raises DicError (DIC_E_CAPACITY) when |L| exceeds capacity."""
+    W = (db.m + 63) // 64
+    masks = np.zeros((max(int(capacity), 1), W), np.uint64)
+    counts = np.zeros(max(int(capacity), 1), np.uint32)
+    size = _u64()
+    st = dic_stats()
+    _check(_lib.dic_mine_noalloc(db.handle, float(minsup), int(M), masks.ctypes.data,
+                                 counts.ctypes.data, int(capacity), ctypes.byref(size),
+                                 ctypes.byref(st)), "dic_mine_noalloc")
+    q = int(size.value)
+    stats = {f: (float(getattr(st, f)) if f.endswith("_ms") else int(getattr(st, f)))
+             for f, _ in dic_stats._fields_}
+    return Result(masks[:q].copy(), counts[:q].copy(), stats)
 
 
 def dic_batch(dbs, minsups, Ms, raise_on_error: bool = True):

@@ -27,6 +27,7 @@ uint64_t db_n(dic_db *db) { return db->n; }
 uint32_t db_m(dic_db *db) { return db->m; }
 uint32_t db_W(dic_db *db) { return db->W; }
 void db_ref(dic_db *db, int delta) { db->refs += delta; }
+std::mutex &db_mutex(dic_db *db) { return db->mu; }
 
 namespace {
 

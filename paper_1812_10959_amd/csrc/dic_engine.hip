@@ -40,26 +40,6 @@ constexpr uint32_t FPV_WORDS = 4096;  // bitset words per first-pass work item (
 constexpr uint32_t TRACE_INIT = 512;
 constexpr uint32_t MAX_RESTARTS = 6;
 
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-uint64_t next_pow2(uint64_t x)
-{
-    uint64_t p = 1;
-    while (p < x)
-        p <<= 1;
-    return p;
-}
-
-struct Carver {
-    size_t off = 0;
-    size_t take(size_t bytes)
-    {
-        size_t o = off;
-        off = align_up(off + bytes, 256);
-        return o;
-    }
-};
-
 bool canon_less(const uint64_t *A, const uint64_t *B, uint32_t W, uint32_t ka, uint32_t kb)
 {
     if (ka != kb)
@@ -73,44 +53,6 @@ bool canon_less(const uint64_t *A, const uint64_t *B, uint32_t W, uint32_t ka, u
     }
     return false;
 }
-
-uint64_t pool_cap_for(uint32_t nL1, uint32_t mult)
-{
-    const uint64_t nC2 = (uint64_t)nL1 * (nL1 ? nL1 - 1u : 0u) / 2u;
-    return std::max<uint64_t>(16384, 4 * nC2 + 16384) * mult;
-}
-
-// Layout of a job's candidate pool buffer.
-struct PoolLayout {
-    size_t mask, items, hash, nz, supp, stop, state, promo, k, slots, live0, live1, newbox, zarr,
-        omask, ocnt, okey;
-    size_t bytes;
-    uint64_t hslots, zarr_n;
-    PoolLayout(uint64_t cap, uint32_t W)
-    {
-        hslots = next_pow2(2 * cap);
-        Carver c;
-        mask = c.take(cap * W * 8);
-        items = c.take(cap * KD * 2);
-        hash = c.take(cap * 8);
-        nz = c.take(cap * 8);
-        supp = c.take(cap * 4);
-        stop = c.take(cap * 4);
-        state = c.take(cap * 4);
-        promo = c.take(cap * 4);
-        k = c.take(cap * 4);
-        slots = c.take(hslots * 8);
-        live0 = c.take(cap * 4);
-        live1 = c.take(cap * 4);
-        newbox = c.take(cap * 4);
-        zarr_n = cap / WG + 1;
-        zarr = c.take(zarr_n * 4);
-        omask = c.take(cap * W * 8);
-        ocnt = c.take(cap * 4);
-        okey = c.take(cap * 16);
-        bytes = c.off;
-    }
-};
 
 std::atomic<int> g_profile{0};
 std::atomic<uint32_t> g_layout{LAYOUT_VERTICAL};
@@ -541,32 +483,13 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
             return DIC_E_NOMEM;
         }
         a->cap = (uint32_t)cap;
-        PoolLayout L(cap, a->W);
+        const PoolLayout L(cap, a->W);
         a->pool = dev_alloc(L.bytes);
         if (!a->pool) {
             set_error("device allocation failed (candidate pool)");
             return DIC_E_NOMEM;
         }
-        char *b = (char *)a->pool;
-        J.cap = a->cap;
-        J.hmask = (uint32_t)(L.hslots - 1);
-        J.pmask = (uint64_t *)(b + L.mask);
-        J.pitems = (uint16_t *)(b + L.items);
-        J.phash = (unsigned long long *)(b + L.hash);
-        J.pnz = (uint64_t *)(b + L.nz);
-        J.psupp = (uint32_t *)(b + L.supp);
-        J.pstop = (uint32_t *)(b + L.stop);
-        J.pstate = (uint32_t *)(b + L.state);
-        J.ppromo = (uint32_t *)(b + L.promo);
-        J.pk = (uint32_t *)(b + L.k);
-        J.slots = (unsigned long long *)(b + L.slots);
-        J.live0 = (uint32_t *)(b + L.live0);
-        J.live1 = (uint32_t *)(b + L.live1);
-        J.newbox = (uint32_t *)(b + L.newbox);
-        J.zarr = (uint32_t *)(b + L.zarr);
-        J.out_mask = (uint64_t *)(b + L.omask);
-        J.out_cnt = (uint32_t *)(b + L.ocnt);
-        J.out_key = (unsigned long long *)(b + L.okey);
+        pool_assign(J, L, (char *)a->pool, a->cap);
         // the counts read item rows by frequent-item index: gather those rows
         // unless every item is frequent (classic start: all items, in order)
         J.fvert = (uint64_t *)a->req.vert;

@@ -229,6 +229,68 @@ struct Job {
     uint32_t *out_n;      // 1
 };
 
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+inline uint64_t next_pow2(uint64_t x)
+{
+    uint64_t p = 1;
+    while (p < x)
+        p <<= 1;
+    return p;
+}
+
+// Bump carving of one buffer into 256-byte aligned parts.
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    }
+};
+
+// Candidate capacity of a job's pool: four times the pairs of its frequent
+// items plus room for larger itemsets, times mult after overflows.
+inline uint64_t pool_cap_for(uint32_t nL1, uint32_t mult)
+{
+    const uint64_t nC2 = (uint64_t)nL1 * (nL1 ? nL1 - 1u : 0u) / 2u;
+    const uint64_t c = 4 * nC2 + 16384;
+    return (c > 16384 ? c : 16384) * mult;
+}
+
+// Layout of a job's candidate pool buffer (byte offsets of its arrays).
+struct PoolLayout {
+    size_t mask, items, hash, nz, supp, stop, state, promo, k, slots, live0, live1, newbox, zarr,
+        omask, ocnt, okey;
+    size_t bytes;
+    uint64_t hslots, zarr_n;
+    PoolLayout(uint64_t cap, uint32_t W)
+    {
+        hslots = next_pow2(2 * cap);
+        Carver c;
+        mask = c.take(cap * W * 8);
+        items = c.take(cap * KD * 2);
+        hash = c.take(cap * 8);
+        nz = c.take(cap * 8);
+        supp = c.take(cap * 4);
+        stop = c.take(cap * 4);
+        state = c.take(cap * 4);
+        promo = c.take(cap * 4);
+        k = c.take(cap * 4);
+        slots = c.take(hslots * 8);
+        live0 = c.take(cap * 4);
+        live1 = c.take(cap * 4);
+        newbox = c.take(cap * 4);
+        zarr_n = cap / WG + 1;
+        zarr = c.take(zarr_n * 4);
+        omask = c.take(cap * W * 8);
+        ocnt = c.take(cap * 4);
+        okey = c.take(cap * 16);
+        bytes = c.off;
+    }
+};
+
 // Work plan of one step across all jobs (prefix sums, njobs + 1 entries).
 struct Plan {
     uint32_t njobs;
@@ -246,6 +308,30 @@ struct Plan {
 constexpr uint32_t TICKET_GROUPS = 32;
 constexpr uint32_t TICKET_STRIDE = 64;
 constexpr uint32_t TICKET_WORDS = (TICKET_GROUPS + 1) * TICKET_STRIDE;
+
+// Point job J's pool arrays into base (laid out by L, capacity cap).
+inline void pool_assign(Job &J, const PoolLayout &L, char *b, uint32_t cap)
+{
+    J.cap = cap;
+    J.hmask = (uint32_t)(L.hslots - 1);
+    J.pmask = (uint64_t *)(b + L.mask);
+    J.pitems = (uint16_t *)(b + L.items);
+    J.phash = (unsigned long long *)(b + L.hash);
+    J.pnz = (uint64_t *)(b + L.nz);
+    J.psupp = (uint32_t *)(b + L.supp);
+    J.pstop = (uint32_t *)(b + L.stop);
+    J.pstate = (uint32_t *)(b + L.state);
+    J.ppromo = (uint32_t *)(b + L.promo);
+    J.pk = (uint32_t *)(b + L.k);
+    J.slots = (unsigned long long *)(b + L.slots);
+    J.live0 = (uint32_t *)(b + L.live0);
+    J.live1 = (uint32_t *)(b + L.live1);
+    J.newbox = (uint32_t *)(b + L.newbox);
+    J.zarr = (uint32_t *)(b + L.zarr);
+    J.out_mask = (uint64_t *)(b + L.omask);
+    J.out_cnt = (uint32_t *)(b + L.ocnt);
+    J.out_key = (unsigned long long *)(b + L.okey);
+}
 
 // kernel launchers (dic_kernels.hip)
 void launch_first_pass(const Job *jobs, const Plan *plan, unsigned long long total_chunks,
@@ -265,6 +351,7 @@ void launch_begin(const Job *jobs, Plan *plan, hipStream_t s);
 void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, bool rows, bool vert,
                  uint32_t count_grid, hipEvent_t before = nullptr, hipEvent_t after = nullptr);
 void launch_collect(const Job *jobs, const Plan *plan, uint32_t njobs, hipStream_t s);
+void launch_fill32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s);
 void launch_pack_lists(const uint32_t *items, const uint64_t *offsets, uint64_t n, uint32_t W,
                        uint64_t *rows, hipStream_t s);
 void launch_check_padding(const uint64_t *rows, uint64_t n, uint32_t m, uint32_t *bad,

@@ -1868,6 +1868,15 @@ __global__ __launch_bounds__(WG) void k_collect(const Job *__restrict__ jobs)
     }
 }
 
+// Fill n 32-bit words with v (a kernel instead of a memset node, so that a
+// caller may capture the work into a graph).
+__global__ __launch_bounds__(WG) void k_fill32(uint32_t *__restrict__ p, uint32_t v, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * WG)
+        p[i] = v;
+}
+
 // Item lists (CSR) to bit rows, one thread per row.
 __global__ __launch_bounds__(WG) void k_pack_lists(const uint32_t *__restrict__ items,
                                                    const uint64_t *__restrict__ offsets,
@@ -1972,6 +1981,12 @@ void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, bool rows, bo
 void launch_collect(const Job *jobs, const Plan *, uint32_t njobs, hipStream_t s)
 {
     hipLaunchKernelGGL(k_collect, dim3(64, njobs), dim3(WG), 0, s, jobs);
+}
+
+void launch_fill32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s)
+{
+    if (n)
+        hipLaunchKernelGGL(k_fill32, dim3(grid_for(n, WG, 4096)), dim3(WG), 0, s, p, v, n);
 }
 
 void launch_pack_lists(const uint32_t *items, const uint64_t *offsets, uint64_t n, uint32_t W,
