@@ -360,10 +360,10 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         table_aux_ = dev_alloc(sizeof(Job) * max_jobs_);
         Carver c;
         const size_t p0 = c.take(sizeof(Plan)), p1 = c.take(sizeof(Plan));
-        const size_t a0 = c.take(4ull * (max_jobs_ + 1)), a1 = c.take(4ull * (max_jobs_ + 1));
+        const size_t a0 = c.take(4ull * (max_jobs_ + 1));
         const size_t av = c.take(4ull * (max_jobs_ + 1)), bv = c.take(4ull * (max_jobs_ + 1));
         const size_t a2 = c.take(8ull * (max_jobs_ + 1)), a3 = c.take(8ull * (max_jobs_ + 1));
-        const size_t b0 = c.take(4ull * (max_jobs_ + 1)), b1 = c.take(4ull * (max_jobs_ + 1));
+        const size_t b0 = c.take(4ull * (max_jobs_ + 1));
         const size_t b2 = c.take(8ull * (max_jobs_ + 1)), b3 = c.take(8ull * (max_jobs_ + 1));
         const size_t tk = c.take(4ull * TICKET_WORDS);
         plan_buf_ = dev_alloc(c.off);
@@ -377,11 +377,9 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         plan_step_.pre_count = (uint32_t *)(pb + a0);
         plan_step_.pre_countv = (uint32_t *)(pb + av);
         plan_aux_.pre_countv = (uint32_t *)(pb + bv);
-        plan_step_.pre_epi = (uint32_t *)(pb + a1);
         plan_step_.pre_cg = (unsigned long long *)(pb + a2);
         plan_step_.pre_fp = (unsigned long long *)(pb + a3);
         plan_aux_.pre_count = (uint32_t *)(pb + b0);
-        plan_aux_.pre_epi = (uint32_t *)(pb + b1);
         plan_aux_.pre_cg = (unsigned long long *)(pb + b2);
         plan_aux_.pre_fp = (unsigned long long *)(pb + b3);
         plan_step_.tickets = plan_aux_.tickets = (uint32_t *)(pb + tk);
@@ -677,7 +675,7 @@ int Engine::collect(std::vector<ActiveJob *> &fin,
         ActiveJob *a = fin[i];
         Part &P = part[i];
         P.q = outn[a->slot];
-        P.ntr = std::min(st_[a->slot].epoch, a->trace_cap);
+        P.ntr = std::min(st_[a->slot].stops, a->trace_cap);
         P.mask = take(8ull * P.q * a->W);
         P.cnt = take(4ull * P.q);
         P.key = take(16ull * P.q);
@@ -814,7 +812,7 @@ int Engine::collect(std::vector<ActiveJob *> &fin,
         S.tau = a->tau;
         S.block = a->Mp;
         S.stop_max = a->stop_max;
-        S.stops = s.epoch;
+        S.stops = s.stops;
         S.tests = s.tests;
         S.peak_live = s.peak_K;
         S.n_frequent = q;

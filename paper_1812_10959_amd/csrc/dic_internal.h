@@ -26,7 +26,6 @@ enum : uint32_t {
     ST_SOLID_BOX = 4,
 };
 
-constexpr uint32_t NO_EPOCH = 0xFFFFFFFFu;
 constexpr unsigned long long SLOT_EMPTY = ~0ull;
 constexpr uint32_t MAX_ITEMS = 4096;  // W <= 64, so a 64-bit map covers the words
 constexpr int WG = 256;               // threads per workgroup in every kernel
@@ -106,71 +105,72 @@ __host__ __device__ inline uint32_t row_tile_rows(uint32_t W)
     return r < 64u ? 64u : r;
 }
 
+// Standing of a pool itemset in one 32-bit word: its state in the low three
+// bits and, above them, the index (epoch) of the stop that promoted it to a
+// box (PROMO_NONE while it is a circle).  One word, so a reader in the same
+// launch sees the state and its promotion stop together.
+constexpr uint32_t PROMO_NONE = 0x1FFFFFFFu;
+__host__ __device__ inline uint32_t standing(uint32_t state, uint32_t promo)
+{
+    return state | (promo << 3);
+}
+__host__ __device__ inline uint32_t standing_state(uint32_t w) { return w & 7u; }
+__host__ __device__ inline uint32_t standing_promo(uint32_t w) { return w >> 3; }
+
 // Mutable state of one mining run, updated only by kernels during a run.
+// Stop e (epoch e, counted from 1) is one launch: it counts the survivors
+// of stop e-1 (the current list) and the candidates made for stop e-1's new
+// boxes on block e, prunes them, and appends its own survivors to the next
+// list and its promotions to the next new-box list.
 struct JobState {
-    uint32_t done;      // DASHED became empty
+    uint32_t done;      // no candidate left
     uint32_t overflow;  // candidate pool capacity exceeded
-    uint32_t stop;      // current block index 1..stop_max (0 before the first)
-    uint32_t epoch;     // stops executed so far
+    uint32_t stop;      // block index 1..stop_max of the current stop (0 before the first)
+    uint32_t epoch;     // index of the current stop (from 1); promotions are tagged with it
     // survivors appended to the next live list and boxes promoted at this
     // stop: one 64-bit word so that a workgroup reserves both with one atomic
     uint32_t k_next;
     uint32_t n_new;
-    uint32_t K;         // live candidates counted at this stop
-    uint32_t pool_n;    // itemsets in the pool (>= cap means overflow)
+    uint32_t k_cur;     // survivors of the last stop: the current list, counted at this one
+    uint32_t pool_n;    // itemsets in the pool (> cap: overflow)
     uint32_t nL1;       // frequent items
-    uint32_t max_rem;   // stops the surviving candidates certainly still need
-    uint32_t parity;    // live list in use: live[parity]
+    uint32_t max_rem;   // most stops a kept candidate still needs (atomic max)
+    uint32_t parity;    // 1: current list live1, last stop's new boxes newbox1; 0: the others
     uint32_t first;     // block [first, last) of this stop
     uint32_t last;
     uint32_t n_ct;      // count plan: candidate groups
-    uint32_t n_ri;      //             row items
-    uint32_t rpi;       //             rows per row item
+    uint32_t n_ri;      //             row or tile chunks per group
+    uint32_t rpi;       //             rows (row bitmaps) or tiles (bitsets) per chunk
     uint32_t peak_K;
     uint32_t asserts;   // invariant violations (must stay 0)
     unsigned long long tests;
-    uint32_t fw, lw;    // vertical: 64-row words [fw, lw] hold the block
-    uint32_t tw;        // vertical: words per tile
-    uint32_t cpt;       // vertical: candidates per thread
-    uint32_t cmode;     // vertical: 0 LDS tiles, 1 one wave per candidate
-    uint32_t pool_base; // pool size when this stop began: entries at or above
-                        // it were created by this stop's candidate generation;
-                        // they follow the survivors in the next live list
-    uint32_t pending;   // added, not yet moved to its first block
-    uint32_t need;      // stops the current live set certainly still needs
-    uint32_t ks;        // candidates at the head of the current list counted by X
-    uint32_t znc;       // Z tile mode: tile chunks per group of new candidates (0: wave mode)
-    uint32_t ztw;       //              words per item in a tile
-    uint32_t zrpi;      //              tiles per chunk
+    uint32_t fw, lw;    // bitsets: 64-row words [fw, lw] hold the block
+    uint32_t tw;        // bitsets: words per tile
+    uint32_t cpt;       // bitsets: candidates per thread
+    uint32_t cmode;     // bitsets: 0 LDS tiles, 1 one wave per candidate
+    uint32_t pool_base; // pool size when this stop began: entries at or above it
+                        // were made at this stop for the last stop's new boxes
+    uint32_t pending;   // added, its first stop not begun
+    uint32_t need;      // stops the live set certainly still needs after this one
+    uint32_t n_prev;    // boxes promoted at the last stop (extended at this one)
+    uint32_t stops;     // stops completed
+    uint32_t pad[2];
 };
 static_assert(sizeof(JobState) == 128, "JobState is read back as 128-byte records");
 static_assert(offsetof(JobState, k_next) % 8 == 0, "k_next/n_new form one 64-bit word");
 
-// Candidates created since the stop began (they follow the survivors in the
-// next live list), and the size of that list.
-__host__ __device__ inline uint32_t new_candidates(const JobState &s, uint32_t cap)
-{
-    const uint32_t pn = s.pool_n < cap ? s.pool_n : cap;
-    return pn > s.pool_base ? pn - s.pool_base : 0u;
-}
-__host__ __device__ inline uint32_t next_live(const JobState &s, uint32_t cap)
-{
-    return s.k_next + new_candidates(s, cap);
-}
-// Between chunks of stops a job is either pending (added, its first stop not
-// begun) or already begun on its next stop by the last candidate generation.
-inline bool job_running(const JobState &s, uint32_t cap)
+// Between chunks of stops a job is either pending (added, its first stop
+// not begun; it runs if it has first candidates) or begun on its next stop.
+inline bool job_running(const JobState &s, uint32_t)
 {
     if (s.done || s.overflow)
         return false;
-    return s.pending ? next_live(s, cap) > 0 : true;
+    return s.pending ? s.pool_n > 0 : true;
 }
-// Stops the job's current live set certainly still needs.
-inline uint32_t job_need(const JobState &s, uint32_t cap, uint32_t stop_max)
+// Stops the job's live set certainly still needs.
+inline uint32_t job_need(const JobState &s, uint32_t, uint32_t stop_max)
 {
-    if (s.pending)
-        return new_candidates(s, cap) ? stop_max : s.max_rem;
-    return s.need;
+    return s.pending ? stop_max : s.need;
 }
 
 constexpr int KD = 16;  // frequent-item indices stored per candidate (larger: decode the mask)
@@ -212,10 +212,11 @@ struct Job {
     uint16_t *pitems; // cap * KD: frequent-item indices of each itemset (size <= KD)
     unsigned long long *phash;  // Zobrist hash of each itemset
     uint64_t *pnz;    // bitmap of nonzero words
-    uint32_t *psupp, *pstop, *pstate, *ppromo, *pk;
+    uint32_t *psupp, *pstop, *pk;
+    uint32_t *pstate;           // standing word (state, promotion stop) of each itemset
     unsigned long long *slots;  // open addressing: idx<<32 | fp24<<8 | k8
     uint32_t *live0, *live1;    // cap each
-    uint32_t *newbox;           // cap
+    uint32_t *newbox0, *newbox1;  // cap each: boxes promoted at a stop (by parity)
     uint32_t *zarr;             // cap / WG + 1 arrival counters of Z's tile chunks (zero between uses)
     uint32_t *l1;               // m
     uint32_t *item_cnt;         // m
@@ -261,8 +262,8 @@ inline uint64_t pool_cap_for(uint32_t nL1, uint32_t mult)
 
 // Layout of a job's candidate pool buffer (byte offsets of its arrays).
 struct PoolLayout {
-    size_t mask, items, hash, nz, supp, stop, state, promo, k, slots, live0, live1, newbox, zarr,
-        omask, ocnt, okey;
+    size_t mask, items, hash, nz, supp, stop, state, k, slots, live0, live1, newbox0, newbox1,
+        zarr, omask, ocnt, okey;
     size_t bytes;
     uint64_t hslots, zarr_n;
     PoolLayout(uint64_t cap, uint32_t W)
@@ -276,12 +277,12 @@ struct PoolLayout {
         supp = c.take(cap * 4);
         stop = c.take(cap * 4);
         state = c.take(cap * 4);
-        promo = c.take(cap * 4);
         k = c.take(cap * 4);
         slots = c.take(hslots * 8);
         live0 = c.take(cap * 4);
         live1 = c.take(cap * 4);
-        newbox = c.take(cap * 4);
+        newbox0 = c.take(cap * 4);
+        newbox1 = c.take(cap * 4);
         zarr_n = cap / WG + 1;
         zarr = c.take(zarr_n * 4);
         omask = c.take(cap * W * 8);
@@ -295,9 +296,8 @@ struct PoolLayout {
 struct Plan {
     uint32_t njobs;
     uint32_t pad;
-    uint32_t *pre_count;   // row-major count work items
-    uint32_t *pre_countv;  // vertical count work items
-    uint32_t *pre_epi;
+    uint32_t *pre_count;   // row-bitmap count work items (k_count)
+    uint32_t *pre_countv;  // survivors' work items of the stop kernel
     unsigned long long *pre_cg;
     unsigned long long *pre_fp;  // first pass row chunks
     uint32_t vt_target, vt_wave_k, vt_tile_words, count_target;  // see Knobs
@@ -321,12 +321,12 @@ inline void pool_assign(Job &J, const PoolLayout &L, char *b, uint32_t cap)
     J.psupp = (uint32_t *)(b + L.supp);
     J.pstop = (uint32_t *)(b + L.stop);
     J.pstate = (uint32_t *)(b + L.state);
-    J.ppromo = (uint32_t *)(b + L.promo);
     J.pk = (uint32_t *)(b + L.k);
     J.slots = (unsigned long long *)(b + L.slots);
     J.live0 = (uint32_t *)(b + L.live0);
     J.live1 = (uint32_t *)(b + L.live1);
-    J.newbox = (uint32_t *)(b + L.newbox);
+    J.newbox0 = (uint32_t *)(b + L.newbox0);
+    J.newbox1 = (uint32_t *)(b + L.newbox1);
     J.zarr = (uint32_t *)(b + L.zarr);
     J.out_mask = (uint64_t *)(b + L.omask);
     J.out_cnt = (uint32_t *)(b + L.ocnt);

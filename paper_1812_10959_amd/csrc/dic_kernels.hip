@@ -5,14 +5,14 @@
 // a step launches each kernel once for all jobs, and each workgroup or wave
 // locates its job by binary search over per-job prefix sums of work.
 //
-// Per stop (the loop body of Algorithm 2, Section 4.2), two launches:
-//   k_stepx     MakeCandidates (extend new boxes by frequent items) and, in
-//               other workgroups, CountSupport (Algorithm 3) of the last
-//               stop's survivors on the next block (k_count counts row-bitmap
-//               jobs just before); the last workgroup completes the stop
-//   k_stepz     CountSupport of the new candidates, then Prune (Algorithm 4)
-//               and CheckFullPass (Algorithm 5) with compaction of the live
-//               list; the last workgroup moves every job to its next block
+// Per stop (the loop body of Algorithm 2, Section 4.2), one launch:
+//   k_stop      MakeCandidates for the last stop's new boxes, with the new
+//               candidates' CountSupport (Algorithm 3) on this stop's block
+//               and their Prune (Algorithm 4) and CheckFullPass (Algorithm 5)
+//               in the workgroup that made them; in other workgroups the
+//               last stop's survivors are counted on the block and pruned
+//               (k_count counts row-bitmap jobs just before); the last
+//               workgroup completes the stop and begins the next one
 // k_begin starts a chunk of stops: newly added jobs move to their first
 // block, and every job is planned for the current job table.
 // Before the loop: k_first_pass and k_l1 (FirstPass: item supports, the
@@ -27,12 +27,9 @@ namespace {
 
 constexpr uint32_t FP_ROWS = 4096;       // first pass rows per workgroup item
 constexpr uint32_t FPV_WORDS = 4096;     // first pass (bitsets): words per work item
-constexpr int VT_CPT = 8;                // bitset count: candidates per thread at most
+constexpr int VT_CPT = 4;                // bitset count: candidates per thread at most
 constexpr uint32_t NONE = 0xFFFFFFFFu;
-constexpr uint32_t Z_TILE_MIN = 1024;    // new candidates from which Z counts on LDS tiles
-constexpr uint32_t Z_TILE_WORDS = VT_WORDS;  // 64-bit words of Z's tile
-constexpr uint32_t Z_TARGET = 512;       // Z tile-mode work items aimed at per job
-constexpr int ZP = 2;                    // survivors pruned per thread in a Z work item
+constexpr int ZP = 2;                    // row-bitmap survivors pruned per thread
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
@@ -225,71 +222,10 @@ __device__ uint32_t block_sum(uint32_t v, uint32_t *sh)
     return t;
 }
 
-// Workgroup-aggregated append: one atomic on ctr per workgroup; returns the
-// slot of a thread whose pred is true.  Every thread of the workgroup calls.
-// sh holds WG/64 + 1 words.
-__device__ uint32_t block_append(uint32_t *ctr, bool pred, uint32_t *sh)
-{
-    const unsigned long long b = __ballot(pred);
-    const uint32_t wave = threadIdx.x >> 6;
-    if (lane_id() == 0)
-        sh[wave] = (uint32_t)__popcll(b);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (int w = 0; w < WG / 64; ++w) {
-            const uint32_t c = sh[w];
-            sh[w] = t;
-            t += c;
-        }
-        sh[WG / 64] = t ? atomicAdd(ctr, t) : 0u;
-    }
-    __syncthreads();
-    const uint32_t pos = sh[WG / 64] + sh[wave] + (uint32_t)__popcll(b & lanemask_lt());
-    __syncthreads();
-    return pos;
-}
-
-// Two workgroup-aggregated appends with one 64-bit atomic: ctr points at a
-// pair of adjacent u32 counters (low word first); *pa / *pb receive the
-// slots of threads whose a / b is true.  sh holds 2 * (WG/64) + 2 words.
-__device__ void block_append2(uint32_t *ctr, bool a, bool b, uint32_t *sh, uint32_t *pa,
-                              uint32_t *pb)
-{
-    const unsigned long long ba = __ballot(a), bb = __ballot(b);
-    const uint32_t wave = threadIdx.x >> 6;
-    constexpr int NW = WG / 64;
-    if (lane_id() == 0) {
-        sh[wave] = (uint32_t)__popcll(ba);
-        sh[NW + wave] = (uint32_t)__popcll(bb);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t ta = 0, tb = 0;
-        for (int w = 0; w < NW; ++w) {
-            const uint32_t ca = sh[w], cb = sh[NW + w];
-            sh[w] = ta;
-            sh[NW + w] = tb;
-            ta += ca;
-            tb += cb;
-        }
-        unsigned long long old = 0;
-        if (ta | tb)
-            old = atomicAdd((unsigned long long *)ctr,
-                            ((unsigned long long)tb << 32) | (unsigned long long)ta);
-        sh[2 * NW] = (uint32_t)old;
-        sh[2 * NW + 1] = (uint32_t)(old >> 32);
-    }
-    __syncthreads();
-    const unsigned long long lt = lanemask_lt();
-    *pa = sh[2 * NW] + sh[wave] + (uint32_t)__popcll(ba & lt);
-    *pb = sh[2 * NW + 1] + sh[NW + wave] + (uint32_t)__popcll(bb & lt);
-    __syncthreads();
-}
-
-// NQ rounds of two appends (as NQ calls of block_append2, in round order)
-// with one 64-bit atomic for the workgroup.  sh holds 2 * NQ * (WG/64) + 2
-// words.
+// NQ rounds of two workgroup-aggregated appends (ctr points at a pair of
+// adjacent u32 counters, low word first; pa / pb receive the slots of threads
+// whose a / b is true), in round order, with one 64-bit atomic for the
+// workgroup.  sh holds 2 * NQ * (WG/64) + 2 words.
 template <int NQ>
 __device__ void block_append2_rounds(uint32_t *ctr, const bool (&a)[NQ], const bool (&b)[NQ],
                                      uint32_t *sh, uint32_t (&pa)[NQ], uint32_t (&pb)[NQ])
@@ -472,7 +408,6 @@ __global__ __launch_bounds__(WG) void k_l1(const Job *__restrict__ jobs)
         if (threadIdx.x == 0) {
             st->nL1 = J->m;
             st->pending = 1;
-            st->k_next = 0;
             st->pool_base = 0;
             st->pool_n = J->m;
             st->max_rem = 0;
@@ -496,7 +431,6 @@ __global__ __launch_bounds__(WG) void k_l1(const Job *__restrict__ jobs)
         const uint64_t nC2 = (uint64_t)nL1 * (nL1 ? nL1 - 1u : 0u) / 2u;
         st->nL1 = nL1;
         st->pending = 1;
-        st->k_next = 0;  // no survivors: the next live list is the pairs alone
         st->pool_base = 0;
         st->pool_n = (uint32_t)nC2;
         st->max_rem = 0;
@@ -530,8 +464,7 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
             J->pitems[(uint64_t)a * KD] = (uint16_t)a;
             J->psupp[a] = 0;
             J->pstop[a] = 0;
-            J->pstate[a] = ST_DASHED_CIRCLE;
-            J->ppromo[a] = NO_EPOCH;
+            J->pstate[a] = standing(ST_DASHED_CIRCLE, PROMO_NONE);
             J->live1[a] = a;
             hash_insert(J, zob(a), 1, a);
             continue;
@@ -555,9 +488,8 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
         J->pitems[(uint64_t)p * KD + 1] = (uint16_t)b;
         J->psupp[p] = 0;
         J->pstop[p] = 0;
-        J->pstate[p] = ST_DASHED_CIRCLE;
-        J->ppromo[p] = NO_EPOCH;
-        J->live1[p] = p;  // parity starts at 0, so the first stop reads live1
+        J->pstate[p] = standing(ST_DASHED_CIRCLE, PROMO_NONE);
+        J->live1[p] = p;  // the first stop's current list is live1
         // no hash entry: outside the classic start a pair is only ever looked
         // up by its index (MakeCandidates' 2-subsets); larger itemsets and
         // the classic start's pairs go through the hash table
@@ -565,24 +497,33 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
 }
 
 // ---------------------------------------------------------------------------
-// One stop.
+// One stop per launch.
 // ---------------------------------------------------------------------------
+//
+// Stop e (epoch e) is one launch of k_stop (k_count counts the row-bitmap
+// jobs' survivors just before it).  Its work items do not depend on each
+// other:
+//   * MakeCandidates for the boxes promoted at stop e-1: C = S | {a} for a
+//     new box S and a frequent item a.  Each C admitted is counted on block
+//     e by the workgroup that made it (CountSupport, Algorithm 3) and pruned
+//     there at once (Algorithm 4, with CheckFullPass, Algorithm 5);
+//   * CountSupport of the survivors of stop e-1 on block e, then Prune and
+//     CheckFullPass of each (by the last chunk of a candidate group when the
+//     group's block is split over several work items).
+// The last workgroup to finish completes stop e for every job and begins
+// stop e+1: the block advance with the rewind of Algorithm 2, the swap of
+// the live and new-box lists, the plan of the next launch.
+//
+// MakeCandidates for stop e-1 runs while stop e's Prune changes the standing
+// of other itemsets.  It must see each itemset as it stood at the end of
+// stop e-1, and the standing word gives exactly that: an itemset is a box
+// for it only if it was promoted at a stop before e.  The itemsets, counts
+// and per-stop trace are those of the paper's order (at every stop: Count,
+// Prune, MakeCandidates, CheckFullPass).
 
-// A stop runs as two launches, the first overlapping the next block:
-//   X(e)   MakeCandidates for the boxes promoted at stop e and, in other
-//          workgroups, CountSupport of stop e's survivors on block e + 1
-//          (they are already in the next live list); the last workgroup
-//          finishes stop e (the new candidates join the list) and plans Z;
-//   Z(e+1) CountSupport of the candidates created at stop e (one wave each)
-//          on block e + 1, then Prune and CheckFullPass of every candidate of
-//          stop e + 1; the last workgroup moves each job to block e + 2 for
-//          its survivors and plans X.
-// Counting the survivors before MakeCandidates is done changes nothing they
-// count, so results and traces are those of the paper's order.
-
-// Move a job to its next block (Algorithm 2: stop <- stop + 1, rewinding past
-// stop_max) for the survivors in its next live list; they are counted by X.
-__device__ void to_next_block(const Job *J, JobState *st)
+// Begin the job's next stop: the next block (stop <- stop + 1, back to the
+// first block after the last), the next epoch and its zeroed trace entry.
+__device__ void begin_stop(const Job *J, JobState *st)
 {
     const uint32_t stop = st->stop % J->stop_max + 1u;
     st->stop = stop;
@@ -592,97 +533,88 @@ __device__ void to_next_block(const Job *J, JobState *st)
     st->last = (uint32_t)(end < J->n ? end : J->n);
     st->fw = st->first >> 6;  // the block's 64-row words, for the bitset counts
     st->lw = (st->last - 1u) >> 6;
-    // stops the live set certainly still needs: one fewer than when this
-    // stop began, at least the survivors' remaining stops, and at least one
-    // if MakeCandidates is still to run for new boxes
-    const uint32_t left = st->need > 1u ? st->need - 1u : 0u;
-    const uint32_t floor = st->max_rem > (st->n_new ? 1u : 0u) ? st->max_rem
-                                                                 : (st->n_new ? 1u : 0u);
-    st->need = left > floor ? left : floor;
-}
-
-// Finish stop e after MakeCandidates: the created pool entries follow the
-// survivors in the list, which becomes the current list of stop e + 1.
-// pool_n is read atomically (other workgroups of the launch added to it).
-__device__ void finish_stop(const Job *J, JobState *st, uint32_t pool_n, uint32_t tile_words)
-{
-    const uint32_t pn = pool_n < J->cap ? pool_n : J->cap;
-    const uint32_t gen = pn > st->pool_base ? pn - st->pool_base : 0u;
-    if (pool_n > J->cap) {  // MakeCandidates ran out of pool room
-        st->overflow = 1;
-        return;
-    }
-    if (st->epoch >= 1u && st->epoch - 1u < J->trace_cap)
-        J->trace[st->epoch - 1u].generated = gen;
-    const uint32_t K = st->k_next + gen;
-    st->K = K;
-    if (K == 0) {
-        st->done = 1;
-        st->need = 0;
-        return;
-    }
-    // stops the new live set certainly needs: a full pass for a created
-    // candidate, else the survivors' remaining stops (from the last Prune)
-    st->need = gen ? J->stop_max : st->max_rem;
-    st->ks = st->k_next;  // counted already, by X
-    // Z counts the new candidates one wave each unless they are many: then
-    // one thread each on LDS tiles, the tiles split in chunks over workgroups
-    st->znc = 0;
-    const uint32_t nwords = st->lw - st->fw + 1u;
-    if (J->layout == LAYOUT_VERTICAL && gen >= Z_TILE_MIN && st->nL1 <= Z_TILE_WORDS) {
-        const uint32_t tw = vert_tile_words(st->nL1, tile_words, Z_TILE_WORDS);
-        const uint32_t ntile = (nwords + tw - 1u) / tw;
-        const uint32_t groups = (gen + WG - 1u) / WG;
-        uint32_t want = (Z_TARGET + groups - 1u) / groups;  // chunks per group
-        want = want < 1u ? 1u : (want > ntile ? ntile : want);
-        const uint32_t tpc = (ntile + want - 1u) / want;
-        st->ztw = tw;
-        st->zrpi = tpc;
-        st->znc = (ntile + tpc - 1u) / tpc;
-    }
-    st->pool_base = pn;
-    st->k_next = 0;
-    st->n_new = 0;
-    st->max_rem = 0;
-    st->parity ^= 1u;
     st->epoch += 1u;
-    const uint32_t rows = st->last - st->first;
-    st->tests += (unsigned long long)K * rows;
-    if (K > st->peak_K)
-        st->peak_K = K;
     if (st->epoch - 1u < J->trace_cap) {
-        dic_stop_trace t;
-        t.stop = st->stop;
-        t.rows = rows;
-        t.live = K;
-        t.promoted = t.pruned = t.generated = t.solidified = t.words = t.items = 0;
-        t.reserved = 0;
+        dic_stop_trace t{};
         J->trace[st->epoch - 1u] = t;
     }
 }
 
-// Work of X for one job: chunks of MakeCandidates (WG (new box, item) pairs
-// each) and the counting work items of its survivors (k_next of them, in the
-// next list) on the current block, by layout.
-__device__ void plan_x(const Job *J, JobState *st, const Plan *plan, uint32_t *items,
-                       uint32_t *itemsv, unsigned long long *chunks)
+// Complete stop e for one job once every work item of the launch is done
+// (last workgroup): the candidates made at this launch for stop e-1's new
+// boxes (the pool's growth), the trace, then the end of the run or the
+// beginning of stop e+1.  Counters that other workgroups of the launch
+// updated with atomics are read with device-scope atomic loads.
+__device__ void end_stop(const Job *J, JobState *st)
 {
-    *items = *itemsv = 0;
-    *chunks = 0;
-    if (st->done || st->overflow)
+    const uint32_t pn = __hip_atomic_load(&st->pool_n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (pn > J->cap) {  // MakeCandidates ran out of pool room
+        st->overflow = 1;
         return;
-    *chunks = ((unsigned long long)st->n_new * st->nL1 + WG - 1u) / WG;
-    const uint32_t K = st->k_next;
+    }
+    const uint32_t E = st->epoch;
+    const uint32_t gen = pn - st->pool_base;
+    if (E >= 2u && E - 2u < J->trace_cap)
+        J->trace[E - 2u].generated = gen;
+    const uint32_t live = st->k_cur + gen;
+    if (live == 0u) {  // nothing was live at this stop: the run ended with the last one
+        st->done = 1;
+        st->need = 0;
+        st->stops = E - 1u;
+        return;
+    }
+    const uint32_t rows = st->last - st->first;
+    st->stops = E;
+    st->tests += (unsigned long long)live * rows;
+    if (live > st->peak_K)
+        st->peak_K = live;
+    if (E - 1u < J->trace_cap) {
+        dic_stop_trace *t = J->trace + (E - 1u);
+        t->stop = st->stop;
+        t->rows = rows;
+        t->live = live;
+    }
+    const uint32_t kn = __hip_atomic_load(&st->k_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t nn = __hip_atomic_load(&st->n_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t mr = __hip_atomic_load(&st->max_rem, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (kn == 0u && nn == 0u) {  // no survivor and no new box: DASHED stays empty
+        st->done = 1;
+        st->need = 0;
+        return;
+    }
+    st->k_cur = kn;
+    st->n_prev = nn;
+    st->k_next = 0;
+    st->n_new = 0;
+    st->max_rem = 0;
+    st->pool_base = pn;
+    st->parity ^= 1u;
+    // stops certainly still needed: the kept candidates' remaining stops, and
+    // one for the new boxes' candidate generation
+    st->need = mr > (nn ? 1u : 0u) ? mr : (nn ? 1u : 0u);
+    begin_stop(J, st);
+}
+
+// Work of one job in the next launch: chunks of MakeCandidates (WG (new box,
+// frequent item) pairs each), the survivors' work items by layout, and the
+// row-bitmap count's work items (k_count).
+__device__ void plan_stop(const Job *J, JobState *st, const Plan *plan, uint32_t *items_rows,
+                          uint32_t *items_stop, unsigned long long *chunks)
+{
+    *items_rows = *items_stop = 0;
+    *chunks = 0;
+    if (st->done || st->overflow || st->pending)
+        return;
+    *chunks = ((unsigned long long)st->n_prev * st->nL1 + WG - 1u) / WG;
+    const uint32_t K = st->k_cur;
     if (K == 0)
         return;
     const uint32_t first = st->first, last = st->last;
     const uint32_t rows = last - first;
     if (J->layout == LAYOUT_VERTICAL && K < plan->vt_wave_k) {
         // few candidates: one wave per candidate, no tile
-        st->fw = first >> 6;
-        st->lw = (last - 1u) >> 6;
         st->cmode = 1;
-        *itemsv = (K + WG / 64 - 1u) / (WG / 64);
+        *items_stop = (K + WG / 64 - 1u) / (WG / 64);
     } else if (J->layout == LAYOUT_VERTICAL) {
         // (candidate groups of WG * cpt) x (chunks of tiles of tw words)
         st->cmode = 0;
@@ -701,14 +633,14 @@ __device__ void plan_x(const Job *J, JobState *st, const Plan *plan, uint32_t *i
         uint32_t want = ((uint32_t)vt_target + n_cg - 1u) / n_cg;
         want = want < 1u ? 1u : (want > ntile ? ntile : want);
         const uint32_t tpc = (ntile + want - 1u) / want;
-        st->fw = fw;
-        st->lw = lw;
         st->tw = tw;
         st->n_ct = n_cg;
         st->rpi = tpc;
         st->n_ri = (ntile + tpc - 1u) / tpc;
-        *itemsv = n_cg * st->n_ri;
+        *items_stop = n_cg * st->n_ri;
     } else {
+        // k_count counts (row range x candidate group); the stop kernel then
+        // prunes ZP * WG survivors per work item
         const uint32_t rt = row_tile_rows(J->W);
         const uint32_t n_ct = (K + CAND_PER_WG - 1u) / CAND_PER_WG;
         const uint32_t tiles = (rows + rt - 1u) / rt;
@@ -718,21 +650,9 @@ __device__ void plan_x(const Job *J, JobState *st, const Plan *plan, uint32_t *i
         st->n_ct = n_ct;
         st->rpi = rpi;
         st->n_ri = (rows + rpi - 1u) / rpi;
-        *items = n_ct * st->n_ri;
+        *items_rows = n_ct * st->n_ri;
+        *items_stop = (K + ZP * WG - 1u) / (ZP * WG);
     }
-}
-
-// Work of Z for one job: chunks of ZP * WG survivors (counted by X), then the new
-// candidates: groups of WG/64, one wave each (wave mode), or groups of WG, one
-// thread each, times chunks of LDS tiles of the block (tile mode, znc > 0).
-__device__ uint32_t plan_z(const JobState *st)
-{
-    if (st->done || st->overflow || st->K == 0)
-        return 0;
-    const uint32_t nsc = (st->ks + ZP * WG - 1u) / (ZP * WG);
-    if (st->znc)
-        return nsc + (st->K - st->ks + WG - 1u) / WG * st->znc;
-    return nsc + (st->K - st->ks + WG / 64 - 1u) / (WG / 64);
 }
 
 // Arrival counter of a launch, called by one thread per workgroup after the
@@ -760,11 +680,11 @@ __device__ bool arrive_last(uint32_t *tickets, uint32_t n)
     return true;
 }
 
-// Write per-job prefix sums of work: X (rows count, bitset count,
-// MakeCandidates chunks) or Z.  One workgroup, every thread calls; sh holds
-// 2 * (WG/64) words.
-__device__ void write_plan_x(const Job *__restrict__ jobs, Plan *plan, uint32_t *sh,
-                             unsigned long long *shc)
+// Per-job prefix sums of the next launch's work (row-bitmap count items,
+// stop-kernel survivor items, MakeCandidates chunks).  One workgroup, every
+// thread calls; sh holds 2 * (WG/64) words.
+__device__ void write_plan(const Job *__restrict__ jobs, Plan *plan, uint32_t *sh,
+                           unsigned long long *shc)
 {
     const uint32_t njobs = plan->njobs;
     uint32_t carry_c = 0, carry_v = 0;
@@ -779,7 +699,7 @@ __device__ void write_plan_x(const Job *__restrict__ jobs, Plan *plan, uint32_t 
         uint32_t items = 0, itemsv = 0;
         unsigned long long chunks = 0;
         if (j < njobs)
-            plan_x(jobs + j, jobs[j].st, plan, &items, &itemsv, &chunks);
+            plan_stop(jobs + j, jobs[j].st, plan, &items, &itemsv, &chunks);
         uint32_t v[2] = {items, itemsv}, t[2];
         block_scan_n<2>(v, sh, t);
         unsigned long long tg;
@@ -792,22 +712,6 @@ __device__ void write_plan_x(const Job *__restrict__ jobs, Plan *plan, uint32_t 
         carry_c += t[0];
         carry_v += t[1];
         carry_g += tg;
-    }
-}
-
-__device__ void write_plan_z(const Job *__restrict__ jobs, Plan *plan, uint32_t *sh)
-{
-    const uint32_t njobs = plan->njobs;
-    uint32_t carry = 0;
-    if (threadIdx.x == 0)
-        plan->pre_epi[0] = 0;
-    for (uint32_t b = 0; b < njobs; b += WG) {
-        const uint32_t j = b + threadIdx.x;
-        uint32_t v[1] = {j < njobs ? plan_z(jobs[j].st) : 0u}, t[1];
-        block_scan_n<1>(v, sh, t);
-        if (j < njobs)
-            plan->pre_epi[j + 1] = carry + v[0];
-        carry += t[0];
     }
 }
 
@@ -832,9 +736,9 @@ __global__ __launch_bounds__(WG) void k_gather_vert(const Job *__restrict__ jobs
 }
 
 // Start of a chunk of stops (one workgroup).  A job added since the last
-// chunk has its first candidates in the next live list: they become its
-// survivors (counted by X like any), and it moves to its first block.  Every
-// job is then planned for X against the current job table.
+// chunk begins its first stop: its first candidates (pool entries 0..pn-1,
+// already in live1) are the current list, counted like survivors.  Every job
+// is then planned against the current job table.
 __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan *plan)
 {
     __shared__ uint32_t sh[2 * (WG / 64)];
@@ -843,27 +747,32 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
         JobState *st = jobs[j].st;
         if (st->pending && !st->done && !st->overflow) {
             const uint32_t pn = st->pool_n < jobs[j].cap ? st->pool_n : jobs[j].cap;
-            st->k_next = pn;  // every first candidate, in the next list
-            st->pool_base = pn;
+            st->k_cur = pn;
+            st->n_prev = 0;
+            st->k_next = 0;
             st->n_new = 0;
             st->max_rem = 0;
-            st->need = 0;
-            to_next_block(jobs + j, st);
-            st->need = jobs[j].stop_max;  // they need a full pass
+            st->pool_base = pn;
+            st->parity = 1;
+            st->stop = 0;
+            st->epoch = 0;
+            st->need = jobs[j].stop_max;  // a first candidate needs a full pass
             st->pending = 0;
+            begin_stop(jobs + j, st);
         }
     }
     __syncthreads();
-    write_plan_x(jobs, plan, sh, shc);
+    write_plan(jobs, plan, sh, shc);
 }
 
-// CountSupport (Algorithm 3).  Work item = (row range, group of CAND_PER_WG
-// candidates).  The workgroup stages the complemented rows of a tile in LDS
-// as 32-bit planes (plane d holds dword d of every row), each wave takes CW
-// candidates, and for every candidate each lane holds one row per 64-row
-// group: acc = OR over the candidate's nonzero dwords of (c_d AND NOT t_d);
-// the row contains the candidate iff acc == 0.  The 64 answers of a group
-// are counted with a wave ballot and a popcount.
+// CountSupport (Algorithm 3) on row bitmaps, ahead of the stop kernel.  Work
+// item = (row range, group of CAND_PER_WG survivors).  The workgroup stages
+// the complemented rows of a tile in LDS as 32-bit planes (plane d holds
+// dword d of every row), each wave takes CW candidates, and for every
+// candidate each lane holds one row per 64-row group: acc = OR over the
+// candidate's nonzero dwords of (c_d AND NOT t_d); the row contains the
+// candidate iff acc == 0.  The 64 answers of a group are counted with a
+// wave ballot and a popcount.
 __global__ __launch_bounds__(WG) void k_count(const Job *__restrict__ jobs,
                                               const Plan *__restrict__ plan)
 {
@@ -884,9 +793,8 @@ __global__ __launch_bounds__(WG) void k_count(const Job *__restrict__ jobs,
         const uint32_t r_begin = st->first + ri * st->rpi;
         const uint32_t r_lim = r_begin + st->rpi;
         const uint32_t r_end = r_lim < st->last ? r_lim : st->last;
-        // X counts the survivors of the last stop, at the head of the next list
-        const uint32_t K = st->k_next;
-        const uint32_t *live = st->parity ? J->live0 : J->live1;
+        const uint32_t K = st->k_cur;  // the last stop's survivors, in the current list
+        const uint32_t *live = st->parity ? J->live1 : J->live0;
         const uint32_t c0 = ct * CAND_PER_WG + wave * CW;
 
         uint32_t pidx[CW];
@@ -963,35 +871,53 @@ __global__ __launch_bounds__(WG) void k_count(const Job *__restrict__ jobs,
     }
 }
 
-// CountSupport (Algorithm 3) on item bitsets.  Work item = (group of WG
-// candidates, chunk of tiles).  A tile holds, for every frequent item, its
-// bitset over tw consecutive 64-row words of the block (edge words masked to
-// the block).  Each thread owns one candidate: it ANDs the tile rows of the
-// candidate's items word by word and popcounts the result, so a 64-bit AND
-// tests 64 transactions at once.  Lanes of a wave mostly share all but one
-// item (candidates are appended per generating itemset), so most tile reads
-// are broadcasts.
-// CountSupport of candidate p by one wave over every 64-row word of the
+// What the bitset counts need of a candidate: its size and, with at most KD
+// items, its frequent-item indices (16 x u16, ascending).  A larger one is
+// counted from a pool entry's mask (wide) plus at most one extra frequent
+// item (a candidate made at this stop from its generating box).
+struct CandItems {
+    uint32_t k;
+    uint32_t pk32[KD / 2];
+    uint32_t wide;   // pool entry whose mask holds the items (k > KD)
+    uint32_t extra;  // frequent-item index added to it, or NONE
+};
+
+__device__ __forceinline__ CandItems cand_items(const Job *J, uint32_t p)
+{
+    CandItems ci;
+    ci.k = J->pk[p];
+    ci.wide = p;
+    ci.extra = NONE;
+    if (ci.k <= (uint32_t)KD) {
+        const uint4 *ip = (const uint4 *)(J->pitems + (uint64_t)p * KD);
+        const uint4 h0 = ip[0], h1 = ip[1];
+        ci.pk32[0] = h0.x; ci.pk32[1] = h0.y; ci.pk32[2] = h0.z; ci.pk32[3] = h0.w;
+        ci.pk32[4] = h1.x; ci.pk32[5] = h1.y; ci.pk32[6] = h1.z; ci.pk32[7] = h1.w;
+    } else {
+#pragma unroll
+        for (int t = 0; t < KD / 2; ++t)
+            ci.pk32[t] = 0u;
+    }
+    return ci;
+}
+
+// CountSupport of one candidate by one wave over every 64-row word of the
 // current block, straight from the item bitsets (no tile).  Returns the
 // count in every lane.
-__device__ __forceinline__ uint32_t count_wave_bitsets(const Job *J, const JobState *st, uint32_t p)
+__device__ __forceinline__ uint32_t count_wave_bitsets(const Job *J, const JobState *st,
+                                                       const CandItems &ci)
 {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t k = J->pk[p];
     const uint64_t lo_mask = ~0ull << (st->first & 63u);
     const uint64_t hi_mask =
         (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
     const uint32_t nw = J->nw;
     uint32_t cnt = 0;
-    if (k <= (uint32_t)KD) {
-        // item rows from the candidate's item list: the loads of all
-        // its items for a word are independent
-        uint32_t iw[KD / 2];
-        load_items(J->pitems + (uint64_t)p * KD, iw);
+    if (ci.k <= (uint32_t)KD) {
         uint32_t row[KD];
 #pragma unroll
         for (int t = 0; t < KD; ++t)
-            row[t] = (uint32_t)t < k ? item_at(iw, t) : 0u;
+            row[t] = (uint32_t)t < ci.k ? (ci.pk32[t >> 1] >> (16 * (t & 1))) & 0xFFFFu : 0u;
         // 3 words per lane per pass: all their loads issued together
         for (uint32_t w0 = st->fw + lane; w0 <= st->lw; w0 += 192u) {
             uint64_t acc[3];
@@ -1003,7 +929,7 @@ __device__ __forceinline__ uint32_t count_wave_bitsets(const Job *J, const JobSt
             }
 #pragma unroll
             for (int t = 0; t < KD; ++t)
-                if ((uint32_t)t < k) {
+                if ((uint32_t)t < ci.k) {
 #pragma unroll
                     for (int u = 0; u < 3; ++u) {
                         const uint32_t w = w0 + 64u * u;
@@ -1016,11 +942,13 @@ __device__ __forceinline__ uint32_t count_wave_bitsets(const Job *J, const JobSt
                 cnt += (uint32_t)__popcll(acc[u]);
         }
     } else {
-        const uint64_t nz = J->pnz[p];
-        const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+        const uint64_t nz = J->pnz[ci.wide];
+        const uint64_t *cm = J->pmask + (uint64_t)ci.wide * J->W;
         for (uint32_t w = st->fw + lane; w <= st->lw; w += 64) {
             uint64_t acc =
                 (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull);
+            if (ci.extra != NONE)
+                acc &= J->fvert[(uint64_t)ci.extra * nw + w];
             uint64_t nzw = nz;
             while (nzw) {
                 const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
@@ -1034,6 +962,34 @@ __device__ __forceinline__ uint32_t count_wave_bitsets(const Job *J, const JobSt
             }
             cnt += (uint32_t)__popcll(acc);
         }
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        cnt += (uint32_t)__shfl_xor((int)cnt, off);
+    return cnt;
+}
+
+// CountSupport of one candidate by one wave over the current block in row
+// bitmaps: lanes take rows, each testing (row & I) == I on I's nonzero
+// words.  I is pool entry p's mask plus item `extra` (NONE: none).
+__device__ __forceinline__ uint32_t count_wave_rows(const Job *J, const JobState *st, uint32_t p, uint32_t extra)
+{
+    const uint32_t W = J->W, lane = threadIdx.x & 63u;
+    const uint64_t *I = J->pmask + (uint64_t)p * W;
+    const uint32_t xw = extra != NONE ? extra >> 6 : 0xFFFFFFFFu;
+    const uint64_t xb = extra != NONE ? 1ull << (extra & 63u) : 0ull;
+    const uint64_t nz = J->pnz[p] | (extra != NONE ? 1ull << xw : 0ull);
+    uint32_t cnt = 0;
+    for (uint32_t r = st->first + lane; r < st->last; r += 64u) {
+        const uint64_t *row = J->rows + (uint64_t)r * W;
+        bool in = true;
+        uint64_t nzw = nz;
+        while (nzw && in) {
+            const uint32_t w = (uint32_t)__builtin_ctzll(nzw);
+            nzw &= nzw - 1;
+            const uint64_t iw = I[w] | (w == xw ? xb : 0ull);
+            in = (row[w] & iw) == iw;
+        }
+        cnt += in ? 1u : 0u;
     }
     for (int off = 32; off > 0; off >>= 1)
         cnt += (uint32_t)__shfl_xor((int)cnt, off);
@@ -1073,33 +1029,9 @@ __device__ __forceinline__ void stage_tile(const Job *J, const JobState *st, uin
     __syncthreads();
 }
 
-// A candidate's size and, when it has at most KD items, its frequent-item
-// indices (16 x u16, ascending), read once for several tiles.
-struct CandItems {
-    uint32_t k;
-    uint32_t pk32[KD / 2];
-};
-
-__device__ __forceinline__ CandItems cand_items(const Job *J, uint32_t p)
-{
-    CandItems ci;
-    ci.k = J->pk[p];
-    if (ci.k <= (uint32_t)KD) {
-        const uint4 *ip = (const uint4 *)(J->pitems + (uint64_t)p * KD);
-        const uint4 h0 = ip[0], h1 = ip[1];
-        ci.pk32[0] = h0.x; ci.pk32[1] = h0.y; ci.pk32[2] = h0.z; ci.pk32[3] = h0.w;
-        ci.pk32[4] = h1.x; ci.pk32[5] = h1.y; ci.pk32[6] = h1.z; ci.pk32[7] = h1.w;
-    } else {
-#pragma unroll
-        for (int t = 0; t < KD / 2; ++t)
-            ci.pk32[t] = 0u;
-    }
-    return ci;
-}
-
-// Transactions of a staged tile (nwt words) that contain candidate p (items
-// ci): the AND of its items' tile rows, popcounted.
-__device__ __forceinline__ uint32_t and_tile_items(const Job *J, uint32_t p, const CandItems &ci,
+// Transactions of a staged tile (nwt words) that contain the candidate: the
+// AND of its items' tile rows, popcounted.
+__device__ __forceinline__ uint32_t and_tile_items(const Job *J, const CandItems &ci,
                                                    const uint64_t *tile, uint32_t ts, uint32_t nwt)
 {
     uint64_t acc[VT_MAXW];
@@ -1119,8 +1051,15 @@ __device__ __forceinline__ uint32_t and_tile_items(const Job *J, uint32_t p, con
             }
         }
     } else {
-        uint64_t nzw = J->pnz[p];
-        const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+        if (ci.extra != NONE) {
+            const uint64_t *row = tile + ci.extra * ts;
+#pragma unroll
+            for (int w = 0; w < VT_MAXW; ++w)
+                if ((uint32_t)w < nwt)
+                    acc[w] &= row[w];
+        }
+        uint64_t nzw = J->pnz[ci.wide];
+        const uint64_t *cm = J->pmask + (uint64_t)ci.wide * J->W;
         while (nzw) {
             const uint32_t wd = (uint32_t)__builtin_ctzll(nzw);
             nzw &= nzw - 1;
@@ -1144,26 +1083,182 @@ __device__ __forceinline__ uint32_t and_tile_items(const Job *J, uint32_t p, con
     return sum;
 }
 
-// CountSupport (Algorithm 3) on item bitsets, one work item of X: the
-// survivors of the last stop (head of the next live list) on the current
-// block.  Work item = (group of WG candidates, chunk of tiles).  A tile
-// holds, for every frequent item, its bitset over tw consecutive 64-row
-// words of the block (edge words masked to the block).  Each thread owns
-// cpt candidates: it ANDs the tile rows of each candidate's items word by
-// word and popcounts the result, so a 64-bit AND tests 64 transactions at
-// once.  With few candidates (wave mode) one wave counts each candidate
-// with no tile.  Every thread of the workgroup calls.
-__device__ __forceinline__ void count_vert_item(const Job *J, const JobState *st, uint32_t local, uint64_t *tile)
+// Nonzero 32-bit words of a pool entry's mask (the row-bitmap count's AND
+// work per transaction, for the trace), with an optional extra item.
+__device__ __forceinline__ uint32_t mask_dwords(const Job *J, uint32_t p, uint32_t extra)
 {
-    if (st->cmode == 1) {
-        const uint32_t c = local * (WG / 64) + (threadIdx.x >> 6);
-        if (c < st->k_next) {
-            const uint32_t p =
-                __builtin_amdgcn_readfirstlane((st->parity ? J->live0 : J->live1)[c]);
-            const uint32_t cnt = count_wave_bitsets(J, st, p);
-            if ((threadIdx.x & 63u) == 0 && cnt)
-                J->psupp[p] += cnt;  // the only writer of this candidate's count
+    uint32_t words = 0;
+    const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
+    uint64_t nzw = J->pnz[p] | (extra != NONE ? 1ull << (extra >> 6) : 0ull);
+    while (nzw) {
+        const uint32_t w = (uint32_t)__builtin_ctzll(nzw);
+        nzw &= nzw - 1;
+        const uint64_t v = cm[w] | (extra != NONE && w == (extra >> 6) ? 1ull << (extra & 63u) : 0ull);
+        words += ((uint32_t)v != 0u) + ((uint32_t)(v >> 32) != 0u);
+    }
+    return words;
+}
+
+// Prune (Algorithm 4) and CheckFullPass (Algorithm 5) of NQ candidates per
+// thread at this stop.  For candidate q (when valid): p its pool entry, supp
+// its support after this stop's count, sc the stops it has been counted on
+// now (Algorithm 3's stop_I + 1), stw its standing before this stop, items
+// its size, words its nonzero mask dwords (row bitmaps).  A dashed circle
+// with supp >= tau becomes a box (promoted at this epoch); otherwise, if
+// supp + M * (stop_max - sc) < tau it is pruned (kept as known, never output
+// or generated again).  One that has seen every block becomes solid.
+// Survivors go to the next live list and new boxes to the next new-box list,
+// with one append atomic per workgroup; the stop's statistics are summed
+// over the workgroup.  Every thread of the workgroup calls.
+template <int NQ>
+__device__ __forceinline__ void prune_core(const Job *J, JobState *st, const uint32_t (&p)[NQ],
+                           const uint32_t (&supp)[NQ], const uint32_t (&sc)[NQ],
+                           const uint32_t (&stw)[NQ], const uint32_t (&items)[NQ],
+                           const uint32_t (&words)[NQ], const bool (&valid)[NQ], uint32_t *sh_app,
+                           uint32_t *sh_red)
+{
+    const uint32_t E = st->epoch;
+    bool keep[NQ], promoted[NQ];
+    uint32_t nwords = 0, nitems = 0, npro = 0, npru = 0, nsol = 0, rem = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        keep[q] = promoted[q] = false;
+        if (!valid[q])
+            continue;
+        nwords += words[q];
+        nitems += items[q];
+        uint32_t state = standing_state(stw[q]), promo = standing_promo(stw[q]);
+        bool pruned = false;
+        if (state == ST_DASHED_CIRCLE) {
+            if (supp[q] >= J->tau) {
+                state = ST_DASHED_BOX;
+                promo = E;
+                promoted[q] = true;
+                ++npro;
+            } else if ((uint64_t)supp[q] + (uint64_t)J->Mp * (uint64_t)(J->stop_max - sc[q]) <
+                       (uint64_t)J->tau) {
+                state = ST_PRUNED;
+                pruned = true;
+                ++npru;
+            }
         }
+        if (!pruned) {
+            if (sc[q] == J->stop_max) {
+                ++nsol;
+                state = state == ST_DASHED_BOX ? ST_SOLID_BOX : ST_SOLID_CIRCLE;
+            } else {
+                keep[q] = true;
+                const uint32_t r = J->stop_max - sc[q];
+                rem = r > rem ? r : rem;
+            }
+        }
+        J->pstop[p[q]] = sc[q];
+        J->pstate[p[q]] = standing(state, promo);
+    }
+    uint32_t *next = st->parity ? J->live0 : J->live1;
+    uint32_t *nbox = st->parity ? J->newbox0 : J->newbox1;
+    uint32_t pos[NQ], npos[NQ];
+    block_append2_rounds<NQ>(&st->k_next, keep, promoted, sh_app, pos, npos);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (keep[q])
+            next[pos[q]] = p[q];
+        if (promoted[q])
+            nbox[npos[q]] = p[q];
+    }
+    uint32_t v[6] = {nwords, nitems, npro, npru, nsol, rem};
+    block_reduce<5>(v, sh_red);
+    if (threadIdx.x == 0) {
+        dic_stop_trace *tr = trace_of(J, st);
+        if (tr) {
+            if (v[0])
+                atomicAdd(&tr->words, v[0]);
+            if (v[1])
+                atomicAdd(&tr->items, v[1]);
+            if (v[2])
+                atomicAdd(&tr->promoted, v[2]);
+            if (v[3])
+                atomicAdd(&tr->pruned, v[3]);
+            if (v[4])
+                atomicAdd(&tr->solidified, v[4]);
+        }
+        if (v[5])
+            atomicMax(&st->max_rem, v[5]);
+    }
+}
+
+// Prune and CheckFullPass of NQ survivors per thread whose supports after
+// this stop's count are supp: their standing, stops and sizes are loaded
+// together first.  Every thread of the workgroup calls.
+template <int NQ>
+__device__ __forceinline__ void prune_survivors(const Job *J, JobState *st, const uint32_t (&p)[NQ],
+                                const uint32_t (&supp)[NQ], const bool (&valid)[NQ],
+                                uint32_t *sh_app, uint32_t *sh_red)
+{
+    uint32_t sc[NQ], stw[NQ], items[NQ], words[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        sc[q] = valid[q] ? J->pstop[p[q]] + 1u : 0u;
+        stw[q] = valid[q] ? J->pstate[p[q]] : 0u;
+        items[q] = valid[q] ? J->pk[p[q]] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        words[q] = valid[q] && J->layout == LAYOUT_ROWS ? mask_dwords(J, p[q], NONE) : 0u;
+    prune_core<NQ>(J, st, p, supp, sc, stw, items, words, valid, sh_app, sh_red);
+}
+
+// Work item of the survivors of the last stop (the current list) at this
+// stop.  Bitsets, wave mode: WG/64 candidates, one wave each, counted over
+// the whole block, then pruned.  Bitsets, tile mode: (group of WG * cpt
+// candidates) x (chunk of tiles); each thread ANDs the tile rows of its
+// candidates' items word by word and popcounts, so a 64-bit AND tests 64
+// transactions.  With one chunk per group the work item prunes its group;
+// otherwise each chunk adds its partial counts with atomics that return the
+// old value (so each thread has waited for its adds before the barrier
+// below: a barrier alone does not wait for other waves' atomics), one
+// thread adds 1 to the group's counter, and the chunk that arrives last
+// reads the totals at device scope and prunes the group.  Row bitmaps:
+// k_count has counted; ZP * WG survivors are pruned.  Every thread calls.
+__device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uint64_t *tile, uint32_t *sh_app,
+                               uint32_t *sh_red, uint32_t *sh_supp, uint32_t *sh_flag)
+{
+    JobState *st = J->st;
+    const uint32_t *cur = st->parity ? J->live1 : J->live0;
+    const uint32_t K = st->k_cur;
+    if (J->layout == LAYOUT_ROWS) {
+        uint32_t p[ZP], supp[ZP];
+        bool valid[ZP];
+#pragma unroll
+        for (int q = 0; q < ZP; ++q) {
+            const uint32_t c = local * (ZP * WG) + (uint32_t)q * WG + threadIdx.x;
+            valid[q] = c < K;
+            p[q] = valid[q] ? cur[c] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < ZP; ++q)
+            supp[q] = valid[q] ? J->psupp[p[q]] : 0u;
+        prune_survivors<ZP>(J, st, p, supp, valid, sh_app, sh_red);
+        return;
+    }
+    if (st->cmode == 1) {
+        const uint32_t wave = threadIdx.x >> 6;
+        const uint32_t c = local * (WG / 64) + wave;
+        if (c < K) {
+            const uint32_t p = __builtin_amdgcn_readfirstlane(cur[c]);
+            const uint32_t cnt = count_wave_bitsets(J, st, cand_items(J, p));
+            if ((threadIdx.x & 63u) == 0) {
+                const uint32_t supp = J->psupp[p] + cnt;  // the only writer of this count
+                J->psupp[p] = supp;
+                sh_supp[wave] = supp;
+            }
+        }
+        __syncthreads();
+        const uint32_t c1 = local * (WG / 64) + threadIdx.x;
+        bool valid[1] = {threadIdx.x < WG / 64 && c1 < K};
+        uint32_t p[1] = {valid[0] ? cur[c1] : 0u};
+        uint32_t supp[1] = {valid[0] ? sh_supp[threadIdx.x] : 0u};
+        prune_survivors<1>(J, st, p, supp, valid, sh_app, sh_red);
         return;
     }
     const uint32_t n_cg = st->n_ct;
@@ -1174,14 +1269,14 @@ __device__ __forceinline__ void count_vert_item(const Job *J, const JobState *st
     const uint32_t ntile = (lw - fw + tw) / tw;
     const uint32_t t0 = rc * st->rpi;
     const uint32_t t1 = t0 + st->rpi < ntile ? t0 + st->rpi : ntile;
-    const uint32_t K = st->k_next;  // survivors, at the head of the next list
     const uint32_t cpt = st->cpt;
-    const uint32_t *live = st->parity ? J->live0 : J->live1;
     uint32_t pidx[VT_CPT], cnt[VT_CPT];
+    bool valid[VT_CPT];
 #pragma unroll
     for (int q = 0; q < VT_CPT; ++q) {
         const uint32_t c = (cg * cpt + (uint32_t)q) * WG + threadIdx.x;
-        pidx[q] = ((uint32_t)q < cpt && c < K) ? live[c] : NONE;
+        valid[q] = (uint32_t)q < cpt && c < K;
+        pidx[q] = valid[q] ? cur[c] : 0u;
         cnt[q] = 0;
     }
     for (uint32_t t = t0; t < t1; ++t) {
@@ -1189,346 +1284,51 @@ __device__ __forceinline__ void count_vert_item(const Job *J, const JobState *st
         const uint32_t nwt = (lw + 1u - w0) < tw ? (lw + 1u - w0) : tw;
         // the first candidate's item list loads during the tile fill, and
         // each next one's while the current one is ANDed
-        CandItems cur = pidx[0] != NONE ? cand_items(J, pidx[0]) : CandItems{};
+        CandItems cur_ci = valid[0] ? cand_items(J, pidx[0]) : CandItems{};
         stage_tile(J, st, w0, nwt, ts, tile);
 #pragma unroll
         for (int q = 0; q < VT_CPT; ++q) {
             CandItems nxt{};
-            if (q + 1 < VT_CPT && pidx[q + 1] != NONE)
+            if (q + 1 < VT_CPT && valid[q + 1])
                 nxt = cand_items(J, pidx[q + 1]);
-            if (pidx[q] != NONE)
-                cnt[q] += and_tile_items(J, pidx[q], cur, tile, ts, nwt);
-            cur = nxt;
+            if (valid[q])
+                cnt[q] += and_tile_items(J, cur_ci, tile, ts, nwt);
+            cur_ci = nxt;
         }
     }
+    uint32_t supp[VT_CPT];
+    if (st->n_ri == 1u) {
 #pragma unroll
-    for (int q = 0; q < VT_CPT; ++q)
-        if (pidx[q] != NONE && cnt[q])
-            atomicAdd(J->psupp + pidx[q], cnt[q]);
-}
-
-// Prune (Algorithm 4) and CheckFullPass (Algorithm 5) for live candidate p
-// (when valid) whose support after this stop's count is supp.  It is counted
-// for stop_I += 1 here (Algorithm 3's first line).  Survivors go to the next
-// live list and new boxes to the promoted list; appends and statistics are
-// aggregated over the workgroup (one atomic per counter), so every thread of
-// the workgroup calls.
-__device__ void prune_and_check(const Job *J, JobState *st, bool valid, uint32_t p, uint32_t supp,
-                                uint32_t *sh_app, uint32_t *sh_red)
-{
-    bool promoted = false, pruned = false, solid = false, keep = false;
-    uint32_t sc = 0, words = 0, items = 0;
-    if (valid) {
-        items = J->pk[p];
-        if (J->layout == LAYOUT_ROWS) {
-            // nonzero 32-bit words of this candidate: its AND work per row
-            uint64_t nzw = J->pnz[p];
-            const uint64_t *cm = J->pmask + (uint64_t)p * J->W;
-            while (nzw) {
-                const uint64_t v = cm[__builtin_ctzll(nzw)];
-                nzw &= nzw - 1;
-                words += ((uint32_t)v != 0u) + ((uint32_t)(v >> 32) != 0u);
-            }
-        }
-        sc = J->pstop[p] + 1u;
-        J->pstop[p] = sc;
-        uint32_t state = J->pstate[p];
-        if (state == ST_DASHED_CIRCLE) {
-            if (supp >= J->tau) {
-                state = ST_DASHED_BOX;
-                J->ppromo[p] = st->epoch;
-                promoted = true;
-            } else if ((uint64_t)supp + (uint64_t)J->Mp * (uint64_t)(J->stop_max - sc) <
-                       (uint64_t)J->tau) {
-                state = ST_PRUNED;
-                pruned = true;
-            }
-        }
-        if (!pruned) {
-            if (sc == J->stop_max) {
-                solid = true;
-                state = state == ST_DASHED_BOX ? ST_SOLID_BOX : ST_SOLID_CIRCLE;
-            } else {
-                keep = true;
-            }
-        }
-        J->pstate[p] = state;
-    }
-    uint32_t *next = st->parity ? J->live0 : J->live1;
-    uint32_t pos, npos;
-    block_append2(&st->k_next, keep, promoted, sh_app, &pos, &npos);
-    if (keep)
-        next[pos] = p;
-    if (promoted)
-        J->newbox[npos] = p;
-    uint32_t v[6] = {words, items, promoted ? 1u : 0u, pruned ? 1u : 0u, solid ? 1u : 0u,
-                     keep ? J->stop_max - sc : 0u};
-    block_reduce<5>(v, sh_red);
-    if (threadIdx.x == 0) {
-        dic_stop_trace *tr = trace_of(J, st);
-        if (tr) {
-            atomicAdd(&tr->words, v[0]);
-            atomicAdd(&tr->items, v[1]);
-            if (v[2])
-                atomicAdd(&tr->promoted, v[2]);
-            if (v[3])
-                atomicAdd(&tr->pruned, v[3]);
-            if (v[4])
-                atomicAdd(&tr->solidified, v[4]);
-        }
-        if (v[5])
-            atomicMax(&st->max_rem, v[5]);
-    }
-}
-
-// Prune and CheckFullPass of the survivors at list positions [c0, c0 + ZP*WG)
-// below cend, ZP per thread (position c0 + q*WG + thread), whose counts X has
-// completed: the same decisions as prune_and_check, with every candidate's
-// loads issued together and one append atomic and one set of statistics
-// atomics per workgroup.  Every thread of the workgroup calls.
-template <int NQ>
-__device__ void prune_survivors(const Job *J, JobState *st, const uint32_t *cur, uint32_t c0,
-                                uint32_t cend, uint32_t *sh_app, uint32_t *sh_red)
-{
-    uint32_t p[NQ], supp[NQ], sc[NQ], state[NQ], items[NQ];
-    bool valid[NQ];
+        for (int q = 0; q < VT_CPT; ++q)
+            supp[q] = valid[q] ? J->psupp[pidx[q]] + cnt[q] : 0u;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const uint32_t c = c0 + (uint32_t)q * WG + threadIdx.x;
-        valid[q] = c < cend;
-        p[q] = valid[q] ? cur[c] : 0u;
-    }
+        for (int q = 0; q < VT_CPT; ++q)
+            if (valid[q])
+                J->psupp[pidx[q]] = supp[q];  // the only writer of these counts
+    } else {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        supp[q] = valid[q] ? J->psupp[p[q]] : 0u;
-        sc[q] = valid[q] ? J->pstop[p[q]] + 1u : 0u;
-        state[q] = valid[q] ? J->pstate[p[q]] : 0u;
-        items[q] = valid[q] ? J->pk[p[q]] : 0u;
-    }
-    bool keep[NQ], promoted[NQ];
-    uint32_t words = 0, nitems = 0, npro = 0, npru = 0, nsol = 0, rem = 0;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        keep[q] = promoted[q] = false;
-        if (!valid[q])
-            continue;
-        const uint32_t pq = p[q];
-        if (J->layout == LAYOUT_ROWS) {
-            uint64_t nzw = J->pnz[pq];
-            const uint64_t *cm = J->pmask + (uint64_t)pq * J->W;
-            while (nzw) {
-                const uint64_t v = cm[__builtin_ctzll(nzw)];
-                nzw &= nzw - 1;
-                words += ((uint32_t)v != 0u) + ((uint32_t)(v >> 32) != 0u);
+        for (int q = 0; q < VT_CPT; ++q)
+            if (valid[q] && cnt[q]) {
+                const uint32_t before = atomicAdd(J->psupp + pidx[q], cnt[q]);
+                if (before + cnt[q] > J->n)  // a support never exceeds n
+                    atomicAdd(&st->asserts, 1u);
             }
-        }
-        nitems += items[q];
-        J->pstop[pq] = sc[q];
-        uint32_t stt = state[q];
-        bool pruned = false;
-        if (stt == ST_DASHED_CIRCLE) {
-            if (supp[q] >= J->tau) {
-                stt = ST_DASHED_BOX;
-                J->ppromo[pq] = st->epoch;
-                promoted[q] = true;
-                ++npro;
-            } else if ((uint64_t)supp[q] + (uint64_t)J->Mp * (uint64_t)(J->stop_max - sc[q]) <
-                       (uint64_t)J->tau) {
-                stt = ST_PRUNED;
-                pruned = true;
-                ++npru;
-            }
-        }
-        if (!pruned) {
-            if (sc[q] == J->stop_max) {
-                ++nsol;
-                stt = stt == ST_DASHED_BOX ? ST_SOLID_BOX : ST_SOLID_CIRCLE;
-            } else {
-                keep[q] = true;
-                const uint32_t r = J->stop_max - sc[q];
-                rem = r > rem ? r : rem;
-            }
-        }
-        J->pstate[pq] = stt;
-    }
-    uint32_t *next = st->parity ? J->live0 : J->live1;
-    uint32_t pos[NQ], npos[NQ];
-    block_append2_rounds<NQ>(&st->k_next, keep, promoted, sh_app, pos, npos);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        if (keep[q])
-            next[pos[q]] = p[q];
-        if (promoted[q])
-            J->newbox[npos[q]] = p[q];
-    }
-    uint32_t v[6] = {words, nitems, npro, npru, nsol, rem};
-    block_reduce<5>(v, sh_red);
-    if (threadIdx.x == 0) {
-        dic_stop_trace *tr = trace_of(J, st);
-        if (tr) {
-            atomicAdd(&tr->words, v[0]);
-            atomicAdd(&tr->items, v[1]);
-            if (v[2])
-                atomicAdd(&tr->promoted, v[2]);
-            if (v[3])
-                atomicAdd(&tr->pruned, v[3]);
-            if (v[4])
-                atomicAdd(&tr->solidified, v[4]);
-        }
-        if (v[5])
-            atomicMax(&st->max_rem, v[5]);
-    }
-}
-
-// CountSupport of a candidate by one wave over the current block in row
-// bitmaps: lanes take rows, each testing (row & I) == I on I's nonzero words.
-__device__ uint32_t count_wave_rows(const Job *J, const JobState *st, uint32_t p)
-{
-    const uint32_t W = J->W, lane = threadIdx.x & 63u;
-    const uint64_t *I = J->pmask + (uint64_t)p * W;
-    const uint64_t nz = J->pnz[p];
-    uint32_t cnt = 0;
-    for (uint32_t r = st->first + lane; r < st->last; r += 64u) {
-        const uint64_t *row = J->rows + (uint64_t)r * W;
-        bool in = true;
-        uint64_t nzw = nz;
-        while (nzw && in) {
-            const uint32_t w = (uint32_t)__builtin_ctzll(nzw);
-            nzw &= nzw - 1;
-            in = (row[w] & I[w]) == I[w];
-        }
-        cnt += in ? 1u : 0u;
-    }
-    for (int off = 32; off > 0; off >>= 1)
-        cnt += (uint32_t)__shfl_xor((int)cnt, off);
-    return cnt;
-}
-
-// Z: Prune and CheckFullPass of every candidate of the stop.  Work items of a
-// job: chunks of WG survivors (counted by X), then groups of WG/64 candidates
-// created at the last stop, which one wave each counts on the block first.
-// The last workgroup to finish moves every job to its next block and plans X.
-__global__ __launch_bounds__(WG) void k_stepz(const Job *__restrict__ jobs, Plan *plan)
-{
-    __shared__ uint32_t sh_app[2 * ZP * (WG / 64) + 2];
-    __shared__ uint32_t sh_red[6 * (WG / 64)];
-    __shared__ uint32_t sh_supp[WG / 64];
-    __shared__ uint64_t tile[Z_TILE_WORDS];
-    __shared__ unsigned long long shc[WG / 64];
-    __shared__ uint32_t sh_last;
-    const uint32_t total = plan->pre_epi[plan->njobs];
-    for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
-        const uint32_t j = find_job(plan->pre_epi, plan->njobs, it);
-        const Job *J = jobs + j;
-        JobState *st = J->st;
-        const uint32_t local = it - plan->pre_epi[j];
-        const uint32_t *cur = st->parity ? J->live1 : J->live0;
-        const uint32_t ks = st->ks, K = st->K;
-        const uint32_t nsc = (ks + ZP * WG - 1u) / (ZP * WG);
-        if (local < nsc) {
-            prune_survivors<ZP>(J, st, cur, local * ZP * WG, ks, sh_app, sh_red);
-        } else if (st->znc) {
-            // tile mode: work item = (group of WG new candidates, one per
-            // thread) x (chunk of zrpi tiles of the block, staged in LDS)
-            const uint32_t wi = local - nsc;
-            const uint32_t g = wi / st->znc, r = wi - g * st->znc;
-            const uint32_t c = ks + g * WG + threadIdx.x;
-            const bool valid = c < K;
-            const uint32_t p = valid ? cur[c] : 0u;
-            const CandItems ci = valid ? cand_items(J, p) : CandItems{};
-            const uint32_t tw = st->ztw, ts = vert_tile_stride(tw);
-            const uint32_t ntile = (st->lw - st->fw + tw) / tw;
-            const uint32_t t0 = r * st->zrpi;
-            const uint32_t t1 = t0 + st->zrpi < ntile ? t0 + st->zrpi : ntile;
-            uint32_t cnt = 0;
-            for (uint32_t t = t0; t < t1; ++t) {
-                const uint32_t w0 = st->fw + t * tw;
-                const uint32_t nwt = (st->lw + 1u - w0) < tw ? (st->lw + 1u - w0) : tw;
-                stage_tile(J, st, w0, nwt, ts, tile);
-                if (valid)
-                    cnt += and_tile_items(J, p, ci, tile, ts, nwt);
-            }
-            uint32_t supp = 0;
-            if (st->znc == 1u) {
-                if (valid) {
-                    supp = J->psupp[p] + cnt;
-                    J->psupp[p] = supp;  // the only writer of this candidate's count
-                }
-            } else {
-                // partial count of this chunk; the group's last chunk to
-                // arrive prunes.  The add returns its old value, so this
-                // thread has waited for it before the barrier below (a
-                // barrier alone does not wait for other waves' atomics).
-                if (valid && cnt) {
-                    const uint32_t before = atomicAdd(J->psupp + p, cnt);
-                    if (before + cnt > J->n)  // a support never exceeds n
-                        atomicAdd(&st->asserts, 1u);
-                }
-                __syncthreads();
-                if (threadIdx.x == 0)
-                    sh_last = atomicAdd(J->zarr + g, 1u) == st->znc - 1u;
-                __syncthreads();
-                if (!sh_last)
-                    continue;
-                if (threadIdx.x == 0)
-                    __hip_atomic_store(J->zarr + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                // every chunk's add is complete: read the totals at device scope
-                supp = valid ? __hip_atomic_load(J->psupp + p, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT)
-                             : 0u;
-            }
-            prune_and_check(J, st, valid, p, supp, sh_app, sh_red);
-        } else {
-            const uint32_t c0 = ks + (local - nsc) * (WG / 64);
-            const uint32_t wave = threadIdx.x >> 6;
-            if (c0 + wave < K) {
-                const uint32_t p = __builtin_amdgcn_readfirstlane(cur[c0 + wave]);
-                const uint32_t cnt = J->layout == LAYOUT_VERTICAL ? count_wave_bitsets(J, st, p)
-                                                                  : count_wave_rows(J, st, p);
-                if ((threadIdx.x & 63u) == 0) {
-                    const uint32_t supp = J->psupp[p] + cnt;  // the only writer
-                    J->psupp[p] = supp;
-                    sh_supp[wave] = supp;
-                }
-            }
-            __syncthreads();
-            const bool valid = threadIdx.x < WG / 64 && c0 + threadIdx.x < K;
-            const uint32_t p = valid ? cur[c0 + threadIdx.x] : 0u;
-            prune_and_check(J, st, valid, p, valid ? sh_supp[threadIdx.x] : 0u, sh_app, sh_red);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)
-        sh_last = arrive_last(plan->tickets, total < gridDim.x ? (total ? total : 1u) : gridDim.x);
-    __syncthreads();
-    if (sh_last) {
-        for (uint32_t j = threadIdx.x; j < plan->njobs; j += WG) {
-            JobState *st = jobs[j].st;
-            if (st->done || st->overflow)
-                continue;
-            // the survivor and new-box counts and the survivors' remaining
-            // stops were updated by atomics of this launch: read them at
-            // device scope (a cached copy of the state may predate them) and
-            // keep them for the plain reads below
-            const uint32_t kn = __hip_atomic_load(&st->k_next, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t nn = __hip_atomic_load(&st->n_new, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t mr = __hip_atomic_load(&st->max_rem, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-            st->k_next = kn;
-            st->n_new = nn;
-            st->max_rem = mr;
-            if (kn == 0 && nn == 0) {
-                st->done = 1;  // no survivor and no new box: nothing left to count
-                st->need = 0;
-            } else {
-                to_next_block(jobs + j, st);
-            }
-        }
         __syncthreads();
-        write_plan_x(jobs, plan, sh_red, shc);
+        if (threadIdx.x == 0)
+            *sh_flag = atomicAdd(J->zarr + cg, 1u) == st->n_ri - 1u;
+        __syncthreads();
+        if (!*sh_flag)
+            return;
+        if (threadIdx.x == 0)
+            __hip_atomic_store(J->zarr + cg, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // every chunk's add is complete: read the totals at device scope
+#pragma unroll
+        for (int q = 0; q < VT_CPT; ++q)
+            supp[q] = valid[q] ? __hip_atomic_load(J->psupp + pidx[q], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)
+                               : 0u;
     }
+    prune_survivors<VT_CPT>(J, st, pidx, supp, valid, sh_app, sh_red);
 }
 
 // Copy W 64-bit words (the loads of a group of eight are issued together).
@@ -1572,10 +1372,9 @@ __device__ __forceinline__ bool list_equals(const uint32_t pw[KD / 2], const uin
 
 // Continue the linear probe for the k-itemset "C without position ct"
 // (hash h) after slot s.  Only itemsets that existed when the stop began
-// (index < base) are considered: one created by this stop's candidate
-// generation is a fresh circle, never the box being looked for, and its
-// pool entry may still be in flight from another workgroup, so it is
-// skipped without being read.
+// (index < base) are considered: one created at this stop is a fresh
+// circle, never the box being looked for, and its pool entry may still be
+// in flight from another workgroup, so it is skipped without being read.
 __device__ __forceinline__ uint32_t probe_list(const Job *J, unsigned long long h, uint32_t k,
                                                const uint32_t sw[KD / 2], uint32_t pos, uint32_t a,
                                                uint32_t ct, uint32_t s, uint32_t base)
@@ -1596,17 +1395,26 @@ __device__ __forceinline__ uint32_t probe_list(const Job *J, unsigned long long 
     }
 }
 
-// MakeCandidates' admission test for C = S | {a}, |S| = k with 3 <= k <= KD:
-// every maximal subset (S \ {s_t}) | {a} other than S must be a box, and
-// none that drops an item larger than a may have been promoted at this stop
-// (that subset generates C).  sw: S's ascending list; pos: a's
-// place in C.  Subsets are checked in groups of SUBG whose hash-slot,
-// item-list and state loads are issued together.
+// Whether standing word w is a box as of the end of the last stop (epoch
+// E - 1): a dashed or solid box promoted before epoch E.  Prune at epoch E
+// may be changing the word in this very launch; either value read answers
+// the same.
+__device__ __forceinline__ bool box_before(uint32_t w, uint32_t E)
+{
+    const uint32_t s = standing_state(w);
+    return (s == ST_DASHED_BOX || s == ST_SOLID_BOX) && standing_promo(w) < E;
+}
+
+// MakeCandidates' admission test for C = S | {a}, |S| = k with k <= KD:
+// every maximal subset (S \ {s_t}) | {a} other than S must have been a box
+// at the end of the last stop, and none that drops an item larger than a
+// may have been promoted at that stop (that subset generates C).  sw: S's
+// ascending list; pos: a's place in C.  Subsets are checked in groups of
+// SUBG whose hash-slot, item-list and standing loads are issued together.
 constexpr int SUBG = 2;
 __device__ __forceinline__ bool subsets_are_boxes(const Job *J, const uint32_t sw[KD / 2],
                                                   uint32_t k, uint32_t a, uint32_t pos,
-                                                  unsigned long long hC,
-                                                  uint32_t base, uint32_t epoch)
+                                                  unsigned long long hC, uint32_t base, uint32_t E)
 {
     bool ok = true;
 #pragma unroll
@@ -1621,7 +1429,7 @@ __device__ __forceinline__ bool subsets_are_boxes(const Job *J, const uint32_t s
             slot[u] = (uint32_t)h[u] & J->hmask;
             v[u] = (uint32_t)(g + u) < k ? slot_read(J, slot[u]) : SLOT_EMPTY;
         }
-        uint32_t idx[SUBG], pw[SUBG][KD / 2], sst[SUBG], spr[SUBG];
+        uint32_t idx[SUBG], pw[SUBG][KD / 2], sst[SUBG];
 #pragma unroll
         for (int u = 0; u < SUBG; ++u) {
             const bool hit = v[u] != SLOT_EMPTY && (uint32_t)v[u] == slot_tag(h[u], k) &&
@@ -1630,7 +1438,6 @@ __device__ __forceinline__ bool subsets_are_boxes(const Job *J, const uint32_t s
             if (hit) {
                 load_items(J->pitems + (uint64_t)idx[u] * KD, pw[u]);
                 sst[u] = J->pstate[idx[u]];
-                spr[u] = J->ppromo[idx[u]];
             }
         }
 #pragma unroll
@@ -1640,22 +1447,19 @@ __device__ __forceinline__ bool subsets_are_boxes(const Job *J, const uint32_t s
                 continue;
             const uint32_t drop = item_at(sw, t);
             const uint32_t ct = (uint32_t)t < pos ? (uint32_t)t : (uint32_t)t + 1u;
-            uint32_t sub = idx[u], s2 = 0, pr = 0;
+            uint32_t sub = idx[u], s2 = 0;
             if (sub != NONE && list_equals(pw[u], sw, pos, a, ct, k)) {
                 s2 = sst[u];
-                pr = spr[u];
             } else if (v[u] == SLOT_EMPTY) {
                 sub = NONE;
             } else {
                 sub = probe_list(J, h[u], k, sw, pos, a, ct, slot[u], base);
-                if (sub != NONE) {
+                if (sub != NONE)
                     s2 = J->pstate[sub];
-                    pr = J->ppromo[sub];
-                }
             }
-            if (sub == NONE || (s2 != ST_DASHED_BOX && s2 != ST_SOLID_BOX))
+            if (sub == NONE || !box_before(s2, E))
                 ok = false;
-            else if (drop > a && pr == epoch)
+            else if (drop > a && standing_promo(s2) == E - 1u)
                 ok = false;
         }
     }
@@ -1665,7 +1469,7 @@ __device__ __forceinline__ bool subsets_are_boxes(const Job *J, const uint32_t s
 // The same test for |S| = k > KD (no item list): S's items come from its
 // bit mask and subsets are compared by mask.
 __device__ __forceinline__ bool subsets_are_boxes_wide(const Job *J, uint32_t p, uint32_t k, uint32_t a,
-                                       unsigned long long hC, uint32_t base, uint32_t epoch)
+                                       unsigned long long hC, uint32_t base, uint32_t E)
 {
     const uint32_t W = J->W;
     const uint32_t i = J->l1[a];
@@ -1684,48 +1488,83 @@ __device__ __forceinline__ bool subsets_are_boxes_wide(const Job *J, uint32_t p,
             if (sub == NONE)
                 return false;
             const uint32_t s2 = J->pstate[sub];
-            if (s2 != ST_DASHED_BOX && s2 != ST_SOLID_BOX)
+            if (!box_before(s2, E))
                 return false;
-            if (xj > i && J->ppromo[sub] == epoch)
+            if (xj > i && standing_promo(s2) == E - 1u)
                 return false;  // a subset dropping a larger item generates C
         }
     }
     return true;
 }
 
-// MakeCandidates: for each itemset S promoted at this stop and each frequent
-// item i not in S, C = S | {i} is admitted when every maximal proper subset
-// of C is a box.  C is produced by exactly one of its newly promoted subsets
-// C \ {i}: the one with the largest i, so no candidate is generated twice
-// and no set of already-known itemsets is needed (an itemset whose subsets
-// were all boxes before this stop was generated at an earlier stop).
-// Work item = (job, chunk of WG (new box, frequent item) pairs); every
-// workgroup derives the per-job prefix of chunks itself.
-// MakeCandidates for one chunk of WG (new box, frequent item) pairs of job J:
-// for each itemset S promoted at this stop and each frequent item i not in
-// S, C = S | {i} is admitted when every maximal proper subset of C is a box.
-// C is produced by exactly one of its newly promoted subsets C \\ {i}: the one
-// with the largest i, so no candidate is generated twice and no set of
-// already-known itemsets is needed (an itemset whose subsets were all boxes
-// before this stop was generated at an earlier stop).  Every thread of the
-// workgroup calls.
-__device__ __forceinline__ void candgen_chunk(const Job *J, unsigned long long chunk, uint32_t *sh_app)
+// Workgroup-aggregated append that also reports each thread's rank among
+// the workgroup's appends and their total: one atomic on ctr per workgroup.
+// Every thread of the workgroup calls.  sh holds WG/64 + 2 words.
+__device__ __forceinline__ void block_append_rank(uint32_t *ctr, bool pred, uint32_t *sh, uint32_t *base,
+                                  uint32_t *rank, uint32_t *total)
+{
+    const unsigned long long b = __ballot(pred);
+    const uint32_t wave = threadIdx.x >> 6;
+    if (lane_id() == 0)
+        sh[wave] = (uint32_t)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < WG / 64; ++w) {
+            const uint32_t c = sh[w];
+            sh[w] = t;
+            t += c;
+        }
+        sh[WG / 64] = t ? atomicAdd(ctr, t) : 0u;
+        sh[WG / 64 + 1] = t;
+    }
+    __syncthreads();
+    *rank = sh[wave] + (uint32_t)__popcll(b & lanemask_lt());
+    *base = sh[WG / 64];
+    *total = sh[WG / 64 + 1];
+    __syncthreads();
+}
+
+// Counts of a candidate made at this stop, one wave each: its record in
+// LDS (REC words: generating pool entry, added frequent item, size, a pad,
+// then the item list when the size is at most KD).
+constexpr uint32_t REC = 12;
+
+// MakeCandidates for one chunk of WG (new box, frequent item) pairs of job J,
+// then CountSupport, Prune and CheckFullPass of what it made.  For each
+// itemset S promoted at the last stop and each frequent item a not in S,
+// C = S | {a} is admitted when every maximal proper subset of C was a box
+// at the end of that stop.  C is produced by exactly one of its subsets
+// C \ {i} promoted at that stop: the one with the largest i, so no
+// candidate is generated twice and no set of already-known itemsets is
+// needed (an itemset whose subsets were all boxes before was generated
+// earlier).  C is counted on this stop's block at once, by the waves of the
+// workgroup (few candidates: one wave each, records in LDS) or by its
+// threads over LDS tiles of the block (many), and pruned as a dashed circle
+// seen on one block.  Every thread of the workgroup calls.
+__device__ __forceinline__ void candgen_stop(const Job *J, unsigned long long chunk, uint64_t *lds, uint32_t *sh_app,
+                             uint32_t *sh_red, uint32_t *sh_cnt)
 {
     JobState *st = J->st;
     const uint32_t W = J->W;
     const uint32_t nL1 = st->nL1;
     const uint32_t base = st->pool_base;
+    const uint32_t E = st->epoch;
+    const uint32_t *nb_last = st->parity ? J->newbox1 : J->newbox0;
     const unsigned long long x = chunk * WG + threadIdx.x;
-    const bool valid = x < (unsigned long long)st->n_new * nL1;
+    const bool valid = x < (unsigned long long)st->n_prev * nL1;
     bool gen = false;
     uint32_t p = 0, a = 0, k = 0;
     unsigned long long hC = 0;
     uint32_t sw[KD / 2];  // S's frequent-item indices, ascending (k <= KD)
     uint32_t pos = 0;     // a's place in C = S | {a}
+#pragma unroll
+    for (int t = 0; t < KD / 2; ++t)
+        sw[t] = 0u;
     if (valid) {
         const uint32_t q = (uint32_t)(x / nL1);
         a = (uint32_t)(x % nL1);  // the new item, as a frequent-item index
-        p = J->newbox[q];
+        p = nb_last[q];
         k = J->pk[p];
         const unsigned long long hS = J->phash[p];
         if (k <= (uint32_t)KD) {
@@ -1749,98 +1588,162 @@ __device__ __forceinline__ void candgen_chunk(const Job *J, unsigned long long c
                 const uint32_t lo1 = s1 < a ? s1 : a, hi1 = s1 < a ? a : s1;
                 const uint32_t sub0 = lo0 * nL1 - lo0 * (lo0 + 1u) / 2u + (hi0 - lo0 - 1u);
                 const uint32_t sub1 = lo1 * nL1 - lo1 * (lo1 + 1u) / 2u + (hi1 - lo1 - 1u);
-                const uint32_t st0 = J->pstate[sub0], st1 = J->pstate[sub1];
-                const uint32_t pr0 = J->ppromo[sub0], pr1 = J->ppromo[sub1];
-                gen = (st0 == ST_DASHED_BOX || st0 == ST_SOLID_BOX) &&
-                      (st1 == ST_DASHED_BOX || st1 == ST_SOLID_BOX) &&
+                const uint32_t w0 = J->pstate[sub0], w1 = J->pstate[sub1];
+                gen = box_before(w0, E) && box_before(w1, E) &&
                       // a subset dropping a larger item than a, promoted
-                      // at this stop, generates C instead
-                      !(s1 > a && pr0 == st->epoch) && !(s0 > a && pr1 == st->epoch);
+                      // at the last stop, generates C instead
+                      !(s1 > a && standing_promo(w0) == E - 1u) &&
+                      !(s0 > a && standing_promo(w1) == E - 1u);
             } else if (!in) {
-                gen = subsets_are_boxes(J, sw, k, a, pos, hC, base, st->epoch);
+                gen = subsets_are_boxes(J, sw, k, a, pos, hC, base, E);
             }
         } else {
             hC = hS ^ zob(a);
-            gen = subsets_are_boxes_wide(J, p, k, a, hC, base, st->epoch);
+            gen = subsets_are_boxes_wide(J, p, k, a, hC, base, E);
         }
     }
-    // New entries are pool slots [pool_base, pool_n); in the next live
-    // list they follow the survivors, at k_next + (slot - pool_base).
-    // Lookups in this launch never read them (see probe_list), so no
-    // fence is needed before publishing them in the hash table.
-    const uint32_t np = block_append(&st->pool_n, gen, sh_app);
+    // New entries are pool slots [pool_base, pool_n).  Lookups in this
+    // launch never read them (see probe_list), so no fence is needed before
+    // publishing them in the hash table.
+    uint32_t wg_base, rank, g;
+    block_append_rank(&st->pool_n, gen, sh_app, &wg_base, &rank, &g);
+    const uint32_t np = wg_base + rank;
     const bool stored = gen && np < J->cap;
-    if (gen && !stored)
-        st->overflow = 1u;
+    const uint32_t kc = k + 1u;
+    uint32_t cw[KD / 2];  // C's frequent-item indices, ascending (kc <= KD)
+#pragma unroll
+    for (int u = 0; u < KD / 2; ++u)
+        cw[u] = ((uint32_t)(2 * u) <= k ? c_item(sw, pos, a, 2 * u) : 0u) |
+                (((uint32_t)(2 * u + 1) <= k ? c_item(sw, pos, a, 2 * u + 1) : 0u) << 16);
     if (stored) {
         const uint32_t i = J->l1[a];
         copy_words(J->pmask + (uint64_t)np * W, J->pmask + (uint64_t)p * W, W);
         J->pmask[(uint64_t)np * W + (i >> 6)] |= 1ull << (i & 63u);
         J->phash[np] = hC;
         J->pnz[np] = J->pnz[p] | (1ull << (i >> 6));
-        J->pk[np] = k + 1u;
-        J->psupp[np] = 0;
-        J->pstop[np] = 0;
-        J->pstate[np] = ST_DASHED_CIRCLE;
-        J->ppromo[np] = NO_EPOCH;
-        if (k + 1u <= (uint32_t)KD) {
-            uint32_t w[KD / 2];
+        J->pk[np] = kc;
+        if (kc <= (uint32_t)KD) {
+            uint4 *ci = (uint4 *)(J->pitems + (uint64_t)np * KD);
+            ci[0] = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+            ci[1] = make_uint4(cw[4], cw[5], cw[6], cw[7]);
+        }
+        hash_insert(J, hC, kc, np);
+    }
+    // candidates of this workgroup stored in the pool (ranks 0 .. gs-1)
+    const uint32_t gs = wg_base >= J->cap ? 0u : (g < J->cap - wg_base ? g : J->cap - wg_base);
+    if (gs == 0u)
+        return;
+    // CountSupport of the new candidates on this stop's block
+    uint32_t cnt = 0;
+    const uint32_t nwords = st->lw - st->fw + 1u;
+    const bool vert = J->layout == LAYOUT_VERTICAL;
+    const uint32_t tw = vert_tile_words(nL1, VT_MAXW);
+    const uint32_t ntile = (nwords + tw - 1u) / tw;
+    const uint32_t wave_passes = (gs + WG / 64 - 1u) / (WG / 64) * ((nwords + 191u) / 192u);
+    if (vert && 2u * ntile < wave_passes) {
+        // many: each thread ANDs its own candidate's rows over LDS tiles
+        CandItems ci{};
+        ci.k = kc;
+        ci.wide = p;
+        ci.extra = kc > (uint32_t)KD ? a : NONE;
+#pragma unroll
+        for (int u = 0; u < KD / 2; ++u)
+            ci.pk32[u] = cw[u];
+        const uint32_t ts = vert_tile_stride(tw);
+        for (uint32_t t = 0; t < ntile; ++t) {
+            const uint32_t w0 = st->fw + t * tw;
+            const uint32_t nwt = (st->lw + 1u - w0) < tw ? (st->lw + 1u - w0) : tw;
+            stage_tile(J, st, w0, nwt, ts, lds);
+            if (stored)
+                cnt += and_tile_items(J, ci, lds, ts, nwt);
+        }
+    } else {
+        // few: one wave per candidate, the candidates' records in LDS
+        uint32_t *rec = (uint32_t *)lds;
+        if (stored) {
+            uint32_t *r = rec + rank * REC;
+            r[0] = p;
+            r[1] = a;
+            r[2] = kc;
+            r[3] = 0u;
 #pragma unroll
             for (int u = 0; u < KD / 2; ++u)
-                w[u] = ((uint32_t)(2 * u) <= k ? c_item(sw, pos, a, 2 * u) : 0u) |
-                       (((uint32_t)(2 * u + 1) <= k ? c_item(sw, pos, a, 2 * u + 1) : 0u) << 16);
-            uint4 *ci = (uint4 *)(J->pitems + (uint64_t)np * KD);
-            ci[0] = make_uint4(w[0], w[1], w[2], w[3]);
-            ci[1] = make_uint4(w[4], w[5], w[6], w[7]);
+                r[4 + u] = cw[u];
         }
-        hash_insert(J, hC, k + 1u, np);
-        uint32_t *next = st->parity ? J->live0 : J->live1;
-        next[st->k_next + (np - st->pool_base)] = np;
+        __syncthreads();
+        for (uint32_t r0 = threadIdx.x >> 6; r0 < gs; r0 += WG / 64) {
+            const uint32_t *r = rec + r0 * REC;
+            uint32_t c;
+            if (vert) {
+                CandItems ci;
+                ci.wide = r[0];
+                ci.k = r[2];
+                ci.extra = ci.k > (uint32_t)KD ? r[1] : NONE;
+#pragma unroll
+                for (int u = 0; u < KD / 2; ++u)
+                    ci.pk32[u] = r[4 + u];
+                c = count_wave_bitsets(J, st, ci);
+            } else {
+                c = count_wave_rows(J, st, r[0], J->l1[r[1]]);
+            }
+            if ((threadIdx.x & 63u) == 0)
+                sh_cnt[r0] = c;
+        }
+        __syncthreads();
+        cnt = stored ? sh_cnt[rank] : 0u;
     }
+    // Prune and CheckFullPass: a dashed circle counted on one block
+    uint32_t pp[1] = {np}, supp[1] = {cnt}, sc[1] = {1u};
+    uint32_t stw[1] = {standing(ST_DASHED_CIRCLE, PROMO_NONE)}, items[1] = {kc};
+    uint32_t words[1] = {stored && !vert ? mask_dwords(J, p, J->l1[a]) : 0u};
+    bool ok[1] = {stored};
+    if (stored)
+        J->psupp[np] = cnt;
+    prune_core<1>(J, st, pp, supp, sc, stw, items, words, ok, sh_app, sh_red);
 }
 
-// X: MakeCandidates chunks of every job, then the bitset CountSupport work
-// items of every job's survivors (row-bitmap jobs are counted by k_count,
-// launched just before).  The last workgroup to finish completes the stop
-// for every job and plans Z.
-// Three waves per SIMD (what its LDS tile allows) hold the item lists loaded
-// ahead in registers without spilling; left to itself the compiler took more
-// registers and ran two.
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_stepx(
+// One stop for every job in the table: MakeCandidates chunks (with the new
+// candidates' count and prune) of every job first, then the survivors' work
+// items of every job.  The last workgroup to finish completes the stop for
+// every job, begins its next one and plans the next launch.  Three waves per
+// SIMD (what the LDS tile allows) hold the item lists loaded ahead in
+// registers without spilling.
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_stop(
     const Job *__restrict__ jobs, Plan *plan)
 {
     __shared__ uint64_t tile[VT_WORDS];
-    __shared__ uint32_t sh_app[WG / 64 + 1];
-    __shared__ uint32_t sh_last;
+    __shared__ uint32_t sh_app[2 * VT_CPT * (WG / 64) + 2];
+    __shared__ uint32_t sh_red[6 * (WG / 64)];
+    __shared__ uint32_t sh_cnt[WG];
+    __shared__ unsigned long long shc[WG / 64];
+    __shared__ uint32_t sh_flag;
     const uint32_t njobs = plan->njobs;
     const unsigned long long ncg = plan->pre_cg[njobs];
     const unsigned long long total = ncg + plan->pre_countv[njobs];
     for (unsigned long long it = blockIdx.x; it < total; it += gridDim.x) {
         if (it < ncg) {
             const uint32_t j = find_job(plan->pre_cg, njobs, it);
-            candgen_chunk(jobs + j, it - plan->pre_cg[j], sh_app);
+            candgen_stop(jobs + j, it - plan->pre_cg[j], tile, sh_app, sh_red, sh_cnt);
         } else {
             const uint32_t v = (uint32_t)(it - ncg);
             const uint32_t j = find_job(plan->pre_countv, njobs, v);
-            count_vert_item(jobs + j, jobs[j].st, v - plan->pre_countv[j], tile);
+            survivors_stop(jobs + j, v - plan->pre_countv[j], tile, sh_app, sh_red, sh_cnt,
+                           &sh_flag);
         }
     }
     __syncthreads();
     if (threadIdx.x == 0)
-        sh_last = arrive_last(plan->tickets, total < gridDim.x ? (total ? (uint32_t)total : 1u)
-                                                             : gridDim.x);
+        sh_flag = arrive_last(plan->tickets, total < gridDim.x ? (total ? (uint32_t)total : 1u)
+                                                              : gridDim.x);
     __syncthreads();
-    if (sh_last) {
+    if (sh_flag) {
         for (uint32_t j = threadIdx.x; j < njobs; j += WG) {
             JobState *st = jobs[j].st;
-            if (!st->done && !st->overflow)
-                finish_stop(jobs + j, st,
-                            __hip_atomic_load(&st->pool_n, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT),
-                            plan->vt_tile_words);
+            if (!st->done && !st->overflow && !st->pending)
+                end_stop(jobs + j, st);
         }
         __syncthreads();
-        write_plan_z(jobs, plan, (uint32_t *)tile);
+        write_plan(jobs, plan, (uint32_t *)tile, shc);
     }
 }
 
@@ -1853,7 +1756,7 @@ __global__ __launch_bounds__(WG) void k_collect(const Job *__restrict__ jobs)
     const uint32_t W = J->W;
     for (uint32_t b = blockIdx.x * WG; b < pool_n; b += gridDim.x * WG) {
         const uint32_t p = b + threadIdx.x;
-        const bool box = p < pool_n && J->pstate[p] == ST_SOLID_BOX;
+        const bool box = p < pool_n && standing_state(J->pstate[p]) == ST_SOLID_BOX;
         const uint32_t pos = wave_append(J->out_n, box, true);
         if (box) {
             const uint64_t *pm = J->pmask + (uint64_t)p * W;
@@ -1909,7 +1812,6 @@ __global__ __launch_bounds__(WG) void k_check_padding(const uint64_t *__restrict
 // launchers
 // ---------------------------------------------------------------------------
 namespace {
-constexpr uint32_t GRID_EPI = 512;
 
 uint32_t grid_for(unsigned long long work, uint32_t per, uint32_t cap)
 {
@@ -1967,15 +1869,14 @@ void launch_step(const Job *jobs, const Plan *plan, hipStream_t s, bool rows, bo
                  uint32_t count_grid, hipEvent_t before, hipEvent_t after)
 {
     Plan *pl = const_cast<Plan *>(plan);
-    (void)vert;  // bitset counting is part of X; X runs for every table
+    (void)vert;  // the bitset count is part of the stop kernel
     if (before)
         (void)hipEventRecord(before, s);
     if (rows)
         hipLaunchKernelGGL(k_count, dim3(count_grid), dim3(WG), 0, s, jobs, plan);
-    hipLaunchKernelGGL(k_stepx, dim3(count_grid), dim3(WG), 0, s, jobs, pl);
+    hipLaunchKernelGGL(k_stop, dim3(count_grid), dim3(WG), 0, s, jobs, pl);
     if (after)
         (void)hipEventRecord(after, s);
-    hipLaunchKernelGGL(k_stepz, dim3(GRID_EPI), dim3(WG), 0, s, jobs, pl);
 }
 
 void launch_collect(const Job *jobs, const Plan *, uint32_t njobs, hipStream_t s)

@@ -151,7 +151,7 @@ int mine_once(char *base, hipStream_t s, const MineRequest &req, uint32_t layout
     const size_t o_job = c.take(sizeof(Job));
     const size_t o_aux = c.take(sizeof(Plan)), o_step = c.take(sizeof(Plan));
     const size_t o_a_fp = c.take(16), o_a_cg = c.take(16);
-    const size_t o_s_count = c.take(8), o_s_countv = c.take(8), o_s_epi = c.take(8);
+    const size_t o_s_count = c.take(8), o_s_countv = c.take(8);
     const size_t o_s_cg = c.take(16), o_s_fp = c.take(16);
     const size_t o_tk = c.take(4ull * TICKET_WORDS);
     const size_t m4 = align_up(4ull * m, 256);
@@ -246,7 +246,6 @@ int mine_once(char *base, hipStream_t s, const MineRequest &req, uint32_t layout
     R.step.njobs = 1;
     R.step.pre_count = (uint32_t *)(base + o_s_count);
     R.step.pre_countv = (uint32_t *)(base + o_s_countv);
-    R.step.pre_epi = (uint32_t *)(base + o_s_epi);
     R.step.pre_cg = (unsigned long long *)(base + o_s_cg);
     R.step.pre_fp = (unsigned long long *)(base + o_s_fp);
     R.step.vt_target = k.vt_target;
@@ -310,7 +309,7 @@ int mine_once(char *base, hipStream_t s, const MineRequest &req, uint32_t layout
         stats->tau = tau;
         stats->block = Mp;
         stats->stop_max = stop_max;
-        stats->stops = R.st.epoch;
+        stats->stops = R.st.stops;
         stats->tests = R.st.tests;
         stats->peak_live = R.st.peak_K;
         stats->n_frequent = nf1 + q;
