@@ -175,6 +175,13 @@ inline uint32_t job_need(const JobState &s, uint32_t, uint32_t stop_max)
 
 constexpr int KD = 16;  // frequent-item indices stored per candidate (larger: decode the mask)
 
+// A live candidate travels between stops as a record in the live lists, so
+// that a stop reads everything it needs of a candidate with one load: its
+// pool entry, its support and the stops it has been counted on so far, its
+// size and whether it is a box already, and (size <= KD) its frequent-item
+// indices.  LREC uint4 words: {p, supp, sc, k | box << 16}, then the items.
+constexpr uint32_t LREC = 3;
+
 // Random word of item a for the Zobrist hash of an itemset, the XOR of its
 // items' words (mining keys items by frequent-item index): output a + 1
 // of the SplitMix64 generator (Steele, Lea & Flood, in Vigna's 64-bit form)
@@ -212,10 +219,11 @@ struct Job {
     uint16_t *pitems; // cap * KD: frequent-item indices of each itemset (size <= KD)
     unsigned long long *phash;  // Zobrist hash of each itemset
     uint64_t *pnz;    // bitmap of nonzero words
-    uint32_t *psupp, *pstop, *pk;
+    uint32_t *psupp, *pk;
     uint32_t *pstate;           // standing word (state, promotion stop) of each itemset
     unsigned long long *slots;  // open addressing: idx<<32 | fp24<<8 | k8
-    uint32_t *live0, *live1;    // cap each
+    uint4 *live0, *live1;       // cap records each (LREC uint4 words per record)
+    uint32_t *pcnt;             // cap: partial counts of a split group (zero between stops)
     uint32_t *newbox0, *newbox1;  // cap each: boxes promoted at a stop (by parity)
     uint32_t *zarr;             // cap / WG + 1 arrival counters of Z's tile chunks (zero between uses)
     uint32_t *l1;               // m
@@ -262,7 +270,7 @@ inline uint64_t pool_cap_for(uint32_t nL1, uint32_t mult)
 
 // Layout of a job's candidate pool buffer (byte offsets of its arrays).
 struct PoolLayout {
-    size_t mask, items, hash, nz, supp, stop, state, k, slots, live0, live1, newbox0, newbox1,
+    size_t mask, items, hash, nz, supp, state, k, slots, live0, live1, pcnt, newbox0, newbox1,
         zarr, omask, ocnt, okey;
     size_t bytes;
     uint64_t hslots, zarr_n;
@@ -275,12 +283,12 @@ struct PoolLayout {
         hash = c.take(cap * 8);
         nz = c.take(cap * 8);
         supp = c.take(cap * 4);
-        stop = c.take(cap * 4);
         state = c.take(cap * 4);
         k = c.take(cap * 4);
         slots = c.take(hslots * 8);
-        live0 = c.take(cap * 4);
-        live1 = c.take(cap * 4);
+        live0 = c.take(cap * LREC * 16);
+        live1 = c.take(cap * LREC * 16);
+        pcnt = c.take(cap * 4);
         newbox0 = c.take(cap * 4);
         newbox1 = c.take(cap * 4);
         zarr_n = cap / WG + 1;
@@ -295,7 +303,8 @@ struct PoolLayout {
 // Work plan of one step across all jobs (prefix sums, njobs + 1 entries).
 struct Plan {
     uint32_t njobs;
-    uint32_t pad;
+    uint32_t total_v;               // pre_countv[njobs]: survivors' work items of the stop kernel
+    unsigned long long total_cg;    // pre_cg[njobs]: MakeCandidates chunks
     uint32_t *pre_count;   // row-bitmap count work items (k_count)
     uint32_t *pre_countv;  // survivors' work items of the stop kernel
     unsigned long long *pre_cg;
@@ -319,12 +328,12 @@ inline void pool_assign(Job &J, const PoolLayout &L, char *b, uint32_t cap)
     J.phash = (unsigned long long *)(b + L.hash);
     J.pnz = (uint64_t *)(b + L.nz);
     J.psupp = (uint32_t *)(b + L.supp);
-    J.pstop = (uint32_t *)(b + L.stop);
     J.pstate = (uint32_t *)(b + L.state);
     J.pk = (uint32_t *)(b + L.k);
     J.slots = (unsigned long long *)(b + L.slots);
-    J.live0 = (uint32_t *)(b + L.live0);
-    J.live1 = (uint32_t *)(b + L.live1);
+    J.live0 = (uint4 *)(b + L.live0);
+    J.live1 = (uint4 *)(b + L.live1);
+    J.pcnt = (uint32_t *)(b + L.pcnt);
     J.newbox0 = (uint32_t *)(b + L.newbox0);
     J.newbox1 = (uint32_t *)(b + L.newbox1);
     J.zarr = (uint32_t *)(b + L.zarr);

@@ -152,7 +152,7 @@ __device__ __forceinline__ uint32_t hash_find_sub(const Job *J, unsigned long lo
 // Inclusive block scan of one value per thread (WG threads); *total gets
 // the sum over the block.  sh must hold WG elements.
 template <typename T>
-__device__ T block_scan_incl(T v, T *sh, T *total)
+__device__ __forceinline__ T block_scan_incl(T v, T *sh, T *total)
 {
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     for (uint32_t off = 1; off < 64u; off <<= 1) {
@@ -178,7 +178,7 @@ __device__ T block_scan_incl(T v, T *sh, T *total)
 // pass: shuffles within each wave, then the wave totals through LDS.  tot
 // receives the workgroup totals.  sh holds NV * (WG/64) words.
 template <int NV>
-__device__ void block_scan_n(uint32_t (&v)[NV], uint32_t *sh, uint32_t (&tot)[NV])
+__device__ __forceinline__ void block_scan_n(uint32_t (&v)[NV], uint32_t *sh, uint32_t (&tot)[NV])
 {
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     for (uint32_t off = 1; off < 64u; off <<= 1)
@@ -208,7 +208,7 @@ __device__ void block_scan_n(uint32_t (&v)[NV], uint32_t *sh, uint32_t (&tot)[NV
 }
 
 // Sum of one value per thread over the workgroup (result in every thread).
-__device__ uint32_t block_sum(uint32_t v, uint32_t *sh)
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh)
 {
     for (int off = 32; off > 0; off >>= 1)
         v += (uint32_t)__shfl_xor((int)v, off);
@@ -227,7 +227,7 @@ __device__ uint32_t block_sum(uint32_t v, uint32_t *sh)
 // whose a / b is true), in round order, with one 64-bit atomic for the
 // workgroup.  sh holds 2 * NQ * (WG/64) + 2 words.
 template <int NQ>
-__device__ void block_append2_rounds(uint32_t *ctr, const bool (&a)[NQ], const bool (&b)[NQ],
+__device__ __forceinline__ void block_append2_rounds(uint32_t *ctr, const bool (&a)[NQ], const bool (&b)[NQ],
                                      uint32_t *sh, uint32_t (&pa)[NQ], uint32_t (&pb)[NQ])
 {
     constexpr int NW = WG / 64;
@@ -272,7 +272,7 @@ __device__ void block_append2_rounds(uint32_t *ctr, const bool (&a)[NQ], const b
 // Workgroup sums of NS values and maximum of one more; results valid in
 // thread 0.  sh holds (NS + 1) * WG/64 words.
 template <int NS>
-__device__ void block_reduce(uint32_t (&v)[NS + 1], uint32_t *sh)
+__device__ __forceinline__ void block_reduce(uint32_t (&v)[NS + 1], uint32_t *sh)
 {
     const uint32_t wave = threadIdx.x >> 6;
 #pragma unroll
@@ -463,9 +463,11 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
             J->pk[a] = 1;
             J->pitems[(uint64_t)a * KD] = (uint16_t)a;
             J->psupp[a] = 0;
-            J->pstop[a] = 0;
             J->pstate[a] = standing(ST_DASHED_CIRCLE, PROMO_NONE);
-            J->live1[a] = a;
+            uint4 *r = J->live1 + (uint64_t)a * LREC;  // the first stop's current list
+            r[0] = make_uint4(a, 0u, 0u, 1u);
+            r[1] = make_uint4(a, 0u, 0u, 0u);
+            r[2] = make_uint4(0u, 0u, 0u, 0u);
             hash_insert(J, zob(a), 1, a);
             continue;
         }
@@ -487,9 +489,11 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
         J->pitems[(uint64_t)p * KD] = (uint16_t)a;
         J->pitems[(uint64_t)p * KD + 1] = (uint16_t)b;
         J->psupp[p] = 0;
-        J->pstop[p] = 0;
         J->pstate[p] = standing(ST_DASHED_CIRCLE, PROMO_NONE);
-        J->live1[p] = p;  // the first stop's current list is live1
+        uint4 *r = J->live1 + (uint64_t)p * LREC;  // the first stop's current list
+        r[0] = make_uint4(p, 0u, 0u, 2u);
+        r[1] = make_uint4(a | (b << 16), 0u, 0u, 0u);
+        r[2] = make_uint4(0u, 0u, 0u, 0u);
         // no hash entry: outside the classic start a pair is only ever looked
         // up by its index (MakeCandidates' 2-subsets); larger itemsets and
         // the classic start's pairs go through the hash table
@@ -523,7 +527,7 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
 
 // Begin the job's next stop: the next block (stop <- stop + 1, back to the
 // first block after the last), the next epoch and its zeroed trace entry.
-__device__ void begin_stop(const Job *J, JobState *st)
+__device__ __forceinline__ void begin_stop(const Job *J, JobState *st)
 {
     const uint32_t stop = st->stop % J->stop_max + 1u;
     st->stop = stop;
@@ -540,104 +544,47 @@ __device__ void begin_stop(const Job *J, JobState *st)
     }
 }
 
-// Complete stop e for one job once every work item of the launch is done
-// (last workgroup): the candidates made at this launch for stop e-1's new
-// boxes (the pool's growth), the trace, then the end of the run or the
-// beginning of stop e+1.  Counters that other workgroups of the launch
-// updated with atomics are read with device-scope atomic loads.
-__device__ void end_stop(const Job *J, JobState *st)
-{
-    const uint32_t pn = __hip_atomic_load(&st->pool_n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (pn > J->cap) {  // MakeCandidates ran out of pool room
-        st->overflow = 1;
-        return;
-    }
-    const uint32_t E = st->epoch;
-    const uint32_t gen = pn - st->pool_base;
-    if (E >= 2u && E - 2u < J->trace_cap)
-        J->trace[E - 2u].generated = gen;
-    const uint32_t live = st->k_cur + gen;
-    if (live == 0u) {  // nothing was live at this stop: the run ended with the last one
-        st->done = 1;
-        st->need = 0;
-        st->stops = E - 1u;
-        return;
-    }
-    const uint32_t rows = st->last - st->first;
-    st->stops = E;
-    st->tests += (unsigned long long)live * rows;
-    if (live > st->peak_K)
-        st->peak_K = live;
-    if (E - 1u < J->trace_cap) {
-        dic_stop_trace *t = J->trace + (E - 1u);
-        t->stop = st->stop;
-        t->rows = rows;
-        t->live = live;
-    }
-    const uint32_t kn = __hip_atomic_load(&st->k_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t nn = __hip_atomic_load(&st->n_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t mr = __hip_atomic_load(&st->max_rem, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (kn == 0u && nn == 0u) {  // no survivor and no new box: DASHED stays empty
-        st->done = 1;
-        st->need = 0;
-        return;
-    }
-    st->k_cur = kn;
-    st->n_prev = nn;
-    st->k_next = 0;
-    st->n_new = 0;
-    st->max_rem = 0;
-    st->pool_base = pn;
-    st->parity ^= 1u;
-    // stops certainly still needed: the kept candidates' remaining stops, and
-    // one for the new boxes' candidate generation
-    st->need = mr > (nn ? 1u : 0u) ? mr : (nn ? 1u : 0u);
-    begin_stop(J, st);
-}
-
-// Work of one job in the next launch: chunks of MakeCandidates (WG (new box,
-// frequent item) pairs each), the survivors' work items by layout, and the
-// row-bitmap count's work items (k_count).
-__device__ void plan_stop(const Job *J, JobState *st, const Plan *plan, uint32_t *items_rows,
+// Work of one job in the next launch, from its state s: chunks of
+// MakeCandidates (WG (new box, frequent item) pairs each), the survivors'
+// work items by layout, and the row-bitmap count's work items (k_count).
+// The count plan is stored in s.
+__device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const Plan *plan, uint32_t *items_rows,
                           uint32_t *items_stop, unsigned long long *chunks)
 {
     *items_rows = *items_stop = 0;
     *chunks = 0;
-    if (st->done || st->overflow || st->pending)
+    if (s.done || s.overflow || s.pending)
         return;
-    *chunks = ((unsigned long long)st->n_prev * st->nL1 + WG - 1u) / WG;
-    const uint32_t K = st->k_cur;
+    *chunks = ((unsigned long long)s.n_prev * s.nL1 + WG - 1u) / WG;
+    const uint32_t K = s.k_cur;
     if (K == 0)
         return;
-    const uint32_t first = st->first, last = st->last;
-    const uint32_t rows = last - first;
+    const uint32_t rows = s.last - s.first;
     if (J->layout == LAYOUT_VERTICAL && K < plan->vt_wave_k) {
         // few candidates: one wave per candidate, no tile
-        st->cmode = 1;
+        s.cmode = 1;
         *items_stop = (K + WG / 64 - 1u) / (WG / 64);
     } else if (J->layout == LAYOUT_VERTICAL) {
         // (candidate groups of WG * cpt) x (chunks of tiles of tw words)
-        st->cmode = 0;
-        const uint32_t fw = first >> 6;
-        const uint32_t lw = (last - 1u) >> 6;
-        const uint32_t tw = vert_tile_words(st->nL1, plan->vt_tile_words);
-        const uint32_t ntile = (lw - fw + tw) / tw;
+        s.cmode = 0;
+        const uint32_t tw = vert_tile_words(s.nL1, plan->vt_tile_words);
+        const uint32_t ntile = (s.lw - s.fw + tw) / tw;
         // candidates per thread: spend the parallelism beyond vt_target
         // workgroups on fewer tile loads
         const uint64_t vt_target = plan->vt_target;
         uint64_t cpt = ((uint64_t)K * ntile + (uint64_t)WG * vt_target - 1u) /
                        ((uint64_t)WG * vt_target);
         cpt = cpt < 1u ? 1u : (cpt > (uint64_t)VT_CPT ? (uint64_t)VT_CPT : cpt);
-        st->cpt = (uint32_t)cpt;
+        s.cpt = (uint32_t)cpt;
         const uint32_t n_cg = (K + WG * (uint32_t)cpt - 1u) / (WG * (uint32_t)cpt);
         uint32_t want = ((uint32_t)vt_target + n_cg - 1u) / n_cg;
         want = want < 1u ? 1u : (want > ntile ? ntile : want);
         const uint32_t tpc = (ntile + want - 1u) / want;
-        st->tw = tw;
-        st->n_ct = n_cg;
-        st->rpi = tpc;
-        st->n_ri = (ntile + tpc - 1u) / tpc;
-        *items_stop = n_cg * st->n_ri;
+        s.tw = tw;
+        s.n_ct = n_cg;
+        s.rpi = tpc;
+        s.n_ri = (ntile + tpc - 1u) / tpc;
+        *items_stop = n_cg * s.n_ri;
     } else {
         // k_count counts (row range x candidate group); the stop kernel then
         // prunes ZP * WG survivors per work item
@@ -647,44 +594,140 @@ __device__ void plan_stop(const Job *J, JobState *st, const Plan *plan, uint32_t
         uint32_t want = (plan->count_target + n_ct - 1u) / n_ct;
         want = want < 1u ? 1u : (want > tiles ? tiles : want);
         const uint32_t rpi = ((tiles + want - 1u) / want) * rt;
-        st->n_ct = n_ct;
-        st->rpi = rpi;
-        st->n_ri = (rows + rpi - 1u) / rpi;
-        *items_rows = n_ct * st->n_ri;
+        s.n_ct = n_ct;
+        s.rpi = rpi;
+        s.n_ri = (rows + rpi - 1u) / rpi;
+        *items_rows = n_ct * s.n_ri;
         *items_stop = (K + ZP * WG - 1u) / (ZP * WG);
     }
+}
+
+// One job's turn in the serial part of a launch: complete stop e (finish:
+// after every work item of the stop kernel) or begin the first stop of a
+// job added since the last chunk (begin: in k_begin), then plan the next
+// launch.  The state is read once into registers, updated there and
+// written back whole.  Completing stop e takes the candidates made at this
+// launch for stop e-1's new boxes (the pool's growth), writes the trace,
+// and either ends the run or begins stop e+1.  Counters that other
+// workgroups of the launch updated with atomics are read with device-scope
+// atomic loads.
+__device__ __forceinline__ void settle_job(const Job *J, bool finish, bool begin, const Plan *plan,
+                           uint32_t *items_rows, uint32_t *items_stop, unsigned long long *chunks)
+{
+    JobState *stp = J->st;
+    JobState s;
+    __builtin_memcpy(&s, stp, sizeof(JobState));
+    bool write = false;
+    if (finish && !s.done && !s.overflow && !s.pending) {
+        write = true;
+        const uint32_t pn = __hip_atomic_load(&stp->pool_n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long kn_nn = __hip_atomic_load((unsigned long long *)&stp->k_next,
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t mr = __hip_atomic_load(&stp->max_rem, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s.asserts = __hip_atomic_load(&stp->asserts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t kn = (uint32_t)kn_nn, nn = (uint32_t)(kn_nn >> 32);
+        const uint32_t E = s.epoch;
+        s.pool_n = pn;
+        if (pn > J->cap) {  // MakeCandidates ran out of pool room
+            s.overflow = 1;
+        } else {
+            const uint32_t gen = pn - s.pool_base;
+            if (E >= 2u && E - 2u < J->trace_cap)
+                J->trace[E - 2u].generated = gen;
+            const uint32_t live = s.k_cur + gen;
+            if (live == 0u) {  // nothing was live at this stop: the run ended with the last one
+                s.done = 1;
+                s.need = 0;
+                s.stops = E - 1u;
+            } else {
+                const uint32_t rows = s.last - s.first;
+                s.stops = E;
+                s.tests += (unsigned long long)live * rows;
+                if (live > s.peak_K)
+                    s.peak_K = live;
+                if (E - 1u < J->trace_cap) {
+                    dic_stop_trace *t = J->trace + (E - 1u);
+                    t->stop = s.stop;
+                    t->rows = rows;
+                    t->live = live;
+                }
+                if (kn == 0u && nn == 0u) {  // no survivor and no new box: DASHED stays empty
+                    s.done = 1;
+                    s.need = 0;
+                } else {
+                    s.k_cur = kn;
+                    s.n_prev = nn;
+                    s.pool_base = pn;
+                    s.parity ^= 1u;
+                    // stops certainly still needed: the kept candidates'
+                    // remaining stops, and one for the new boxes' extensions
+                    s.need = mr > (nn ? 1u : 0u) ? mr : (nn ? 1u : 0u);
+                    begin_stop(J, &s);
+                }
+            }
+        }
+        s.k_next = 0;
+        s.n_new = 0;
+        s.max_rem = 0;
+    } else if (begin && s.pending && !s.done && !s.overflow) {
+        // first stop: the first candidates (pool entries 0..pn-1, already in
+        // live1) are the current list, counted like survivors
+        write = true;
+        const uint32_t pn = s.pool_n < J->cap ? s.pool_n : J->cap;
+        s.k_cur = pn;
+        s.n_prev = 0;
+        s.k_next = 0;
+        s.n_new = 0;
+        s.max_rem = 0;
+        s.pool_base = pn;
+        s.parity = 1;
+        s.stop = 0;
+        s.epoch = 0;
+        s.need = J->stop_max;  // a first candidate needs a full pass
+        s.pending = 0;
+        begin_stop(J, &s);
+    }
+    plan_stop(J, s, plan, items_rows, items_stop, chunks);
+    if (write || (!s.done && !s.overflow && !s.pending))
+        __builtin_memcpy(stp, &s, sizeof(JobState));
 }
 
 // Arrival counter of a launch, called by one thread per workgroup after the
 // workgroup's work: true for the workgroup that arrives last.  Only the
 // first n workgroups arrive (n = min(grid, work items), at least 1: the
-// others had no work item); the rest return false at once.  Two levels
-// (workgroups of a group of TICKET_GROUPS, then the groups) keep the atomics
-// on any one counter few; the last arrival clears every counter for the
-// next launch.
-__device__ bool arrive_last(uint32_t *tickets, uint32_t n)
+// others had no work item); the rest return false at once.  Up to
+// TICKET_GROUPS arrivals share one counter; more go through two levels
+// (workgroups of a group, then the groups) so that no counter sees many
+// atomics.  The last arrival clears the counters it used.
+__device__ __forceinline__ bool arrive_last(uint32_t *tickets, uint32_t n)
 {
     if (blockIdx.x >= n)
         return false;
     const uint32_t G = TICKET_GROUPS;
+    if (n <= G) {
+        if (atomicAdd(&tickets[0], 1u) != n - 1u)
+            return false;
+        __hip_atomic_store(&tickets[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
     const uint32_t g = blockIdx.x % G;
-    const uint32_t groups = n < G ? n : G;
     const uint32_t members = n / G + (g < n % G ? 1u : 0u);
     if (atomicAdd(&tickets[(g + 1u) * TICKET_STRIDE], 1u) != members - 1u)
         return false;
-    if (atomicAdd(&tickets[0], 1u) != groups - 1u)
+    if (atomicAdd(&tickets[0], 1u) != G - 1u)
         return false;
-    for (uint32_t x = 0; x <= groups; ++x)
+    for (uint32_t x = 0; x <= G; ++x)
         __hip_atomic_store(&tickets[x * TICKET_STRIDE], 0u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     return true;
 }
 
-// Per-job prefix sums of the next launch's work (row-bitmap count items,
-// stop-kernel survivor items, MakeCandidates chunks).  One workgroup, every
-// thread calls; sh holds 2 * (WG/64) words.
-__device__ void write_plan(const Job *__restrict__ jobs, Plan *plan, uint32_t *sh,
-                           unsigned long long *shc)
+// The serial part of a launch for every job (one workgroup, every thread
+// calls): settle_job per job, then per-job prefix sums of the next launch's
+// work (row-bitmap count items, stop-kernel survivor items, MakeCandidates
+// chunks) and their totals.  sh holds 2 * (WG/64) words.
+__device__ __forceinline__ void settle_and_plan(const Job *__restrict__ jobs, Plan *plan, bool finish, bool begin,
+                                uint32_t *sh, unsigned long long *shc)
 {
     const uint32_t njobs = plan->njobs;
     uint32_t carry_c = 0, carry_v = 0;
@@ -699,7 +742,7 @@ __device__ void write_plan(const Job *__restrict__ jobs, Plan *plan, uint32_t *s
         uint32_t items = 0, itemsv = 0;
         unsigned long long chunks = 0;
         if (j < njobs)
-            plan_stop(jobs + j, jobs[j].st, plan, &items, &itemsv, &chunks);
+            settle_job(jobs + j, finish, begin, plan, &items, &itemsv, &chunks);
         uint32_t v[2] = {items, itemsv}, t[2];
         block_scan_n<2>(v, sh, t);
         unsigned long long tg;
@@ -712,6 +755,10 @@ __device__ void write_plan(const Job *__restrict__ jobs, Plan *plan, uint32_t *s
         carry_c += t[0];
         carry_v += t[1];
         carry_g += tg;
+    }
+    if (threadIdx.x == 0) {
+        plan->total_v = carry_v;
+        plan->total_cg = carry_g;
     }
 }
 
@@ -736,33 +783,13 @@ __global__ __launch_bounds__(WG) void k_gather_vert(const Job *__restrict__ jobs
 }
 
 // Start of a chunk of stops (one workgroup).  A job added since the last
-// chunk begins its first stop: its first candidates (pool entries 0..pn-1,
-// already in live1) are the current list, counted like survivors.  Every job
-// is then planned against the current job table.
+// chunk begins its first stop; every job is then planned against the
+// current job table.
 __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan *plan)
 {
     __shared__ uint32_t sh[2 * (WG / 64)];
     __shared__ unsigned long long shc[WG / 64];
-    for (uint32_t j = threadIdx.x; j < plan->njobs; j += WG) {
-        JobState *st = jobs[j].st;
-        if (st->pending && !st->done && !st->overflow) {
-            const uint32_t pn = st->pool_n < jobs[j].cap ? st->pool_n : jobs[j].cap;
-            st->k_cur = pn;
-            st->n_prev = 0;
-            st->k_next = 0;
-            st->n_new = 0;
-            st->max_rem = 0;
-            st->pool_base = pn;
-            st->parity = 1;
-            st->stop = 0;
-            st->epoch = 0;
-            st->need = jobs[j].stop_max;  // a first candidate needs a full pass
-            st->pending = 0;
-            begin_stop(jobs + j, st);
-        }
-    }
-    __syncthreads();
-    write_plan(jobs, plan, sh, shc);
+    settle_and_plan(jobs, plan, false, true, sh, shc);
 }
 
 // CountSupport (Algorithm 3) on row bitmaps, ahead of the stop kernel.  Work
@@ -794,14 +821,14 @@ __global__ __launch_bounds__(WG) void k_count(const Job *__restrict__ jobs,
         const uint32_t r_lim = r_begin + st->rpi;
         const uint32_t r_end = r_lim < st->last ? r_lim : st->last;
         const uint32_t K = st->k_cur;  // the last stop's survivors, in the current list
-        const uint32_t *live = st->parity ? J->live1 : J->live0;
+        const uint4 *live = st->parity ? J->live1 : J->live0;
         const uint32_t c0 = ct * CAND_PER_WG + wave * CW;
 
         uint32_t pidx[CW];
         uint32_t cnt[CW];
 #pragma unroll
         for (int q = 0; q < CW; ++q) {
-            pidx[q] = (c0 + (uint32_t)q < K) ? live[c0 + q] : NONE;
+            pidx[q] = (c0 + (uint32_t)q < K) ? live[(uint64_t)(c0 + q) * LREC].x : NONE;
             cnt[q] = 0;
         }
 
@@ -898,6 +925,43 @@ __device__ __forceinline__ CandItems cand_items(const Job *J, uint32_t p)
         for (int t = 0; t < KD / 2; ++t)
             ci.pk32[t] = 0u;
     }
+    return ci;
+}
+
+// A live record (see LREC) in registers.
+struct LRec {
+    uint32_t p, supp, sc, kb;  // kb: size | box << 16
+    uint32_t it[KD / 2];
+};
+
+__device__ __forceinline__ LRec load_rec(const uint4 *list, uint32_t c)
+{
+    const uint4 *r = list + (uint64_t)c * LREC;
+    const uint4 a = r[0], b = r[1], d = r[2];
+    LRec x;
+    x.p = a.x; x.supp = a.y; x.sc = a.z; x.kb = a.w;
+    x.it[0] = b.x; x.it[1] = b.y; x.it[2] = b.z; x.it[3] = b.w;
+    x.it[4] = d.x; x.it[5] = d.y; x.it[6] = d.z; x.it[7] = d.w;
+    return x;
+}
+
+__device__ __forceinline__ void store_rec(uint4 *list, uint32_t c, const LRec &x)
+{
+    uint4 *r = list + (uint64_t)c * LREC;
+    r[0] = make_uint4(x.p, x.supp, x.sc, x.kb);
+    r[1] = make_uint4(x.it[0], x.it[1], x.it[2], x.it[3]);
+    r[2] = make_uint4(x.it[4], x.it[5], x.it[6], x.it[7]);
+}
+
+__device__ __forceinline__ CandItems rec_items(const LRec &x)
+{
+    CandItems ci;
+    ci.k = x.kb & 0xFFFFu;
+    ci.wide = x.p;
+    ci.extra = NONE;
+#pragma unroll
+    for (int t = 0; t < KD / 2; ++t)
+        ci.pk32[t] = x.it[t];
     return ci;
 }
 
@@ -1100,22 +1164,22 @@ __device__ __forceinline__ uint32_t mask_dwords(const Job *J, uint32_t p, uint32
 }
 
 // Prune (Algorithm 4) and CheckFullPass (Algorithm 5) of NQ candidates per
-// thread at this stop.  For candidate q (when valid): p its pool entry, supp
-// its support after this stop's count, sc the stops it has been counted on
-// now (Algorithm 3's stop_I + 1), stw its standing before this stop, items
-// its size, words its nonzero mask dwords (row bitmaps).  A dashed circle
-// with supp >= tau becomes a box (promoted at this epoch); otherwise, if
-// supp + M * (stop_max - sc) < tau it is pruned (kept as known, never output
-// or generated again).  One that has seen every block becomes solid.
-// Survivors go to the next live list and new boxes to the next new-box list,
-// with one append atomic per workgroup; the stop's statistics are summed
-// over the workgroup.  Every thread of the workgroup calls.
+// thread at this stop.  Record q (when valid) holds the candidate's support
+// after this stop's count and the stops it has been counted on now
+// (Algorithm 3's stop_I + 1).  A dashed circle with supp >= tau becomes a
+// box (promoted at this epoch); otherwise, if supp + M * (stop_max - sc) <
+// tau it is pruned (kept as known, never output or generated again).  One
+// that has seen every block becomes solid; a box keeps its standing word
+// then (the collection takes dashed and solid boxes alike: none is dashed
+// once the run ends).  Survivors' records go to the next live list and new
+// boxes to the next new-box list, with one append atomic per workgroup;
+// the stop's statistics are summed over the workgroup.  words: nonzero
+// mask dwords (row bitmaps' trace figure).  Every thread of the workgroup
+// calls.
 template <int NQ>
-__device__ __forceinline__ void prune_core(const Job *J, JobState *st, const uint32_t (&p)[NQ],
-                           const uint32_t (&supp)[NQ], const uint32_t (&sc)[NQ],
-                           const uint32_t (&stw)[NQ], const uint32_t (&items)[NQ],
-                           const uint32_t (&words)[NQ], const bool (&valid)[NQ], uint32_t *sh_app,
-                           uint32_t *sh_red)
+__device__ __forceinline__ void prune_core(const Job *J, JobState *st, LRec (&r)[NQ],
+                                           const bool (&valid)[NQ], const uint32_t (&words)[NQ],
+                                           uint32_t *sh_app, uint32_t *sh_red)
 {
     const uint32_t E = st->epoch;
     bool keep[NQ], promoted[NQ];
@@ -1125,46 +1189,49 @@ __device__ __forceinline__ void prune_core(const Job *J, JobState *st, const uin
         keep[q] = promoted[q] = false;
         if (!valid[q])
             continue;
+        const uint32_t p = r[q].p, supp = r[q].supp, sc = r[q].sc;
+        bool box = ((r[q].kb >> 16) & 1u) != 0u;
         nwords += words[q];
-        nitems += items[q];
-        uint32_t state = standing_state(stw[q]), promo = standing_promo(stw[q]);
+        nitems += r[q].kb & 0xFFFFu;
         bool pruned = false;
-        if (state == ST_DASHED_CIRCLE) {
-            if (supp[q] >= J->tau) {
-                state = ST_DASHED_BOX;
-                promo = E;
+        if (!box) {
+            if (supp >= J->tau) {
+                box = true;
                 promoted[q] = true;
                 ++npro;
-            } else if ((uint64_t)supp[q] + (uint64_t)J->Mp * (uint64_t)(J->stop_max - sc[q]) <
+                r[q].kb |= 1u << 16;
+                J->pstate[p] = standing(ST_DASHED_BOX, E);
+            } else if ((uint64_t)supp + (uint64_t)J->Mp * (uint64_t)(J->stop_max - sc) <
                        (uint64_t)J->tau) {
-                state = ST_PRUNED;
                 pruned = true;
                 ++npru;
+                J->pstate[p] = standing(ST_PRUNED, PROMO_NONE);
             }
         }
         if (!pruned) {
-            if (sc[q] == J->stop_max) {
+            if (sc == J->stop_max) {
                 ++nsol;
-                state = state == ST_DASHED_BOX ? ST_SOLID_BOX : ST_SOLID_CIRCLE;
+                if (box)
+                    J->psupp[p] = supp;  // its final count, for the collection
+                else
+                    J->pstate[p] = standing(ST_SOLID_CIRCLE, PROMO_NONE);
             } else {
                 keep[q] = true;
-                const uint32_t r = J->stop_max - sc[q];
-                rem = r > rem ? r : rem;
+                const uint32_t rm = J->stop_max - sc;
+                rem = rm > rem ? rm : rem;
             }
         }
-        J->pstop[p[q]] = sc[q];
-        J->pstate[p[q]] = standing(state, promo);
     }
-    uint32_t *next = st->parity ? J->live0 : J->live1;
+    uint4 *next = st->parity ? J->live0 : J->live1;
     uint32_t *nbox = st->parity ? J->newbox0 : J->newbox1;
     uint32_t pos[NQ], npos[NQ];
     block_append2_rounds<NQ>(&st->k_next, keep, promoted, sh_app, pos, npos);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         if (keep[q])
-            next[pos[q]] = p[q];
+            store_rec(next, pos[q], r[q]);
         if (promoted[q])
-            nbox[npos[q]] = p[q];
+            nbox[npos[q]] = r[q].p;
     }
     uint32_t v[6] = {nwords, nitems, npro, npru, nsol, rem};
     block_reduce<5>(v, sh_red);
@@ -1187,78 +1254,60 @@ __device__ __forceinline__ void prune_core(const Job *J, JobState *st, const uin
     }
 }
 
-// Prune and CheckFullPass of NQ survivors per thread whose supports after
-// this stop's count are supp: their standing, stops and sizes are loaded
-// together first.  Every thread of the workgroup calls.
-template <int NQ>
-__device__ __forceinline__ void prune_survivors(const Job *J, JobState *st, const uint32_t (&p)[NQ],
-                                const uint32_t (&supp)[NQ], const bool (&valid)[NQ],
-                                uint32_t *sh_app, uint32_t *sh_red)
-{
-    uint32_t sc[NQ], stw[NQ], items[NQ], words[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        sc[q] = valid[q] ? J->pstop[p[q]] + 1u : 0u;
-        stw[q] = valid[q] ? J->pstate[p[q]] : 0u;
-        items[q] = valid[q] ? J->pk[p[q]] : 0u;
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-        words[q] = valid[q] && J->layout == LAYOUT_ROWS ? mask_dwords(J, p[q], NONE) : 0u;
-    prune_core<NQ>(J, st, p, supp, sc, stw, items, words, valid, sh_app, sh_red);
-}
-
 // Work item of the survivors of the last stop (the current list) at this
-// stop.  Bitsets, wave mode: WG/64 candidates, one wave each, counted over
-// the whole block, then pruned.  Bitsets, tile mode: (group of WG * cpt
-// candidates) x (chunk of tiles); each thread ANDs the tile rows of its
-// candidates' items word by word and popcounts, so a 64-bit AND tests 64
-// transactions.  With one chunk per group the work item prunes its group;
-// otherwise each chunk adds its partial counts with atomics that return the
-// old value (so each thread has waited for its adds before the barrier
-// below: a barrier alone does not wait for other waves' atomics), one
-// thread adds 1 to the group's counter, and the chunk that arrives last
-// reads the totals at device scope and prunes the group.  Row bitmaps:
-// k_count has counted; ZP * WG survivors are pruned.  Every thread calls.
-__device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uint64_t *tile, uint32_t *sh_app,
-                               uint32_t *sh_red, uint32_t *sh_supp, uint32_t *sh_flag)
+// stop; each candidate's record is read once.  Bitsets, wave mode: WG/64
+// candidates, one wave each, counted over the whole block, then pruned.
+// Bitsets, tile mode: (group of WG * cpt candidates) x (chunk of tiles);
+// each thread ANDs the tile rows of its candidates' items word by word and
+// popcounts, so a 64-bit AND tests 64 transactions.  With one chunk per
+// group the work item prunes its group; otherwise each chunk adds its
+// partial counts (per list position) with atomics that return the old value
+// (so each thread has waited for its adds before the barrier below: a
+// barrier alone does not wait for other waves' atomics), one thread adds 1
+// to the group's counter, and the chunk that arrives last takes the totals
+// at device scope (resetting them to zero) and prunes the group.  Row
+// bitmaps: k_count has added the block's counts to the pool; ZP * WG
+// survivors are pruned.  Every thread calls.
+__device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uint64_t *tile,
+                                               uint32_t *sh_app, uint32_t *sh_red,
+                                               uint32_t *sh_flag)
 {
     JobState *st = J->st;
-    const uint32_t *cur = st->parity ? J->live1 : J->live0;
+    const uint4 *cur = st->parity ? J->live1 : J->live0;
     const uint32_t K = st->k_cur;
     if (J->layout == LAYOUT_ROWS) {
-        uint32_t p[ZP], supp[ZP];
+        LRec r[ZP];
         bool valid[ZP];
+        uint32_t words[ZP];
 #pragma unroll
         for (int q = 0; q < ZP; ++q) {
             const uint32_t c = local * (ZP * WG) + (uint32_t)q * WG + threadIdx.x;
             valid[q] = c < K;
-            p[q] = valid[q] ? cur[c] : 0u;
+            r[q] = valid[q] ? load_rec(cur, c) : LRec{};
         }
 #pragma unroll
-        for (int q = 0; q < ZP; ++q)
-            supp[q] = valid[q] ? J->psupp[p[q]] : 0u;
-        prune_survivors<ZP>(J, st, p, supp, valid, sh_app, sh_red);
+        for (int q = 0; q < ZP; ++q) {
+            r[q].supp = valid[q] ? J->psupp[r[q].p] : 0u;  // k_count's running total
+            r[q].sc += 1u;
+            words[q] = valid[q] ? mask_dwords(J, r[q].p, NONE) : 0u;
+        }
+        prune_core<ZP>(J, st, r, valid, words, sh_app, sh_red);
         return;
     }
     if (st->cmode == 1) {
-        const uint32_t wave = threadIdx.x >> 6;
-        const uint32_t c = local * (WG / 64) + wave;
+        const uint32_t c = local * (WG / 64) + (threadIdx.x >> 6);
+        LRec r[1];
+        bool valid[1] = {false};
+        uint32_t words[1] = {0u};
+        r[0] = LRec{};
         if (c < K) {
-            const uint32_t p = __builtin_amdgcn_readfirstlane(cur[c]);
-            const uint32_t cnt = count_wave_bitsets(J, st, cand_items(J, p));
-            if ((threadIdx.x & 63u) == 0) {
-                const uint32_t supp = J->psupp[p] + cnt;  // the only writer of this count
-                J->psupp[p] = supp;
-                sh_supp[wave] = supp;
-            }
+            r[0] = load_rec(cur, __builtin_amdgcn_readfirstlane(c));
+            const uint32_t cnt = count_wave_bitsets(J, st, rec_items(r[0]));
+            r[0].supp += cnt;
+            r[0].sc += 1u;
+            valid[0] = (threadIdx.x & 63u) == 0u;  // the wave's first lane prunes it
         }
-        __syncthreads();
-        const uint32_t c1 = local * (WG / 64) + threadIdx.x;
-        bool valid[1] = {threadIdx.x < WG / 64 && c1 < K};
-        uint32_t p[1] = {valid[0] ? cur[c1] : 0u};
-        uint32_t supp[1] = {valid[0] ? sh_supp[threadIdx.x] : 0u};
-        prune_survivors<1>(J, st, p, supp, valid, sh_app, sh_red);
+        prune_core<1>(J, st, r, valid, words, sh_app, sh_red);
         return;
     }
     const uint32_t n_cg = st->n_ct;
@@ -1270,49 +1319,50 @@ __device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uin
     const uint32_t t0 = rc * st->rpi;
     const uint32_t t1 = t0 + st->rpi < ntile ? t0 + st->rpi : ntile;
     const uint32_t cpt = st->cpt;
-    uint32_t pidx[VT_CPT], cnt[VT_CPT];
+    LRec r[VT_CPT];
     bool valid[VT_CPT];
+    uint32_t cnt[VT_CPT];
+    const uint32_t cpos0 = cg * cpt * WG + threadIdx.x;  // list position of candidate q: + q * WG
 #pragma unroll
     for (int q = 0; q < VT_CPT; ++q) {
-        const uint32_t c = (cg * cpt + (uint32_t)q) * WG + threadIdx.x;
+        const uint32_t c = cpos0 + (uint32_t)q * WG;
         valid[q] = (uint32_t)q < cpt && c < K;
-        pidx[q] = valid[q] ? cur[c] : 0u;
+        r[q] = valid[q] ? load_rec(cur, c) : LRec{};
         cnt[q] = 0;
     }
     for (uint32_t t = t0; t < t1; ++t) {
         const uint32_t w0 = fw + t * tw;
         const uint32_t nwt = (lw + 1u - w0) < tw ? (lw + 1u - w0) : tw;
-        // the first candidate's item list loads during the tile fill, and
-        // each next one's while the current one is ANDed
-        CandItems cur_ci = valid[0] ? cand_items(J, pidx[0]) : CandItems{};
         stage_tile(J, st, w0, nwt, ts, tile);
-#pragma unroll
+        // one candidate at a time (the loop is not unrolled, so the compiler
+        // decodes one candidate's item rows at a time): the head record is
+        // counted, then the records rotate; VT_CPT rotations restore them
+#pragma unroll 1
         for (int q = 0; q < VT_CPT; ++q) {
-            CandItems nxt{};
-            if (q + 1 < VT_CPT && valid[q + 1])
-                nxt = cand_items(J, pidx[q + 1]);
-            if (valid[q])
-                cnt[q] += and_tile_items(J, cur_ci, tile, ts, nwt);
-            cur_ci = nxt;
+            if (valid[0])
+                cnt[0] += and_tile_items(J, rec_items(r[0]), tile, ts, nwt);
+            const LRec r0 = r[0];
+            const bool v0 = valid[0];
+            const uint32_t c0 = cnt[0];
+#pragma unroll
+            for (int u = 0; u + 1 < VT_CPT; ++u) {
+                r[u] = r[u + 1];
+                valid[u] = valid[u + 1];
+                cnt[u] = cnt[u + 1];
+            }
+            r[VT_CPT - 1] = r0;
+            valid[VT_CPT - 1] = v0;
+            cnt[VT_CPT - 1] = c0;
         }
     }
-    uint32_t supp[VT_CPT];
-    if (st->n_ri == 1u) {
+    if (st->n_ri > 1u) {
+        uint32_t bad = 0;
 #pragma unroll
         for (int q = 0; q < VT_CPT; ++q)
-            supp[q] = valid[q] ? J->psupp[pidx[q]] + cnt[q] : 0u;
-#pragma unroll
-        for (int q = 0; q < VT_CPT; ++q)
-            if (valid[q])
-                J->psupp[pidx[q]] = supp[q];  // the only writer of these counts
-    } else {
-#pragma unroll
-        for (int q = 0; q < VT_CPT; ++q)
-            if (valid[q] && cnt[q]) {
-                const uint32_t before = atomicAdd(J->psupp + pidx[q], cnt[q]);
-                if (before + cnt[q] > J->n)  // a support never exceeds n
-                    atomicAdd(&st->asserts, 1u);
-            }
+            if (valid[q] && cnt[q])  // the old value returned: this thread waits for its adds
+                bad |= atomicAdd(J->pcnt + cpos0 + q * WG, cnt[q]) > J->n ? 1u : 0u;
+        if (bad)
+            atomicAdd(&st->asserts, 1u);
         __syncthreads();
         if (threadIdx.x == 0)
             *sh_flag = atomicAdd(J->zarr + cg, 1u) == st->n_ri - 1u;
@@ -1321,14 +1371,20 @@ __device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uin
             return;
         if (threadIdx.x == 0)
             __hip_atomic_store(J->zarr + cg, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // every chunk's add is complete: read the totals at device scope
+        // every chunk's add is complete: take the totals, leaving zeros
 #pragma unroll
         for (int q = 0; q < VT_CPT; ++q)
-            supp[q] = valid[q] ? __hip_atomic_load(J->psupp + pidx[q], __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT)
-                               : 0u;
+            cnt[q] = valid[q] ? atomicExch(J->pcnt + cpos0 + q * WG, 0u) : 0u;
     }
-    prune_survivors<VT_CPT>(J, st, pidx, supp, valid, sh_app, sh_red);
+#pragma unroll
+    for (int q = 0; q < VT_CPT; ++q) {
+        if (valid[q] && (uint64_t)r[q].supp + cnt[q] > J->n)  // a support never exceeds n
+            atomicAdd(&st->asserts, 1u);
+        r[q].supp += cnt[q];
+        r[q].sc += 1u;
+    }
+    const uint32_t words[VT_CPT] = {};  // a figure of the row-bitmap count only
+    prune_core<VT_CPT>(J, st, r, valid, words, sh_app, sh_red);
 }
 
 // Copy W 64-bit words (the loads of a group of eight are issued together).
@@ -1613,15 +1669,19 @@ __device__ __forceinline__ void candgen_stop(const Job *J, unsigned long long ch
     uint32_t cw[KD / 2];  // C's frequent-item indices, ascending (kc <= KD)
 #pragma unroll
     for (int u = 0; u < KD / 2; ++u)
-        cw[u] = ((uint32_t)(2 * u) <= k ? c_item(sw, pos, a, 2 * u) : 0u) |
-                (((uint32_t)(2 * u + 1) <= k ? c_item(sw, pos, a, 2 * u + 1) : 0u) << 16);
+        cw[u] = 0u;
     if (stored) {
+#pragma unroll
+        for (int u = 0; u < KD / 2; ++u)
+            cw[u] = ((uint32_t)(2 * u) <= k ? c_item(sw, pos, a, 2 * u) : 0u) |
+                    (((uint32_t)(2 * u + 1) <= k ? c_item(sw, pos, a, 2 * u + 1) : 0u) << 16);
         const uint32_t i = J->l1[a];
         copy_words(J->pmask + (uint64_t)np * W, J->pmask + (uint64_t)p * W, W);
         J->pmask[(uint64_t)np * W + (i >> 6)] |= 1ull << (i & 63u);
         J->phash[np] = hC;
         J->pnz[np] = J->pnz[p] | (1ull << (i >> 6));
         J->pk[np] = kc;
+        J->pstate[np] = standing(ST_DASHED_CIRCLE, PROMO_NONE);  // Prune below may change it
         if (kc <= (uint32_t)KD) {
             uint4 *ci = (uint4 *)(J->pitems + (uint64_t)np * KD);
             ci[0] = make_uint4(cw[0], cw[1], cw[2], cw[3]);
@@ -1693,21 +1753,26 @@ __device__ __forceinline__ void candgen_stop(const Job *J, unsigned long long ch
         cnt = stored ? sh_cnt[rank] : 0u;
     }
     // Prune and CheckFullPass: a dashed circle counted on one block
-    uint32_t pp[1] = {np}, supp[1] = {cnt}, sc[1] = {1u};
-    uint32_t stw[1] = {standing(ST_DASHED_CIRCLE, PROMO_NONE)}, items[1] = {kc};
-    uint32_t words[1] = {stored && !vert ? mask_dwords(J, p, J->l1[a]) : 0u};
+    LRec r[1];
+    r[0].p = np;
+    r[0].supp = cnt;
+    r[0].sc = 1u;
+    r[0].kb = kc;
+#pragma unroll
+    for (int u = 0; u < KD / 2; ++u)
+        r[0].it[u] = cw[u];
     bool ok[1] = {stored};
-    if (stored)
-        J->psupp[np] = cnt;
-    prune_core<1>(J, st, pp, supp, sc, stw, items, words, ok, sh_app, sh_red);
+    uint32_t words[1] = {stored && !vert ? mask_dwords(J, p, J->l1[a]) : 0u};
+    if (stored && !vert)
+        J->psupp[np] = cnt;  // row bitmaps keep the running total in the pool
+    prune_core<1>(J, st, r, ok, words, sh_app, sh_red);
 }
 
 // One stop for every job in the table: MakeCandidates chunks (with the new
 // candidates' count and prune) of every job first, then the survivors' work
 // items of every job.  The last workgroup to finish completes the stop for
 // every job, begins its next one and plans the next launch.  Three waves per
-// SIMD (what the LDS tile allows) hold the item lists loaded ahead in
-// registers without spilling.
+// SIMD (what the LDS tile allows).
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_stop(
     const Job *__restrict__ jobs, Plan *plan)
 {
@@ -1718,8 +1783,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     __shared__ unsigned long long shc[WG / 64];
     __shared__ uint32_t sh_flag;
     const uint32_t njobs = plan->njobs;
-    const unsigned long long ncg = plan->pre_cg[njobs];
-    const unsigned long long total = ncg + plan->pre_countv[njobs];
+    const unsigned long long ncg = plan->total_cg;
+    const unsigned long long total = ncg + plan->total_v;
     for (unsigned long long it = blockIdx.x; it < total; it += gridDim.x) {
         if (it < ncg) {
             const uint32_t j = find_job(plan->pre_cg, njobs, it);
@@ -1727,8 +1792,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         } else {
             const uint32_t v = (uint32_t)(it - ncg);
             const uint32_t j = find_job(plan->pre_countv, njobs, v);
-            survivors_stop(jobs + j, v - plan->pre_countv[j], tile, sh_app, sh_red, sh_cnt,
-                           &sh_flag);
+            survivors_stop(jobs + j, v - plan->pre_countv[j], tile, sh_app, sh_red, &sh_flag);
         }
     }
     __syncthreads();
@@ -1736,15 +1800,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         sh_flag = arrive_last(plan->tickets, total < gridDim.x ? (total ? (uint32_t)total : 1u)
                                                               : gridDim.x);
     __syncthreads();
-    if (sh_flag) {
-        for (uint32_t j = threadIdx.x; j < njobs; j += WG) {
-            JobState *st = jobs[j].st;
-            if (!st->done && !st->overflow && !st->pending)
-                end_stop(jobs + j, st);
-        }
-        __syncthreads();
-        write_plan(jobs, plan, (uint32_t *)tile, shc);
-    }
+    if (sh_flag)
+        settle_and_plan(jobs, plan, true, false, (uint32_t *)tile, shc);
 }
 
 // Gather solid boxes (the output L without its 1-itemsets), each with its
@@ -1756,7 +1813,10 @@ __global__ __launch_bounds__(WG) void k_collect(const Job *__restrict__ jobs)
     const uint32_t W = J->W;
     for (uint32_t b = blockIdx.x * WG; b < pool_n; b += gridDim.x * WG) {
         const uint32_t p = b + threadIdx.x;
-        const bool box = p < pool_n && standing_state(J->pstate[p]) == ST_SOLID_BOX;
+        // a box keeps its dashed standing word when it becomes solid; the run
+        // has ended, so every box is solid
+        const uint32_t sw = p < pool_n ? standing_state(J->pstate[p]) : ST_PRUNED;
+        const bool box = sw == ST_SOLID_BOX || sw == ST_DASHED_BOX;
         const uint32_t pos = wave_append(J->out_n, box, true);
         if (box) {
             const uint64_t *pm = J->pmask + (uint64_t)p * W;
