@@ -975,32 +975,50 @@ __device__ __forceinline__ uint32_t count_wave_bitsets(const Job *J, const JobSt
     const uint64_t lo_mask = ~0ull << (st->first & 63u);
     const uint64_t hi_mask =
         (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
-    const uint32_t nw = J->nw;
+    const uint64_t nw = J->nw;
+    const uint64_t *__restrict__ fv = J->fvert;
+    const uint32_t fw = st->fw, lw = st->lw;
     uint32_t cnt = 0;
     if (ci.k <= (uint32_t)KD) {
-        uint32_t row[KD];
-#pragma unroll
-        for (int t = 0; t < KD; ++t)
-            row[t] = (uint32_t)t < ci.k ? (ci.pk32[t >> 1] >> (16 * (t & 1))) & 0xFFFFu : 0u;
-        // 3 words per lane per pass: all their loads issued together
-        for (uint32_t w0 = st->fw + lane; w0 <= st->lw; w0 += 192u) {
+        // items four at a time, 3 words per lane per pass: the twelve loads of a
+        // group carry no condition (past the list: the first item again, past
+        // the block: the last word, both masked out) and issue together
+        for (uint32_t w0 = fw + lane; w0 <= lw; w0 += 192u) {
             uint64_t acc[3];
+            uint32_t wc[3];
 #pragma unroll
             for (int u = 0; u < 3; ++u) {
                 const uint32_t w = w0 + 64u * u;
-                acc[u] = w <= st->lw ? (w == st->fw ? lo_mask : ~0ull) & (w == st->lw ? hi_mask : ~0ull)
-                                     : 0ull;
+                wc[u] = w <= lw ? w : lw;
+                acc[u] = w <= lw ? (w == fw ? lo_mask : ~0ull) & (w == lw ? hi_mask : ~0ull) : 0ull;
             }
+            uint32_t qv[KD / 2];
 #pragma unroll
-            for (int t = 0; t < KD; ++t)
-                if ((uint32_t)t < ci.k) {
+            for (int u = 0; u < KD / 2; ++u)
+                qv[u] = ci.pk32[u];
+            const uint32_t first = qv[0] & 0xFFFFu;
+#pragma unroll 1
+            for (uint32_t t0 = 0; t0 < ci.k; t0 += 4u) {
+                uint32_t row[4];
 #pragma unroll
-                    for (int u = 0; u < 3; ++u) {
-                        const uint32_t w = w0 + 64u * u;
-                        if (w <= st->lw)
-                            acc[u] &= J->fvert[(uint64_t)row[t] * nw + w];
-                    }
+                for (int t = 0; t < 4; ++t) {
+                    row[t] = t0 + t < ci.k ? qv[0] & 0xFFFFu : first;
+#pragma unroll
+                    for (int u = 0; u < KD / 2; ++u)
+                        qv[u] = (qv[u] >> 16) | (u + 1 < KD / 2 ? qv[u + 1] << 16 : 0u);
                 }
+                uint64_t v[4][3];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int u = 0; u < 3; ++u)
+                        v[t][u] = fv[(uint64_t)row[t] * nw + wc[u]];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int u = 0; u < 3; ++u)
+                        acc[u] &= v[t][u];
+            }
 #pragma unroll
             for (int u = 0; u < 3; ++u)
                 cnt += (uint32_t)__popcll(acc[u]);
@@ -1060,32 +1078,41 @@ __device__ __forceinline__ uint32_t count_wave_rows(const Job *J, const JobState
     return cnt;
 }
 
-// Stage the tile of words [w0, w0 + nwt) of the current block: for every
-// frequent item a, its bitset words at tile[a * ts ...] (edge words masked to
-// the block).  Every thread of the workgroup calls; the barriers on both
-// sides keep the previous tile's readers and this tile's readers apart.
+// Stage the tile of words [w0, w0 + tw) of the current block: for every
+// frequent item a, its bitset words at tile[a * ts ...], edge words masked
+// to the block and words past the block's last word zero (so a tile is
+// always ANDed whole).  Every thread of the workgroup calls; the barriers on
+// both sides keep the previous tile's readers and this tile's readers apart.
 __device__ __forceinline__ void stage_tile(const Job *J, const JobState *st, uint32_t w0,
-                                           uint32_t nwt, uint32_t ts, uint64_t *tile)
+                                           uint32_t tw, uint32_t ts, uint64_t *tile)
 {
     const uint32_t fw = st->fw, lw = st->lw, nL1 = st->nL1;
     const uint64_t lo_mask = ~0ull << (st->first & 63u);
     const uint64_t hi_mask = (st->last & 63u) ? ((1ull << (st->last & 63u)) - 1ull) : ~0ull;
+    // the job's fields in registers before the loop: a field read inside the
+    // predicated loads would be re-read (and waited for) before every load
+    const uint64_t *__restrict__ fv = J->fvert;
+    const uint64_t nw = J->nw;
     __syncthreads();
     // thread (q, r) loads word r of items q, q + per, q + 2 per, ...
-    const uint32_t per = WG / nwt;
-    const uint32_t q = threadIdx.x / nwt, r = threadIdx.x - q * nwt;
+    const uint32_t per = WG / tw;
+    const uint32_t q = threadIdx.x / tw, r = threadIdx.x - q * tw;
     if (q < per) {
         const uint32_t g = w0 + r;
-        const uint64_t mask = (g == fw ? lo_mask : ~0ull) & (g == lw ? hi_mask : ~0ull);
-        // 16 loads in flight per batch (the tail of the last batch predicated)
-        const uint64_t *src = J->fvert + g;
-        for (uint32_t a = q; a < nL1; a += 16u * per) {
-            uint64_t v[16];
+        const uint64_t mask = g > lw ? 0ull
+                                     : (g == fw ? lo_mask : ~0ull) & (g == lw ? hi_mask : ~0ull);
+        const uint64_t *src = fv + (g < lw ? g : lw);  // in bounds; masked to 0 past the block
+        // 12 loads in flight per batch: every address is valid (clamped to the
+        // last item), so the loads carry no condition and issue together
+        for (uint32_t a = q; a < nL1; a += 12u * per) {
+            uint64_t v[12];
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
-                v[u] = a + u * per < nL1 ? src[(uint64_t)(a + u * per) * J->nw] : 0ull;
+            for (int u = 0; u < 12; ++u) {
+                const uint32_t it = a + u * per < nL1 ? a + u * per : nL1 - 1u;
+                v[u] = src[(uint64_t)it * nw];
+            }
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
+            for (int u = 0; u < 12; ++u)
                 if (a + u * per < nL1)
                     tile[(a + u * per) * ts + r] = v[u] & mask;
         }
@@ -1093,26 +1120,61 @@ __device__ __forceinline__ void stage_tile(const Job *J, const JobState *st, uin
     __syncthreads();
 }
 
-// Transactions of a staged tile (nwt words) that contain the candidate: the
-// AND of its items' tile rows, popcounted.
+// Transactions of a staged tile (tw words, words past the block zero) that
+// contain the candidate: the AND of its items' tile rows, popcounted.  With
+// full 16-word tiles and an item list, every word is read without a
+// per-word condition, so each row's loads are issued together.
 __device__ __forceinline__ uint32_t and_tile_items(const Job *J, const CandItems &ci,
                                                    const uint64_t *tile, uint32_t ts, uint32_t nwt)
 {
+    if (nwt == (uint32_t)VT_MAXW && ci.k <= (uint32_t)KD) {
+        // one item row per iteration (the loop is not unrolled, so no row's
+        // loads are hoisted ahead of its turn): its 16 words are read with no
+        // per-word condition and all in flight together; the item list is a
+        // queue of 16-bit entries shifted by one item per iteration
+        uint64_t acc[VT_MAXW];
+#pragma unroll
+        for (int w = 0; w < VT_MAXW; ++w)
+            acc[w] = ~0ull;
+        uint32_t qv[KD / 2];
+#pragma unroll
+        for (int u = 0; u < KD / 2; ++u)
+            qv[u] = ci.pk32[u];
+#pragma unroll 1
+        for (uint32_t t = 0; t < ci.k; ++t) {
+            const uint64_t *row = tile + (qv[0] & 0xFFFFu) * ts;
+#pragma unroll
+            for (int u = 0; u < KD / 2; ++u)
+                qv[u] = (qv[u] >> 16) | (u + 1 < KD / 2 ? qv[u + 1] << 16 : 0u);
+#pragma unroll
+            for (int w = 0; w < VT_MAXW; ++w)
+                acc[w] &= row[w];
+        }
+        uint32_t sum = 0;
+#pragma unroll
+        for (int w = 0; w < VT_MAXW; ++w)
+            sum += (uint32_t)__popcll(acc[w]);
+        return sum;
+    }
     uint64_t acc[VT_MAXW];
 #pragma unroll
     for (int w = 0; w < VT_MAXW; ++w)
         acc[w] = ~0ull;
     if (ci.k <= (uint32_t)KD) {
+        uint32_t qv[KD / 2];
 #pragma unroll
-        for (int t = 0; t < KD; ++t) {
-            if ((uint32_t)t < ci.k) {
-                const uint32_t idx = (ci.pk32[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
-                const uint64_t *row = tile + idx * ts;
+        for (int u = 0; u < KD / 2; ++u)
+            qv[u] = ci.pk32[u];
+#pragma unroll 1
+        for (uint32_t t = 0; t < ci.k; ++t) {
+            const uint64_t *row = tile + (qv[0] & 0xFFFFu) * ts;
 #pragma unroll
-                for (int w = 0; w < VT_MAXW; ++w)
-                    if ((uint32_t)w < nwt)
-                        acc[w] &= row[w];
-            }
+            for (int u = 0; u < KD / 2; ++u)
+                qv[u] = (qv[u] >> 16) | (u + 1 < KD / 2 ? qv[u + 1] << 16 : 0u);
+#pragma unroll
+            for (int w = 0; w < VT_MAXW; ++w)
+                if ((uint32_t)w < nwt)
+                    acc[w] &= row[w];
         }
     } else {
         if (ci.extra != NONE) {
@@ -1332,15 +1394,14 @@ __device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uin
     }
     for (uint32_t t = t0; t < t1; ++t) {
         const uint32_t w0 = fw + t * tw;
-        const uint32_t nwt = (lw + 1u - w0) < tw ? (lw + 1u - w0) : tw;
-        stage_tile(J, st, w0, nwt, ts, tile);
+        stage_tile(J, st, w0, tw, ts, tile);
         // one candidate at a time (the loop is not unrolled, so the compiler
         // decodes one candidate's item rows at a time): the head record is
         // counted, then the records rotate; VT_CPT rotations restore them
 #pragma unroll 1
         for (int q = 0; q < VT_CPT; ++q) {
             if (valid[0])
-                cnt[0] += and_tile_items(J, rec_items(r[0]), tile, ts, nwt);
+                cnt[0] += and_tile_items(J, rec_items(r[0]), tile, ts, tw);
             const LRec r0 = r[0];
             const bool v0 = valid[0];
             const uint32_t c0 = cnt[0];
@@ -1712,10 +1773,9 @@ __device__ __forceinline__ void candgen_stop(const Job *J, unsigned long long ch
         const uint32_t ts = vert_tile_stride(tw);
         for (uint32_t t = 0; t < ntile; ++t) {
             const uint32_t w0 = st->fw + t * tw;
-            const uint32_t nwt = (st->lw + 1u - w0) < tw ? (st->lw + 1u - w0) : tw;
-            stage_tile(J, st, w0, nwt, ts, lds);
+            stage_tile(J, st, w0, tw, ts, lds);
             if (stored)
-                cnt += and_tile_items(J, ci, lds, ts, nwt);
+                cnt += and_tile_items(J, ci, lds, ts, tw);
         }
     } else {
         // few: one wave per candidate, the candidates' records in LDS
