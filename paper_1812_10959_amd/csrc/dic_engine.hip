@@ -501,8 +501,7 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
             J.fvert = (uint64_t *)a->fvert;
         }
         HIP_TRY(hipMemsetAsync(J.slots, 0xFF, L.hslots * 8, s_));
-        HIP_TRY(hipMemsetAsync(J.zarr, 0, (L.zarr_n) * 4, s_));
-        HIP_TRY(hipMemsetAsync(J.pcnt, 0, (size_t)cap * 4, s_));
+        HIP_TRY(hipMemsetAsync(J.pcnt, 0, (size_t)cap * 8, s_));
         aux_host_[i] = J;
     }
     // first candidates: pairs of frequent items (nL1 x nL1 work), or every

@@ -223,9 +223,8 @@ struct Job {
     uint32_t *pstate;           // standing word (state, promotion stop) of each itemset
     unsigned long long *slots;  // open addressing: idx<<32 | fp24<<8 | k8
     uint4 *live0, *live1;       // cap records each (LREC uint4 words per record)
-    uint32_t *pcnt;             // cap: partial counts of a split group (zero between stops)
+    unsigned long long *pcnt;   // cap: count | arrivals << 32 of a split group (zero between stops)
     uint32_t *newbox0, *newbox1;  // cap each: boxes promoted at a stop (by parity)
-    uint32_t *zarr;             // cap / WG + 1 arrival counters of Z's tile chunks (zero between uses)
     uint32_t *l1;               // m
     uint32_t *item_cnt;         // m
     dic_stop_trace *trace;
@@ -271,9 +270,9 @@ inline uint64_t pool_cap_for(uint32_t nL1, uint32_t mult)
 // Layout of a job's candidate pool buffer (byte offsets of its arrays).
 struct PoolLayout {
     size_t mask, items, hash, nz, supp, state, k, slots, live0, live1, pcnt, newbox0, newbox1,
-        zarr, omask, ocnt, okey;
+        omask, ocnt, okey;
     size_t bytes;
-    uint64_t hslots, zarr_n;
+    uint64_t hslots;
     PoolLayout(uint64_t cap, uint32_t W)
     {
         hslots = next_pow2(2 * cap);
@@ -288,11 +287,9 @@ struct PoolLayout {
         slots = c.take(hslots * 8);
         live0 = c.take(cap * LREC * 16);
         live1 = c.take(cap * LREC * 16);
-        pcnt = c.take(cap * 4);
+        pcnt = c.take(cap * 8);
         newbox0 = c.take(cap * 4);
         newbox1 = c.take(cap * 4);
-        zarr_n = cap / WG + 1;
-        zarr = c.take(zarr_n * 4);
         omask = c.take(cap * W * 8);
         ocnt = c.take(cap * 4);
         okey = c.take(cap * 16);
@@ -333,10 +330,9 @@ inline void pool_assign(Job &J, const PoolLayout &L, char *b, uint32_t cap)
     J.slots = (unsigned long long *)(b + L.slots);
     J.live0 = (uint4 *)(b + L.live0);
     J.live1 = (uint4 *)(b + L.live1);
-    J.pcnt = (uint32_t *)(b + L.pcnt);
+    J.pcnt = (unsigned long long *)(b + L.pcnt);
     J.newbox0 = (uint32_t *)(b + L.newbox0);
     J.newbox1 = (uint32_t *)(b + L.newbox1);
-    J.zarr = (uint32_t *)(b + L.zarr);
     J.out_mask = (uint64_t *)(b + L.omask);
     J.out_cnt = (uint32_t *)(b + L.ocnt);
     J.out_key = (unsigned long long *)(b + L.okey);

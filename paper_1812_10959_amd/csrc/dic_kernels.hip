@@ -1323,16 +1323,12 @@ __device__ __forceinline__ void prune_core(const Job *J, JobState *st, LRec (&r)
 // each thread ANDs the tile rows of its candidates' items word by word and
 // popcounts, so a 64-bit AND tests 64 transactions.  With one chunk per
 // group the work item prunes its group; otherwise each chunk adds its
-// partial counts (per list position) with atomics that return the old value
-// (so each thread has waited for its adds before the barrier below: a
-// barrier alone does not wait for other waves' atomics), one thread adds 1
-// to the group's counter, and the chunk that arrives last takes the totals
-// at device scope (resetting them to zero) and prunes the group.  Row
-// bitmaps: k_count has added the block's counts to the pool; ZP * WG
-// survivors are pruned.  Every thread calls.
+// partial count and one arrival to a word per candidate (list position),
+// and the chunk that finds every other chunk's arrival there prunes that
+// candidate with the total.  Row bitmaps: k_count has added the block's
+// counts to the pool; ZP * WG survivors are pruned.  Every thread calls.
 __device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uint64_t *tile,
-                                               uint32_t *sh_app, uint32_t *sh_red,
-                                               uint32_t *sh_flag)
+                                               uint32_t *sh_app, uint32_t *sh_red)
 {
     JobState *st = J->st;
     const uint4 *cur = st->parity ? J->live1 : J->live0;
@@ -1417,25 +1413,24 @@ __device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uin
         }
     }
     if (st->n_ri > 1u) {
-        uint32_t bad = 0;
+        // every chunk adds its count plus one arrival (2^32) to the
+        // candidate's word; the chunk that finds the others' n_ri - 1
+        // arrivals there is the last for that candidate: it has the total,
+        // clears the word and prunes the candidate
+        const unsigned long long last_arrivals = (unsigned long long)(st->n_ri - 1u) << 32;
 #pragma unroll
-        for (int q = 0; q < VT_CPT; ++q)
-            if (valid[q] && cnt[q])  // the old value returned: this thread waits for its adds
-                bad |= atomicAdd(J->pcnt + cpos0 + q * WG, cnt[q]) > J->n ? 1u : 0u;
-        if (bad)
-            atomicAdd(&st->asserts, 1u);
-        __syncthreads();
-        if (threadIdx.x == 0)
-            *sh_flag = atomicAdd(J->zarr + cg, 1u) == st->n_ri - 1u;
-        __syncthreads();
-        if (!*sh_flag)
-            return;
-        if (threadIdx.x == 0)
-            __hip_atomic_store(J->zarr + cg, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // every chunk's add is complete: take the totals, leaving zeros
-#pragma unroll
-        for (int q = 0; q < VT_CPT; ++q)
-            cnt[q] = valid[q] ? atomicExch(J->pcnt + cpos0 + q * WG, 0u) : 0u;
+        for (int q = 0; q < VT_CPT; ++q) {
+            if (!valid[q])
+                continue;
+            unsigned long long *wq = J->pcnt + cpos0 + q * WG;
+            const unsigned long long old = atomicAdd(wq, (1ull << 32) | cnt[q]);
+            if ((old & ~0xFFFFFFFFull) == last_arrivals) {
+                cnt[q] += (uint32_t)old;
+                __hip_atomic_store(wq, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                valid[q] = false;  // a later chunk prunes it
+            }
+        }
     }
 #pragma unroll
     for (int q = 0; q < VT_CPT; ++q) {
@@ -1852,7 +1847,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         } else {
             const uint32_t v = (uint32_t)(it - ncg);
             const uint32_t j = find_job(plan->pre_countv, njobs, v);
-            survivors_stop(jobs + j, v - plan->pre_countv[j], tile, sh_app, sh_red, &sh_flag);
+            survivors_stop(jobs + j, v - plan->pre_countv[j], tile, sh_app, sh_red);
         }
     }
     __syncthreads();
