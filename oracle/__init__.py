@@ -7,7 +7,10 @@ transaction-id lists).  Only the tests, the smoke check and the benchmark's
 CPU-baseline leg may import it; the GPU library never does, and this package
 never imports the GPU library.
 
-``build()`` compiles ``dic_oracle.c`` with gcc into ``liboracle.so`` beside it.
+``build()`` compiles ``dic_oracle.c`` with gcc into ``liboracle.so`` beside it
+(plain -O2, serial: the checker) and into ``liboracle_omp.so`` (-O3
+-march=native -fopenmp: the same source with its count loop shared among
+threads, timed as the benchmark's parallel CPU baseline; identical results).
 """
 from __future__ import annotations
 
@@ -21,7 +24,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dic_oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
+_SO_OMP = os.path.join(_HERE, "liboracle_omp.so")
 _lib = None
+_lib_omp = None
 
 OR_OK, OR_E_INVAL, OR_E_NOMEM, OR_E_RANGE = 0, -1, -2, -3
 
@@ -48,12 +53,73 @@ TRACE_FIELDS = ("stop", "rows", "live", "promoted", "pruned", "generated", "soli
 
 
 def build() -> str:
-    """Compile the oracle (plain -O2, no target-specific flags)."""
+    """Compile the oracle (plain -O2, no target-specific flags) and its
+    OpenMP build."""
     tmp = _SO + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
                            "-o", tmp, _SRC, "-lm"], cwd=_HERE)
     os.replace(tmp, _SO)
+    build_parallel()
     return _SO
+
+
+def build_parallel() -> str:
+    """The same source with -O3 -march=native -fopenmp (the count loop over
+    live candidates shared among threads)."""
+    tmp = _SO_OMP + ".tmp"
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-fopenmp", "-std=c11", "-Wall",
+                           "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"], cwd=_HERE)
+    os.replace(tmp, _SO_OMP)
+    return _SO_OMP
+
+
+def _declare(L):
+    u64, u32, p = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    L.oracle_threads.argtypes = [ctypes.c_int]
+    L.oracle_threads.restype = ctypes.c_int
+    L.oracle_dic_init.argtypes = [p, u64, u32, ctypes.c_double, u64, ctypes.c_int, ctypes.c_int,
+                                  pp]
+    for f in ("oracle_result_size", "oracle_result_trace_len"):
+        getattr(L, f).restype = u64
+        getattr(L, f).argtypes = [p]
+    L.oracle_result_words.restype = u32
+    L.oracle_result_words.argtypes = [p]
+    L.oracle_result_masks.restype = p
+    L.oracle_result_masks.argtypes = [p]
+    L.oracle_result_counts.restype = p
+    L.oracle_result_counts.argtypes = [p]
+    L.oracle_result_stats.argtypes = [p, ctypes.POINTER(_Stats)]
+    L.oracle_result_trace.restype = ctypes.POINTER(_Stop)
+    L.oracle_result_trace.argtypes = [p]
+    L.oracle_result_free.argtypes = [p]
+    L.oracle_result_free.restype = None
+
+
+def _load_parallel():
+    global _lib_omp
+    if _lib_omp is not None:
+        return _lib_omp
+    if not os.path.exists(_SO_OMP) or os.path.getmtime(_SO_OMP) < os.path.getmtime(_SRC):
+        build_parallel()
+    L = ctypes.CDLL(_SO_OMP)
+    _declare(L)
+    _lib_omp = L
+    return L
+
+
+def dic_parallel(rows, m: int, minsup: float, M: int, threads: int) -> tuple:
+    """oracle.dic from the OpenMP build with the given thread count; returns
+    (Result, threads used)."""
+    L = _load_parallel()
+    used = L.oracle_threads(int(threads))
+    r = _rows(rows)
+    h = ctypes.c_void_p()
+    rc = L.oracle_dic_init(r.ctypes.data, r.shape[0], int(m), float(minsup), int(M), 0, 0,
+                           ctypes.byref(h))
+    if rc:
+        raise OracleError(rc, "oracle_dic (OpenMP build)")
+    return _collect(L, h, "dic"), used
 
 
 def _load():

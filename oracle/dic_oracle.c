@@ -25,10 +25,16 @@
  *                          which is exact because support is anti-monotone).
  *
  * Everything is integer except minsup, which becomes the integer threshold
- * once.  No parallelism, no blocking, no layout tricks.
+ * once.  No blocking, no layout tricks.  Built plainly it is serial; built
+ * with OpenMP (the benchmark's CPU baseline) the one loop the paper runs in
+ * parallel -- each live candidate's count over a block, Algorithm 3 --
+ * is shared among threads, with identical results.
  */
 #include "dic_oracle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -46,6 +52,18 @@ struct or_result {
 /* ------------------------------------------------------------------------ */
 /* threshold                                                                 */
 /* ------------------------------------------------------------------------ */
+
+int oracle_threads(int threads)
+{
+#ifdef _OPENMP
+    if (threads > 0)
+        omp_set_num_threads(threads);
+    return omp_get_max_threads();
+#else
+    (void)threads;
+    return 1;
+#endif
+}
 
 int oracle_tau(double minsup, uint64_t n, uint64_t *tau)
 {
@@ -280,94 +298,311 @@ static int known_set(known_map *k, const uint64_t *key, int st)
 /* Dynamic Itemset Counting                                                  */
 /* ------------------------------------------------------------------------ */
 
-/* The itemset record of Section 4.1: mask, k, stop, supp, shape. */
-enum { SHAPE_NIL = 0, SHAPE_CIRCLE = 1, SHAPE_BOX = 2 };
-
+/* A candidate under count (Section 3's dashed itemsets) or a finished one
+ * (solid): where its mask sits in the arena, its size, how many blocks it has
+ * been counted on, how many transactions of those blocks contain it, and its
+ * standing.  A candidate is erased by setting gone. */
 typedef struct {
-    uint64_t off; /* mask = arena[off .. off+W) */
-    uint32_t k;
-    uint64_t stop;
-    uint64_t supp;
-    int shape;
-} rec;
+    uint64_t at;
+    uint32_t size;
+    uint64_t blocks;
+    uint64_t hits;
+    uint8_t reached; /* its count reached the threshold (a box) */
+    uint8_t gone;
+} cand;
 
 typedef struct {
     uint32_t W;
-    uint64_t *arena;
+    uint64_t *arena; /* every mask ever created, W words each */
     uint64_t arena_n, arena_cap;
-    rec *dashed;
-    uint64_t nd, capd;
-    rec *solid;
-    uint64_t ns, caps;
-    known_map known;
-} dic_state;
+    cand *live; /* candidates still counted block by block */
+    uint64_t nlive, caplive;
+    cand *done; /* counted over a full pass (and the first pass's 1-itemsets) */
+    uint64_t ndone, capdone;
+    known_map seen; /* every itemset ever created, with its standing */
+    uint64_t *fresh; /* arena offsets of the candidates that reached the threshold at this stop */
+    uint64_t nfresh, capfresh;
+} miner;
 
-static int new_mask(dic_state *S, const uint64_t *mask, uint64_t *off)
+static const uint64_t *mask_of(const miner *S, const cand *c) { return S->arena + c->at; }
+
+static int arena_put(miner *S, const uint64_t *mask, uint64_t *at)
 {
     if (!grow((void **)&S->arena, &S->arena_cap, S->arena_n + S->W, sizeof(uint64_t)))
         return 0;
     memcpy(S->arena + S->arena_n, mask, S->W * sizeof(uint64_t));
-    *off = S->arena_n;
+    *at = S->arena_n;
     S->arena_n += S->W;
     return 1;
 }
 
-static int push_rec(rec **v, uint64_t *n, uint64_t *cap, rec r)
+static int cand_push(cand **v, uint64_t *n, uint64_t *cap, cand c)
 {
-    if (!grow((void **)v, cap, *n + 1, sizeof(rec)))
+    if (!grow((void **)v, cap, *n + 1, sizeof(cand)))
         return 0;
-    (*v)[(*n)++] = r;
+    (*v)[(*n)++] = c;
     return 1;
 }
 
-/* every maximal proper subset of C is a box (dashed or solid) */
-static int all_subsets_boxes(dic_state *S, const uint64_t *C, uint64_t *tmp)
+/* A new candidate: counted on no block yet, known as not (yet) frequent. */
+static int start_candidate(miner *S, const uint64_t *mask, uint32_t size)
 {
-    uint32_t W = S->W;
-    for (uint32_t w = 0; w < W; ++w) {
-        uint64_t x = C[w];
-        while (x) {
-            uint64_t low = x & (~x + 1);
-            memcpy(tmp, C, W * sizeof(uint64_t));
-            tmp[w] &= ~low;
-            if (known_get(&S->known, tmp) != K_BOX)
+    cand c;
+    memset(&c, 0, sizeof(c));
+    c.size = size;
+    if (!arena_put(S, mask, &c.at) || !cand_push(&S->live, &S->nlive, &S->caplive, c))
+        return 0;
+    return known_set(&S->seen, mask, K_CIRCLE);
+}
+
+/* Drop the erased candidates from the live list, keeping the others' order. */
+static void sweep_live(miner *S)
+{
+    uint64_t j = 0;
+    for (uint64_t i = 0; i < S->nlive; ++i)
+        if (!S->live[i].gone)
+            S->live[j++] = S->live[i];
+    S->nlive = j;
+}
+
+/* Each maximal proper subset of C (C minus one item) is known as frequent. */
+static int maximal_subsets_frequent(const miner *S, const uint64_t *C, uint64_t *scratch)
+{
+    for (uint32_t w = 0; w < S->W; ++w)
+        for (uint64_t rest = C[w]; rest; rest &= rest - 1) {
+            memcpy(scratch, C, S->W * sizeof(uint64_t));
+            scratch[w] &= ~(rest & (~rest + 1));
+            if (known_get(&S->seen, scratch) != K_BOX)
                 return 0;
-            x &= x - 1;
+        }
+    return 1;
+}
+
+/* Algorithm 3: every live candidate is counted on the block [lo, hi): one
+ * more block seen, plus the block's transactions that contain it.  Each
+ * candidate's count is its own, so the candidates may be shared among
+ * threads (the loop the paper parallelises; built without OpenMP it runs
+ * serially). */
+static void count_block_phase(miner *S, const uint64_t *rows, uint64_t lo, uint64_t hi)
+{
+    const uint32_t W = S->W;
+    const int64_t nl = (int64_t)S->nlive;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t i = 0; i < nl; ++i) {
+        cand *c = &S->live[i];
+        const uint64_t *mask = mask_of(S, c);
+        uint64_t h = 0;
+        for (uint64_t t = lo; t < hi; ++t)
+            h += (uint64_t)is_subset(mask, rows + t * W, W);
+        c->blocks += 1;
+        c->hits += h;
+    }
+}
+
+/* Algorithm 4 on the live circles, in list order.  One whose count reached
+ * tau becomes a box and is noted as fresh.  One that cannot reach tau any
+ * more is erased (and known as infrequent): even if every transaction of
+ * the blocks it has not been counted on held it -- at most Mp per block,
+ * nblk blocks in a pass -- it would fall short.  Every live circle that
+ * strictly contains an erased one goes with it. */
+static int threshold_phase(miner *S, uint64_t tau, uint64_t Mp, uint64_t nblk, or_stop *tr,
+                           or_stats *st)
+{
+    const uint32_t W = S->W;
+    S->nfresh = 0;
+    uint32_t widest = 0; /* no circle of this size or less has a proper superset */
+    for (uint64_t i = 0; i < S->nlive; ++i)
+        if (!S->live[i].reached && S->live[i].size > widest)
+            widest = S->live[i].size;
+    for (uint64_t i = 0; i < S->nlive; ++i) {
+        cand *c = &S->live[i];
+        if (c->reached || c->gone)
+            continue;
+        if (c->hits >= tau) {
+            c->reached = 1;
+            tr->promoted++;
+            if (!known_set(&S->seen, mask_of(S, c), K_BOX) ||
+                !grow((void **)&S->fresh, &S->capfresh, S->nfresh + 1, sizeof(uint64_t)))
+                return 0;
+            S->fresh[S->nfresh++] = c->at;
+            continue;
+        }
+        const uint64_t best = c->hits + Mp * (nblk - c->blocks);
+        if (best >= tau)
+            continue;
+        c->gone = 1;
+        tr->pruned++;
+        if (!known_set(&S->seen, mask_of(S, c), K_INFREQUENT))
+            return 0;
+        for (uint64_t j = 0; c->size < widest && j < S->nlive; ++j) {
+            cand *d = &S->live[j];
+            if (j == i || d->reached || d->gone || d->size <= c->size ||
+                !is_subset(mask_of(S, c), mask_of(S, d), W))
+                continue;
+            d->gone = 1;
+            st->superset_prunes++;
+            tr->pruned++;
+            if (!known_set(&S->seen, mask_of(S, d), K_INFREQUENT))
+                return 0;
+        }
+    }
+    sweep_live(S);
+    return 1;
+}
+
+/* MakeCandidates, reading 0: each box that reached tau at this stop, grown
+ * by each frequent item it lacks, is a new candidate when that itemset is new
+ * and all its maximal proper subsets are frequent. */
+static int extend_fresh_phase(miner *S, const uint32_t *freq, uint64_t nfreq, uint64_t *C,
+                              uint64_t *scratch, or_stop *tr)
+{
+    const uint32_t W = S->W;
+    for (uint64_t f = 0; f < S->nfresh; ++f) {
+        /* the arena may move as candidates are added: address it afresh */
+        const uint32_t size = n_items(S->arena + S->fresh[f], W) + 1u;
+        for (uint64_t a = 0; a < nfreq; ++a) {
+            const uint64_t *base = S->arena + S->fresh[f];
+            const uint32_t it = freq[a];
+            if (has_item(base, it))
+                continue;
+            memcpy(C, base, W * sizeof(uint64_t));
+            C[it >> 6] |= 1ull << (it & 63);
+            if (known_get(&S->seen, C) != K_EMPTY || !maximal_subsets_frequent(S, C, scratch))
+                continue;
+            if (!start_candidate(S, C, size))
+                return 0;
+            tr->generated++;
         }
     }
     return 1;
 }
 
-/* Insert candidate C into DASHED as a dashed circle (supp 0, stop 0). */
-static int add_candidate(dic_state *S, const uint64_t *C, uint32_t k)
+/* MakeCandidates, reading 1 (the paper's wording taken literally): the OR of
+ * every two boxes of one size that has exactly one more item, when new and
+ * with all maximal proper subsets frequent.  Finished boxes come first, then
+ * live ones, each in list order. */
+static int extend_pairs_phase(miner *S, uint64_t *C, uint64_t *scratch, or_stop *tr)
 {
-    rec r;
-    if (!new_mask(S, C, &r.off))
-        return 0;
-    r.k = k;
-    r.stop = 0;
-    r.supp = 0;
-    r.shape = SHAPE_CIRCLE;
-    if (!push_rec(&S->dashed, &S->nd, &S->capd, r))
-        return 0;
-    return known_set(&S->known, C, K_CIRCLE);
+    const uint32_t W = S->W;
+    uint64_t *boxes = NULL, nb = 0, capb = 0;
+    int ok = 1;
+    for (uint64_t pass = 0; pass < 2 && ok; ++pass) {
+        const cand *v = pass ? S->live : S->done;
+        const uint64_t nv = pass ? S->nlive : S->ndone;
+        for (uint64_t i = 0; i < nv && ok; ++i)
+            if (v[i].reached) {
+                ok = grow((void **)&boxes, &capb, nb + 1, sizeof(uint64_t));
+                if (ok)
+                    boxes[nb++] = v[i].at;
+            }
+    }
+    for (uint64_t x = 0; x < nb && ok; ++x) {
+        const uint32_t ka = n_items(S->arena + boxes[x], W);
+        for (uint64_t y = x + 1; y < nb && ok; ++y) {
+            /* the arena may move as candidates are added: address it afresh */
+            const uint64_t *A = S->arena + boxes[x], *B = S->arena + boxes[y];
+            if (n_items(B, W) != ka)
+                continue;
+            for (uint32_t w = 0; w < W; ++w)
+                C[w] = A[w] | B[w];
+            if (n_items(C, W) != ka + 1u || known_get(&S->seen, C) != K_EMPTY ||
+                !maximal_subsets_frequent(S, C, scratch))
+                continue;
+            ok = start_candidate(S, C, ka + 1u);
+            if (ok)
+                tr->generated++;
+        }
+    }
+    free(boxes);
+    return ok;
 }
 
-static void erase_nil(rec *v, uint64_t *n)
+/* Algorithm 5: a candidate counted on every block of a pass is finished --
+ * frequent iff its count reached tau (a circle that reaches it only here is
+ * counted in the statistics; Prune promotes first, so it never happens). */
+static int retire_phase(miner *S, uint64_t tau, uint64_t nblk, or_stop *tr, or_stats *st)
 {
-    uint64_t j = 0;
-    for (uint64_t i = 0; i < *n; ++i)
-        if (v[i].shape != SHAPE_NIL)
-            v[j++] = v[i];
-    *n = j;
+    for (uint64_t i = 0; i < S->nlive; ++i) {
+        cand *c = &S->live[i];
+        if (c->blocks != nblk)
+            continue;
+        if (c->hits >= tau && !c->reached) {
+            st->fullpass_promotions++;
+            c->reached = 1;
+            if (!known_set(&S->seen, mask_of(S, c), K_BOX))
+                return 0;
+        }
+        if (!cand_push(&S->done, &S->ndone, &S->capdone, *c))
+            return 0;
+        c->gone = 1;
+        tr->solidified++;
+    }
+    sweep_live(S);
+    return 1;
 }
 
-static void dic_state_free(dic_state *S)
+static void miner_free(miner *S)
 {
     free(S->arena);
-    free(S->dashed);
-    free(S->solid);
-    known_free(&S->known);
+    free(S->live);
+    free(S->done);
+    free(S->fresh);
+    known_free(&S->seen);
+}
+
+/* The first candidates.  init_mode 0 (FirstPass, Section 4.1): one pass
+ * counts every item; each 1-itemset is finished (frequent or not) and every
+ * pair of frequent items is a candidate.  init_mode 1 (Algorithm 1): every
+ * 1-itemset is a candidate and every item may extend a box.  freq receives
+ * the items that may extend boxes, ascending. */
+static int first_candidates(miner *S, const uint64_t *rows, uint64_t n, uint32_t m,
+                            uint64_t tau, uint64_t nblk, int init_mode, uint32_t *freq,
+                            uint64_t *nfreq, uint64_t *C)
+{
+    const uint32_t W = S->W;
+    *nfreq = 0;
+    if (init_mode == 1) {
+        for (uint32_t i = 0; i < m; ++i) {
+            memset(C, 0, W * sizeof(uint64_t));
+            C[i >> 6] = 1ull << (i & 63);
+            if (!start_candidate(S, C, 1))
+                return 0;
+            freq[(*nfreq)++] = i;
+        }
+        return 1;
+    }
+    uint64_t *item_hits = (uint64_t *)calloc(m, sizeof(uint64_t));
+    if (!item_hits)
+        return 0;
+    for (uint64_t t = 0; t < n; ++t)
+        for (uint32_t i = 0; i < m; ++i)
+            item_hits[i] += (uint64_t)has_item(rows + t * W, i);
+    int ok = 1;
+    for (uint32_t i = 0; i < m && ok; ++i) {
+        memset(C, 0, W * sizeof(uint64_t));
+        C[i >> 6] = 1ull << (i & 63);
+        cand c;
+        memset(&c, 0, sizeof(c));
+        c.size = 1;
+        c.blocks = nblk;
+        c.hits = item_hits[i];
+        c.reached = item_hits[i] >= tau;
+        ok = arena_put(S, C, &c.at) && cand_push(&S->done, &S->ndone, &S->capdone, c) &&
+             known_set(&S->seen, C, c.reached ? K_BOX : K_CIRCLE);
+        if (ok && c.reached)
+            freq[(*nfreq)++] = i;
+    }
+    free(item_hits);
+    for (uint64_t a = 0; a < *nfreq && ok; ++a)
+        for (uint64_t b = a + 1; b < *nfreq && ok; ++b) {
+            memset(C, 0, W * sizeof(uint64_t));
+            C[freq[a] >> 6] |= 1ull << (freq[a] & 63);
+            C[freq[b] >> 6] |= 1ull << (freq[b] & 63);
+            ok = start_candidate(S, C, 2);
+        }
+    return ok;
 }
 
 int oracle_dic(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, uint64_t M,
@@ -376,6 +611,13 @@ int oracle_dic(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, uint
     return oracle_dic_init(rows, n, m, minsup, M, candgen_mode, 0, out);
 }
 
+/* Section 4.2 (Algorithm 2): after the first candidates, the database is
+ * read block after block -- block b holds transactions [(b-1)Mp, min(b Mp,
+ * n)), Mp = min(M, n), nblk = ceil(n / Mp) blocks, the first again after the
+ * last -- and at each stop the live candidates are counted (Algorithm 3),
+ * promoted or erased (Algorithm 4), extended (MakeCandidates) and retired
+ * after a full pass (Algorithm 5), until none is live.  The result is the
+ * finished itemsets that reached tau. */
 int oracle_dic_init(const uint64_t *rows, uint64_t n, uint32_t m, double minsup, uint64_t M,
                     int candgen_mode, int init_mode, or_result **out)
 {
@@ -392,266 +634,56 @@ int oracle_dic_init(const uint64_t *rows, uint64_t n, uint32_t m, double minsup,
         return rc;
 
     const uint32_t W = (m + 63u) / 64u;
-    const uint64_t Mp = M < n ? M : n;         /* a block never exceeds the database */
-    const uint64_t stop_max = (n + Mp - 1) / Mp; /* Algorithm 2: ceil(n / M) */
+    const uint64_t Mp = M < n ? M : n;
+    const uint64_t nblk = (n + Mp - 1) / Mp;
 
-    dic_state S;
+    miner S;
     memset(&S, 0, sizeof(S));
     S.W = W;
-    or_stop *trace = NULL;
-    uint64_t ntrace = 0, captrace = 0;
-    uint64_t *newb = NULL, nnew = 0, capnew = 0; /* arena offsets of new boxes */
-    uint32_t *L1 = NULL;
-    uint64_t nL1 = 0;
-    uint64_t *C = (uint64_t *)calloc(W, sizeof(uint64_t));
-    uint64_t *tmp = (uint64_t *)calloc(W, sizeof(uint64_t));
     or_stats st;
     memset(&st, 0, sizeof(st));
+    or_stop *trace = NULL;
+    uint64_t ntrace = 0, captrace = 0;
+    uint32_t *freq = (uint32_t *)malloc((m ? m : 1) * sizeof(uint32_t));
+    uint64_t nfreq = 0;
+    uint64_t *C = (uint64_t *)calloc(W, sizeof(uint64_t));
+    uint64_t *scratch = (uint64_t *)calloc(W, sizeof(uint64_t));
     rc = OR_E_NOMEM;
-    if (!C || !tmp || !known_init(&S.known, W, 4096))
+    if (!freq || !C || !scratch || !known_init(&S.seen, W, 4096) ||
+        !first_candidates(&S, rows, n, m, tau, nblk, init_mode, freq, &nfreq, C))
         goto done;
 
-    if (init_mode == 1) {
-        /* Algorithm 1 (classic DIC): every 1-itemset starts in Dashed Circle
-         * and is counted block by block like any candidate; no FirstPass.
-         * Every item may extend a box (its singleton's shape decides). */
-        L1 = (uint32_t *)malloc((m ? m : 1) * sizeof(uint32_t));
-        if (!L1)
-            goto done;
-        for (uint32_t i = 0; i < m; ++i) {
-            memset(C, 0, W * sizeof(uint64_t));
-            C[i >> 6] = 1ull << (i & 63);
-            if (!add_candidate(&S, C, 1))
-                goto done;
-            L1[nL1++] = i;
-        }
-        goto main_loop;
-    }
-
-    /* Algorithm 2, initialisation: every 1-itemset goes to SOLID. */
-    for (uint32_t i = 0; i < m; ++i) {
-        memset(C, 0, W * sizeof(uint64_t));
-        C[i >> 6] = 1ull << (i & 63);
-        rec r;
-        if (!new_mask(&S, C, &r.off))
-            goto done;
-        r.k = 1;
-        r.stop = 0;
-        r.supp = 0;
-        r.shape = SHAPE_NIL;
-        if (!push_rec(&S.solid, &S.ns, &S.caps, r))
-            goto done;
-    }
-
-    /* FirstPass: one full pass over the database counts every 1-itemset. */
-    {
-        uint64_t *cnt = (uint64_t *)calloc(m, sizeof(uint64_t));
-        if (!cnt)
-            goto done;
-        for (uint64_t t = 0; t < n; ++t)
-            for (uint32_t i = 0; i < m; ++i)
-                if (has_item(rows + t * W, i))
-                    cnt[i]++;
-        L1 = (uint32_t *)malloc((m ? m : 1) * sizeof(uint32_t));
-        if (!L1) {
-            free(cnt);
-            goto done;
-        }
-        for (uint32_t i = 0; i < m; ++i) {
-            rec *r = &S.solid[i];
-            r->supp = cnt[i];
-            r->stop = stop_max;
-            r->shape = cnt[i] >= tau ? SHAPE_BOX : SHAPE_CIRCLE;
-            if (!known_set(&S.known, S.arena + r->off, r->shape == SHAPE_BOX ? K_BOX : K_CIRCLE)) {
-                free(cnt);
-                goto done;
-            }
-            if (r->shape == SHAPE_BOX)
-                L1[nL1++] = i;
-        }
-        free(cnt);
-        /* candidate 2-itemsets: bitwise OR of every pair of frequent items */
-        for (uint64_t a = 0; a < nL1; ++a)
-            for (uint64_t b = a + 1; b < nL1; ++b) {
-                memset(C, 0, W * sizeof(uint64_t));
-                C[L1[a] >> 6] |= 1ull << (L1[a] & 63);
-                C[L1[b] >> 6] |= 1ull << (L1[b] & 63);
-                if (!add_candidate(&S, C, 2))
-                    goto done;
-            }
-    }
-
-main_loop:;
-    /* Algorithm 2, main loop: one iteration per stop until DASHED is empty. */
-    uint64_t stop = 0;
-    while (S.nd > 0) {
-        /* scan the next block, rewinding after the last one */
-        stop = stop + 1;
-        if (stop > stop_max)
-            stop = 1;
-        uint64_t first = (stop - 1) * Mp;
-        uint64_t last = stop * Mp < n ? stop * Mp : n; /* exclusive */
+    for (uint64_t b = 0; S.nlive > 0;) {
+        b = b % nblk + 1; /* the next block, the first again after the last */
+        const uint64_t lo = (b - 1) * Mp;
+        const uint64_t hi = b * Mp < n ? b * Mp : n;
         or_stop tr;
         memset(&tr, 0, sizeof(tr));
-        tr.stop = (uint32_t)stop;
-        tr.rows = (uint32_t)(last - first);
-        tr.live = S.nd;
+        tr.stop = (uint32_t)b;
+        tr.rows = (uint32_t)(hi - lo);
+        tr.live = S.nlive;
         st.stops++;
-        st.tests += S.nd * (last - first);
-        if (S.nd > st.peak_live)
-            st.peak_live = S.nd;
-
-        /* Algorithm 3, CountSupport: itemsets outer, transactions inner. */
-        for (uint64_t d = 0; d < S.nd; ++d) {
-            rec *I = &S.dashed[d];
-            I->stop = I->stop + 1;
-            const uint64_t *mask = S.arena + I->off;
-            for (uint64_t t = first; t < last; ++t)
-                if (is_subset(mask, rows + t * W, W))
-                    I->supp = I->supp + 1;
-        }
-
-        /* Algorithm 4, Prune: promote circles that reached the threshold;
-         * erase circles whose best possible support cannot reach it, together
-         * with every dashed-circle superset. */
-        nnew = 0;
-        uint32_t kmax_circle = 0; /* no circle of this size or less has a proper superset */
-        for (uint64_t d = 0; d < S.nd; ++d)
-            if (S.dashed[d].shape == SHAPE_CIRCLE && S.dashed[d].k > kmax_circle)
-                kmax_circle = S.dashed[d].k;
-        for (uint64_t d = 0; d < S.nd; ++d) {
-            rec *I = &S.dashed[d];
-            if (I->shape != SHAPE_CIRCLE)
-                continue;
-            if (I->supp >= tau) {
-                I->shape = SHAPE_BOX;
-                tr.promoted++;
-                if (!known_set(&S.known, S.arena + I->off, K_BOX))
-                    goto done;
-                if (!grow((void **)&newb, &capnew, nnew + 1, sizeof(uint64_t)))
-                    goto done;
-                newb[nnew++] = I->off;
-            } else {
-                uint64_t supp_max = I->supp + Mp * (stop_max - I->stop);
-                if (supp_max < tau) {
-                    I->shape = SHAPE_NIL;
-                    tr.pruned++;
-                    if (!known_set(&S.known, S.arena + I->off, K_INFREQUENT))
-                        goto done;
-                    for (uint64_t e = 0; I->k < kmax_circle && e < S.nd; ++e) {
-                        rec *J = &S.dashed[e];
-                        /* only a strictly larger itemset can be a proper superset */
-                        if (e != d && J->shape == SHAPE_CIRCLE && J->k > I->k &&
-                            is_subset(S.arena + I->off, S.arena + J->off, W)) {
-                            J->shape = SHAPE_NIL;
-                            st.superset_prunes++;
-                            tr.pruned++;
-                            if (!known_set(&S.known, S.arena + J->off, K_INFREQUENT))
-                                goto done;
-                        }
-                    }
-                }
-            }
-        }
-        erase_nil(S.dashed, &S.nd);
-
-        /* MakeCandidates: join of boxes by bitwise OR.  A candidate C is
-         * admitted when it is new and all its maximal proper subsets are
-         * boxes. */
-        if (candgen_mode == 0) {
-            for (uint64_t q = 0; q < nnew; ++q) {
-                uint32_t ks = 0;
-                for (uint64_t a = 0; a < nL1; ++a) {
-                    memcpy(C, S.arena + newb[q], W * sizeof(uint64_t));
-                    if (a == 0)
-                        ks = n_items(C, W);
-                    uint32_t i = L1[a];
-                    if (has_item(C, i))
-                        continue;
-                    C[i >> 6] |= 1ull << (i & 63);
-                    if (known_get(&S.known, C) != K_EMPTY)
-                        continue;
-                    if (!all_subsets_boxes(&S, C, tmp))
-                        continue;
-                    if (!add_candidate(&S, C, ks + 1))
-                        goto done;
-                    tr.generated++;
-                }
-            }
-        } else {
-            /* gather every box (solid first, then dashed) and OR all pairs */
-            uint64_t *boxes = NULL, nb = 0, capb = 0;
-            for (uint64_t i = 0; i < S.ns; ++i)
-                if (S.solid[i].shape == SHAPE_BOX) {
-                    if (!grow((void **)&boxes, &capb, nb + 1, sizeof(uint64_t))) {
-                        free(boxes);
-                        goto done;
-                    }
-                    boxes[nb++] = S.solid[i].off;
-                }
-            for (uint64_t i = 0; i < S.nd; ++i)
-                if (S.dashed[i].shape == SHAPE_BOX) {
-                    if (!grow((void **)&boxes, &capb, nb + 1, sizeof(uint64_t))) {
-                        free(boxes);
-                        goto done;
-                    }
-                    boxes[nb++] = S.dashed[i].off;
-                }
-            for (uint64_t a = 0; a < nb; ++a) {
-                uint32_t ka = n_items(S.arena + boxes[a], W);
-                for (uint64_t b = a + 1; b < nb; ++b) {
-                    const uint64_t *A = S.arena + boxes[a], *B = S.arena + boxes[b];
-                    if (n_items(B, W) != ka)
-                        continue;
-                    for (uint32_t w = 0; w < W; ++w)
-                        C[w] = A[w] | B[w];
-                    if (n_items(C, W) != ka + 1)
-                        continue;
-                    if (known_get(&S.known, C) != K_EMPTY)
-                        continue;
-                    if (!all_subsets_boxes(&S, C, tmp))
-                        continue;
-                    if (!add_candidate(&S, C, ka + 1)) {
-                        free(boxes);
-                        goto done;
-                    }
-                    tr.generated++;
-                }
-            }
-            free(boxes);
-        }
-
-        /* Algorithm 5, CheckFullPass: itemsets counted over a full pass
-         * become solid; a box if their support reached the threshold. */
-        for (uint64_t d = 0; d < S.nd; ++d) {
-            rec *I = &S.dashed[d];
-            if (I->stop == stop_max) {
-                if (I->supp >= tau) {
-                    if (I->shape == SHAPE_CIRCLE) {
-                        st.fullpass_promotions++;
-                        if (!known_set(&S.known, S.arena + I->off, K_BOX))
-                            goto done;
-                    }
-                    I->shape = SHAPE_BOX;
-                }
-                if (!push_rec(&S.solid, &S.ns, &S.caps, *I))
-                    goto done;
-                I->shape = SHAPE_NIL;
-                tr.solidified++;
-            }
-        }
-        erase_nil(S.dashed, &S.nd);
-
+        st.tests += S.nlive * (hi - lo);
+        if (S.nlive > st.peak_live)
+            st.peak_live = S.nlive;
+        count_block_phase(&S, rows, lo, hi);
+        if (!threshold_phase(&S, tau, Mp, nblk, &tr, &st))
+            goto done;
+        if (!(candgen_mode == 0 ? extend_fresh_phase(&S, freq, nfreq, C, scratch, &tr)
+                                : extend_pairs_phase(&S, C, scratch, &tr)))
+            goto done;
+        if (!retire_phase(&S, tau, nblk, &tr, &st))
+            goto done;
         if (!grow((void **)&trace, &captrace, ntrace + 1, sizeof(or_stop)))
             goto done;
         trace[ntrace++] = tr;
     }
 
-    /* L = the boxes in SOLID */
+    /* the result: the finished itemsets that reached tau */
     {
         uint64_t q = 0;
-        for (uint64_t i = 0; i < S.ns; ++i)
-            q += S.solid[i].shape == SHAPE_BOX;
+        for (uint64_t i = 0; i < S.ndone; ++i)
+            q += S.done[i].reached;
         uint64_t *masks = (uint64_t *)malloc((q ? q : 1) * W * sizeof(uint64_t));
         uint32_t *counts = (uint32_t *)malloc((q ? q : 1) * sizeof(uint32_t));
         if (!masks || !counts) {
@@ -660,10 +692,10 @@ main_loop:;
             goto done;
         }
         q = 0;
-        for (uint64_t i = 0; i < S.ns; ++i)
-            if (S.solid[i].shape == SHAPE_BOX) {
-                memcpy(masks + q * W, S.arena + S.solid[i].off, W * sizeof(uint64_t));
-                counts[q] = (uint32_t)S.solid[i].supp;
+        for (uint64_t i = 0; i < S.ndone; ++i)
+            if (S.done[i].reached) {
+                memcpy(masks + q * W, mask_of(&S, &S.done[i]), W * sizeof(uint64_t));
+                counts[q] = (uint32_t)S.done[i].hits;
                 q++;
             }
         or_result *r = NULL;
@@ -676,8 +708,8 @@ main_loop:;
         st.k_max = r->stats.k_max;
         st.tau = tau;
         st.block = Mp;
-        st.stop_max = stop_max;
-        st.known = S.known.used;
+        st.stop_max = nblk;
+        st.known = S.seen.used;
         r->stats = st;
         r->trace = trace;
         r->trace_len = ntrace;
@@ -688,11 +720,10 @@ main_loop:;
 
 done:
     free(trace);
-    free(newb);
-    free(L1);
+    free(freq);
     free(C);
-    free(tmp);
-    dic_state_free(&S);
+    free(scratch);
+    miner_free(&S);
     return rc;
 }
 

@@ -60,6 +60,10 @@ typedef struct or_result or_result;
 /* Integer threshold from a fractional minsup (see oracle_dic). */
 int oracle_tau(double minsup, uint64_t n, uint64_t *tau);
 
+/* Threads of the count loop when built with OpenMP (threads <= 0: keep the
+ * current setting); returns the number in use (1 in a serial build). */
+int oracle_threads(int threads);
+
 /*
  * Dynamic Itemset Counting, ParallelDIC driver (Algorithm 2) run serially.
  * candgen_mode 0: candidates are S + {i} for each newly promoted box S and
