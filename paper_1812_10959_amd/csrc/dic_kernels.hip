@@ -692,6 +692,11 @@ __device__ __forceinline__ void settle_job(const Job *J, bool finish, bool begin
         __builtin_memcpy(stp, &s, sizeof(JobState));
 }
 
+// s_waitcnt operand (gfx9 encoding) that waits for every outstanding vector
+// memory operation of the wave -- loads, stores and atomics -- and for
+// nothing else: vmcnt 0, expcnt 7, lgkmcnt 15.
+constexpr int WAIT_VM0 = 0x0F70;
+
 // Arrival counter of a launch, called by one thread per workgroup after the
 // workgroup's work: true for the workgroup that arrives last.  Only the
 // first n workgroups arrive (n = min(grid, work items), at least 1: the
@@ -1850,6 +1855,17 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
             survivors_stop(jobs + j, v - plan->pre_countv[j], tile, sh_app, sh_red);
         }
     }
+    // Everything the serial part reads from this launch's other workgroups
+    // is a device-scope atomic (pool_n, k_next/n_new, max_rem, asserts) and
+    // is read with device-scope atomic loads.  The returning ones have
+    // completed before their results were used; the no-return ones (max_rem,
+    // asserts) are waited for here, in every wave, so that all of this
+    // workgroup's updates are done before its arrival is counted (a
+    // workgroup barrier alone does not wait for memory operations).  Plain
+    // stores of this launch (records, standings, counts) are read only by
+    // later launches.  A full device-scope release would also write back
+    // this XCD's L2, which costs tens of microseconds per launch.
+    __builtin_amdgcn_s_waitcnt(WAIT_VM0);
     __syncthreads();
     if (threadIdx.x == 0)
         sh_flag = arrive_last(plan->tickets, total < gridDim.x ? (total ? (uint32_t)total : 1u)
