@@ -262,14 +262,31 @@ DIC_API int dic_serve_poll(dic_server *srv, uint64_t ticket, dic_result **out);
 DIC_API int dic_serve_wait(dic_server *srv, uint64_t ticket, int64_t timeout_ms, dic_result **out);
 /* Latency percentiles (submit to completion, ms) and completed requests/s. */
 DIC_API int dic_serve_stats(dic_server *srv, double *p50_ms, double *p99_ms, double *throughput_rps);
+/* Device memory charged against the budget now, the most ever charged, and
+ * the budget itself (any pointer may be NULL).  The charge is each admitted
+ * request's bound plus, once, each database an admitted request uses; a
+ * request whose candidate pool overflows is charged its larger bound before
+ * it runs again, so *peak never exceeds *budget. */
+DIC_API int dic_serve_usage(dic_server *srv, uint64_t *used, uint64_t *peak, uint64_t *budget);
 /* Waits for running work, drops queued requests, frees the server. */
 DIC_API int dic_serve_destroy(dic_server *srv);
 
 /*
- * Route the library's device allocations and work: alloc(size, stream)
- * returns device memory or NULL, free(ptr, stream) releases it, stream is a
- * hipStream_t (NULL: the library's own stream).  Pass NULL functions to
- * return to hipMalloc/hipFree.  Call before loading databases.
+ * Route the library's device allocations through the caller's allocator:
+ * alloc(size, stream) returns device memory or NULL, free(ptr, stream)
+ * releases a block; both are given `stream` (a hipStream_t, or NULL) as
+ * passed here, so an allocator may tie its blocks to it.  A NULL from alloc
+ * fails the call that needed the memory with DIC_E_NOMEM, after it has
+ * released what it had taken.  Every block goes back to the functions that
+ * allocated it, also after they have been replaced.  Pass NULL functions to
+ * return to the library's own hipMalloc-backed cache.
+ *
+ * Streams: database loads (dic_load_db*) and dic_rules run on `stream` when
+ * it is not NULL (else on a library stream).  Mining (dic_mine, dic_batch,
+ * serving) runs on streams private to the library's engines -- a stop chunk
+ * is captured into a HIP graph, which needs a stream no other thread uses --
+ * and every call that hands back results has completed its device work, so
+ * no block is freed while a kernel may still use it.
  */
 DIC_API int dic_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(void *, void *),
                       void *stream);

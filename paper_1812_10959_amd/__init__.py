@@ -8,9 +8,11 @@ fails loudly when ``libdic.so`` has not been built
 (``python paper_1812_10959_amd/build.py``).
 
 PyTorch is optional plumbing: ``use_torch()`` routes the library's device
-allocations through torch's caching allocator and its work onto torch's
-current stream, and ``dic_load_db`` accepts a CUDA/HIP tensor of uint64 (or
-int64) rows already on the device.
+allocations through torch's caching allocator (blocks tied to torch's
+current stream, on which database loads and rule generation also run; the
+mining itself runs on the library's private engine streams and is complete
+when a call returns), and ``dic_load_db`` accepts a CUDA/HIP tensor of
+uint64 (or int64) rows already on the device.
 """
 from __future__ import annotations
 
@@ -50,7 +52,7 @@ ABI_FUNCTIONS = (
     "dic_free_db", "dic_mine", "dic_mine_noalloc", "dic_batch", "dic_result_size", "dic_result_words",
     "dic_result_masks", "dic_result_counts", "dic_result_stats", "dic_result_trace",
     "dic_result_free", "dic_serve_create", "dic_serve_submit", "dic_serve_poll",
-    "dic_serve_wait", "dic_serve_stats", "dic_serve_destroy", "dic_set_allocator",
+    "dic_serve_wait", "dic_serve_stats", "dic_serve_usage", "dic_serve_destroy", "dic_set_allocator",
     "dic_set_option", "dic_last_error", "dic_rules", "dic_rules_from_arrays", "dic_rules_size",
     "dic_rules_words", "dic_rules_itemset", "dic_rules_code", "dic_rules_supp_x",
     "dic_rules_antecedent", "dic_rules_consequent", "dic_rules_stats_of", "dic_rules_free",
@@ -118,6 +120,8 @@ _sig = {
     "dic_serve_wait": ([_p, _u64, _i64, _pp], ctypes.c_int),
     "dic_serve_stats": ([_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                          ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "dic_serve_usage": ([_p, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)],
+                        ctypes.c_int),
     "dic_serve_destroy": ([_p], ctypes.c_int),
     "dic_set_allocator": ([_ALLOC_T, _FREE_T, _p], ctypes.c_int),
     "dic_set_option": ([ctypes.c_char_p, _i64], ctypes.c_int),
@@ -415,6 +419,14 @@ def dic_serve_stats(srv: Server):
     return a.value, b.value, c.value
 
 
+def dic_serve_usage(srv: Server):
+    """(bytes charged now, most ever charged, budget)."""
+    u, p, b = _u64(), _u64(), _u64()
+    _check(_lib.dic_serve_usage(srv.handle, ctypes.byref(u), ctypes.byref(p), ctypes.byref(b)),
+           "dic_serve_usage")
+    return u.value, p.value, b.value
+
+
 def dic_serve_destroy(srv: Server) -> None:
     if srv.handle:
         _check(_lib.dic_serve_destroy(srv.handle), "dic_serve_destroy")
@@ -432,13 +444,17 @@ def dic_set_allocator(alloc=None, free=None, stream: int | None = None) -> None:
     hipMalloc/hipFree."""
     a = _ALLOC_T(alloc) if alloc else _ALLOC_T()
     f = _FREE_T(free) if free else _FREE_T()
-    _keep[:] = [a, f]
+    # every pair stays alive: blocks still go back to the free function that
+    # came with their allocator after it has been replaced
+    _keep.extend([a, f])
     _check(_lib.dic_set_allocator(a, f, stream or None), "dic_set_allocator")
 
 
 def use_torch(stream=None) -> None:
-    """Route device memory through torch's caching allocator and work onto a
-    torch stream (default: the current stream)."""
+    """Route the library's device memory through torch's caching allocator,
+    with blocks tied to a torch stream (default: the current stream).  Database
+    loads and dic_rules run on that stream; mining runs on the library's own
+    engine streams and has finished when its call returns."""
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
 

@@ -27,6 +27,10 @@ uint64_t db_n(dic_db *db) { return db->n; }
 uint32_t db_m(dic_db *db) { return db->m; }
 uint32_t db_W(dic_db *db) { return db->W; }
 void db_ref(dic_db *db, int delta) { db->refs += delta; }
+uint64_t db_bytes(dic_db *db)
+{
+    return alloc_bytes(8ull * db->n * db->W) + alloc_bytes(8ull * db->m * db->nw);
+}
 std::mutex &db_mutex(dic_db *db) { return db->mu; }
 
 namespace {
@@ -38,6 +42,14 @@ void *(*g_alloc)(size_t, void *) = nullptr;
 void (*g_free)(void *, void *) = nullptr;
 void *g_user_stream = nullptr;
 hipStream_t g_stream = nullptr;
+// Blocks from a caller's allocator, each with the free function and stream
+// it came with: a block goes back to the allocator that made it even after
+// the allocator was changed (engines are pooled and outlive such changes).
+struct UserBlock {
+    void (*free_fn)(void *, void *);
+    void *stream;
+};
+std::map<void *, UserBlock> g_user_blocks;
 
 // Small caching allocator over hipMalloc: freed blocks are kept by size and
 // handed out again to requests that fit (a mining run allocates and frees
@@ -48,12 +60,7 @@ std::map<void *, size_t> g_sizes;
 size_t g_cached_bytes = 0;
 constexpr size_t CACHE_LIMIT = 32ull << 30;
 
-size_t round_size(size_t b)
-{
-    if (b <= (1u << 20))
-        return (b + 4095) & ~(size_t)4095;
-    return (b + (2u << 20) - 1) & ~(size_t)((2u << 20) - 1);
-}
+size_t round_size(size_t b) { return (size_t)alloc_bytes(b); }
 
 }  // namespace
 
@@ -61,10 +68,20 @@ void set_error(const std::string &msg) { t_err = msg; }
 
 void *dev_alloc(size_t bytes)
 {
+    void *(*alloc)(size_t, void *) = nullptr;
+    UserBlock ub{};
     {
         std::lock_guard<std::mutex> g(g_cfg_mu);
-        if (g_alloc)
-            return g_alloc(bytes, g_user_stream);
+        alloc = g_alloc;
+        ub = UserBlock{g_free, g_user_stream};
+    }
+    if (alloc) {  // the caller's functions run without the library's locks held
+        void *p = alloc(bytes, ub.stream);
+        if (p) {
+            std::lock_guard<std::mutex> g(g_cfg_mu);
+            g_user_blocks[p] = ub;
+        }
+        return p;
     }
     const size_t r = round_size(bytes);
     {
@@ -102,12 +119,18 @@ void dev_free(void *p)
 {
     if (!p)
         return;
+    UserBlock ub{};
     {
         std::lock_guard<std::mutex> g(g_cfg_mu);
-        if (g_free) {
-            g_free(p, g_user_stream);
-            return;
+        auto u = g_user_blocks.find(p);
+        if (u != g_user_blocks.end()) {
+            ub = u->second;
+            g_user_blocks.erase(u);
         }
+    }
+    if (ub.free_fn) {
+        ub.free_fn(p, ub.stream);
+        return;
     }
     std::lock_guard<std::mutex> g(g_cache_mu);
     auto it = g_sizes.find(p);

@@ -123,14 +123,25 @@ bool threshold(double minsup, uint64_t n, uint64_t *tau)
     return true;
 }
 
-uint64_t job_bytes(uint32_t m, uint64_t cap, uint32_t trace_cap)
+uint64_t trace_bound(uint64_t n, uint64_t M, uint64_t cap)
 {
-    const uint32_t W = (m + 63u) / 64u;
-    return PoolLayout(cap, W).bytes + 3ull * m * 4 + 1024 +
-           (uint64_t)trace_cap * sizeof(dic_stop_trace);
+    const uint64_t Mp = std::max<uint64_t>(1, std::min(M, n));
+    const uint64_t stop_max = (n + Mp - 1) / Mp;
+    uint32_t lg = 0;
+    while (lg < 63 && (2ull << lg) <= cap)
+        ++lg;
+    return std::min<uint64_t>((lg + 3ull) * (stop_max + 1) + 2, 0x7FFFFFFFull);
 }
 
-uint64_t job_bytes_bound(uint32_t m) { return job_bytes(m, pool_cap_for(m, 1), TRACE_INIT); }
+uint64_t job_bytes_bound(uint32_t m, uint64_t n, uint64_t M, uint32_t mult)
+{
+    const uint32_t W = (m + 63u) / 64u;
+    const uint64_t nw = (n + 63) / 64;
+    const uint64_t cap = pool_cap_for(m, mult);
+    const uint64_t tr = std::max<uint64_t>(TRACE_INIT, trace_bound(n, M, cap));
+    return alloc_bytes(PoolLayout(cap, W).bytes) + alloc_bytes(12ull * m + 768) +
+           alloc_bytes(8ull * m * nw) + 2 * alloc_bytes(tr * sizeof(dic_stop_trace));
+}
 
 // ---------------------------------------------------------------------------
 // per-job host record
@@ -279,15 +290,6 @@ bool Engine::running() const
     return false;
 }
 
-uint64_t Engine::job_bytes_of(uint64_t id) const
-{
-    for (ActiveJob *j : jobs_)
-        if (j->id == id)
-            return job_bytes(j->req.m, j->cap ? j->cap : pool_cap_for(j->req.m, j->mult),
-                             j->trace_cap);
-    return 0;
-}
-
 int Engine::read_states()
 {
     int hi = -1;
@@ -314,6 +316,10 @@ int Engine::add(const std::vector<MineRequest> &reqs, const std::vector<uint64_t
         ActiveJob *a = new ActiveJob;
         a->id = ids[i];
         a->req = reqs[i];
+        a->mult = std::max(1u, reqs[i].mult);
+        a->restarts = reqs[i].restarts;
+        a->count_ms = reqs[i].count_ms;
+        a->count_launches = reqs[i].count_launches;
         a->t0 = now;
         a->layout = reqs[i].vert ? layout : LAYOUT_ROWS;
         a->classic = classic;
@@ -572,9 +578,16 @@ int Engine::ensure_trace(uint32_t steps)
         const uint32_t epoch = st_[a->slot].epoch;
         if (epoch + steps <= a->trace_cap)
             continue;
-        uint32_t nc = a->trace_cap;
+        // no run takes more stops than trace_bound: the kernels write no
+        // entry at or beyond trace_cap, and collection checks the count
+        const uint64_t most = std::max<uint64_t>(
+            TRACE_INIT, trace_bound(a->req.n, a->req.M, a->cap ? a->cap : pool_cap_for(a->nL1, a->mult)));
+        if (a->trace_cap >= most)
+            continue;
+        uint64_t nc = a->trace_cap;
         while (nc < epoch + steps)
             nc *= 2;
+        nc = std::min(nc, most);
         void *nb = dev_alloc(sizeof(dic_stop_trace) * nc);
         if (!nb) {
             set_error("device allocation failed (trace)");
@@ -585,9 +598,9 @@ int Engine::ensure_trace(uint32_t steps)
         HIP_TRY(hipStreamSynchronize(s_));
         dev_free(a->trace);
         a->trace = nb;
-        a->trace_cap = nc;
+        a->trace_cap = (uint32_t)nc;
         a->job.trace = (dic_stop_trace *)nb;
-        a->job.trace_cap = nc;
+        a->job.trace_cap = (uint32_t)nc;
         table_dirty_ = true;
     }
     return DIC_OK;
@@ -824,6 +837,10 @@ int Engine::collect(std::vector<ActiveJob *> &fin,
         S.count_ms = a->count_ms;
         S.count_launches = a->count_launches;
         o.status = s.asserts ? DIC_E_DEVICE : DIC_OK;
+        if (s.stops > a->trace_cap) {
+            o.status = DIC_E_DEVICE;
+            set_error("the run took more stops than its trace can hold");
+        }
         out.emplace_back(a->id, std::move(o));
     }
     return DIC_OK;
@@ -860,10 +877,23 @@ int Engine::harvest(std::vector<std::pair<uint64_t, MineOutput>> &done)
             delete a;
         return rc;
     }
-    // rerun overflowed jobs with four times the candidate room
+    // rerun overflowed jobs with four times the candidate room (requeue
+    // mode: hand them back to be added again once the room is granted)
     std::vector<ActiveJob *> again;
     for (ActiveJob *a : over) {
         free_slots_.push_back(a->slot);
+        if (requeue_ && a->restarts < MAX_RESTARTS) {
+            MineOutput o;
+            o.requeue = true;
+            o.again = a->req;
+            o.again.mult = a->mult * 4;
+            o.again.restarts = a->restarts + 1;
+            o.again.count_ms = a->count_ms;
+            o.again.count_launches = a->count_launches;
+            done.emplace_back(a->id, std::move(o));
+            delete a;
+            continue;
+        }
         if (a->restarts >= MAX_RESTARTS) {
             MineOutput o;
             o.status = DIC_E_NOMEM;

@@ -377,6 +377,11 @@ struct MineRequest {
     uint32_t n, m;
     double minsup;
     uint64_t M;
+    // a rerun after candidate-pool overflows: the pool multiplier, the
+    // restarts so far and the count time of the earlier attempts
+    uint32_t mult = 1, restarts = 0;
+    double count_ms = 0;
+    uint64_t count_launches = 0;
 };
 
 struct MineOutput {
@@ -385,6 +390,10 @@ struct MineOutput {
     std::vector<uint32_t> counts;
     std::vector<dic_stop_trace> trace;
     dic_stats stats{};
+    // an engine in requeue mode hands an overflowed job back instead of
+    // rerunning it: `again` is the request to add once its memory is granted
+    bool requeue = false;
+    MineRequest again{};
 };
 
 // Compute tau from minsup; returns false on invalid minsup.
@@ -397,11 +406,25 @@ int run_jobs(const std::vector<MineRequest> &reqs, std::vector<MineOutput> &outs
 bool use_graphs();
 void set_use_graphs(bool on);
 
-// Device bytes of a job's working memory for a given candidate capacity.
-uint64_t job_bytes(uint32_t m, uint64_t cap, uint32_t trace_cap);
-// Upper bound of a job's working memory before its first pass (every item
-// frequent), used for admission.
-uint64_t job_bytes_bound(uint32_t m);
+// Bytes the library's allocator sets aside for a request of b bytes.
+inline uint64_t alloc_bytes(uint64_t b)
+{
+    if (b <= (1u << 20))
+        return (b + 4095) & ~(uint64_t)4095;
+    return (b + (2u << 20) - 1) & ~(uint64_t)((2u << 20) - 1);
+}
+// Most stops a run can take: a candidate is counted for one full pass
+// (stop_max stops); a candidate of size k+1 is made at the latest one stop
+// after its last k-subset ends its pass, so size-k candidates are done
+// within k * (stop_max + 1) stops; and a candidate of size k has all its
+// 2^k - 2 proper nonempty subsets frequent, those of size >= 2 (all of them
+// in the classic start) in the pool with it, so k <= log2(cap) + 1.
+uint64_t trace_bound(uint64_t n, uint64_t M, uint64_t cap);
+// Upper bound of a job's device memory before its first pass (every item
+// frequent), for a pool of pool_cap_for(m, mult): the pool, the per-item
+// records, the frequent items' bitsets and the trace at its largest (twice:
+// the old and new buffer while it grows), each as the allocator rounds it.
+uint64_t job_bytes_bound(uint32_t m, uint64_t n, uint64_t M, uint32_t mult);
 
 bool profiling();
 void set_profiling(int on);
@@ -416,7 +439,8 @@ struct ActiveJob;
 // step chunks (their first pass runs at once); every advance() runs up to
 // max_steps stops for all unfinished jobs with one launch per kernel per
 // stop; harvest() hands back finished jobs and releases their memory.  A
-// job whose candidate pool overflowed is restarted with four times the room.
+// job whose candidate pool overflowed is restarted with four times the room
+// (or handed back for that, in requeue mode).
 // Not thread-safe: one owner thread.
 class Engine {
   public:
@@ -432,7 +456,10 @@ class Engine {
     int harvest(std::vector<std::pair<uint64_t, MineOutput>> &done);
     size_t size() const { return jobs_.size(); }
     bool running() const;
-    uint64_t job_bytes_of(uint64_t id) const;
+    // Requeue mode (serving): harvest hands an overflowed job back with
+    // MineOutput::requeue set instead of rerunning it with a larger pool,
+    // so that its owner can grant the larger memory first.
+    void set_requeue(bool on) { requeue_ = on; }
 
   private:
     int add_internal(std::vector<ActiveJob *> &fresh);
@@ -465,6 +492,7 @@ class Engine {
     void *pinned_ = nullptr;  // pinned host staging of finished jobs' outputs
     size_t pinned_cap_ = 0;
     bool table_dirty_ = true;
+    bool requeue_ = false;
     std::vector<hipEvent_t> events_;
 };
 

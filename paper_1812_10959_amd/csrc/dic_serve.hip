@@ -7,6 +7,15 @@
 // together a few stops at a time (one launch per kernel per stop for all of
 // them), so requests that arrive while others are running join at the next
 // stop chunk.  Finished requests free their slot and budget at once.
+//
+// The budget counts device memory: each admitted request's bound
+// (job_bytes_bound: pool, per-item records, frequent-item bitsets, trace)
+// and, once while any admitted request uses it, each database's resident
+// rows and bitsets.  A request whose candidate pool overflows gives its
+// memory back and goes to the head of the queue with the bound of the four
+// times larger pool; it runs again when that fits, and fails with
+// DIC_E_CAPACITY if it can never fit.  The engine's own tables (a few MB,
+// allocated once) are not counted.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -29,6 +38,7 @@ uint64_t db_n(dic_db *db);
 uint32_t db_m(dic_db *db);
 uint32_t db_W(dic_db *db);
 void db_ref(dic_db *db, int delta);
+uint64_t db_bytes(dic_db *db);
 }  // namespace dic
 
 namespace {
@@ -44,10 +54,12 @@ struct Req {
     dic_db *db;
     double minsup;
     uint64_t M;
-    uint64_t bytes;  // budget charged while admitted
+    uint64_t bytes;  // budget charged while admitted (without the database)
+    MineRequest again{};  // after a pool overflow: the rerun (again.mult > 1)
     clk::time_point submit;
     bool admitted = false, done = false;
     int status = DIC_OK;
+    std::string error;
     MineOutput out;
 };
 
@@ -61,7 +73,8 @@ struct dic_server {
     std::deque<uint64_t> queue;
     std::map<uint64_t, std::unique_ptr<Req>> reqs;
     uint64_t next_ticket = 1;
-    uint64_t used = 0;
+    uint64_t used = 0, peak = 0;
+    std::map<dic_db *, uint32_t> resident;  // databases of admitted requests
     uint32_t active = 0;
     bool stopping = false;
     std::vector<double> lat_ms;
@@ -73,24 +86,49 @@ struct dic_server {
 
 namespace {
 
-void finish(dic_server *S, Req *r, int status, MineOutput &&o)
+// Budget a request needs to be admitted now (its database counts once).
+uint64_t need_of(dic_server *S, const Req *r)
 {
-    // called with S->mu held
+    return r->bytes + (S->resident.count(r->db) ? 0 : db_bytes(r->db));
+}
+
+// Give an admitted request's memory back (called with S->mu held).
+void release(dic_server *S, Req *r)
+{
+    S->used -= r->bytes;
+    auto it = S->resident.find(r->db);
+    if (--it->second == 0) {
+        S->used -= db_bytes(r->db);
+        S->resident.erase(it);
+    }
+    S->active--;
+    r->admitted = false;
+}
+
+// Hand a request's outcome over (called with S->mu held; the request holds
+// no budget any more).
+void complete(dic_server *S, Req *r, int status, MineOutput &&o)
+{
     r->status = status;
     r->out = std::move(o);
     r->done = true;
-    S->used -= r->bytes;
-    S->active--;
     db_ref(r->db, -1);
     const auto now = clk::now();
     S->lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->submit).count());
     S->last_done = now;
 }
 
+void finish(dic_server *S, Req *r, int status, MineOutput &&o)
+{
+    release(S, r);
+    complete(S, r, status, std::move(o));
+}
+
 void worker_main(dic_server *S)
 {
     (void)hipSetDevice(S->device);
     Engine eng(nullptr, S->max_active);  // its own stream: step graphs can be captured
+    eng.set_requeue(true);  // overflowed requests come back through admission
     std::vector<std::pair<uint64_t, MineOutput>> done;
     for (;;) {
         std::vector<MineRequest> add;
@@ -101,14 +139,21 @@ void worker_main(dic_server *S)
                 // admit from the head of the queue while slots and budget allow
                 while (!S->queue.empty() && S->active < S->max_active) {
                     Req *r = S->reqs[S->queue.front()].get();
-                    if (S->used + r->bytes > S->budget)
+                    const uint64_t need = need_of(S, r);
+                    if (S->used + need > S->budget)
                         break;
                     S->queue.pop_front();
                     r->admitted = true;
-                    S->used += r->bytes;
+                    S->used += need;
+                    S->resident[r->db]++;
+                    S->peak = std::max(S->peak, S->used);
                     S->active++;
-                    add.push_back({db_rows(r->db), db_vert(r->db), (uint32_t)db_n(r->db),
-                                   db_m(r->db), r->minsup, r->M});
+                    if (r->again.mult > 1) {
+                        add.push_back(r->again);
+                    } else {
+                        add.push_back({db_rows(r->db), db_vert(r->db), (uint32_t)db_n(r->db),
+                                       db_m(r->db), r->minsup, r->M});
+                    }
                     ids.push_back(r->ticket);
                 }
                 if (!add.empty() || eng.size() > 0)
@@ -136,10 +181,32 @@ void worker_main(dic_server *S)
             if (!rc)
                 rc = eng.harvest(done);
             std::lock_guard<std::mutex> g(S->mu);
-            for (auto &d : done)
-                finish(S, S->reqs[d.first].get(), d.second.status, std::move(d.second));
-            if (!done.empty())
+            bool any_done = false;
+            for (auto &d : done) {
+                Req *r = S->reqs[d.first].get();
+                if (!d.second.requeue) {
+                    finish(S, r, d.second.status, std::move(d.second));
+                    any_done = true;
+                    continue;
+                }
+                // pool overflow: back to the head of the queue with the
+                // larger pool's bound, or fail if that can never fit
+                release(S, r);
+                r->again = d.second.again;
+                r->bytes = job_bytes_bound(db_m(r->db), db_n(r->db), r->M, r->again.mult);
+                if (r->bytes + db_bytes(r->db) > S->budget) {
+                    r->error = "the request's candidate pool outgrew the budget";
+                    MineOutput o;
+                    complete(S, r, DIC_E_CAPACITY, std::move(o));
+                    any_done = true;
+                } else {
+                    S->queue.push_front(r->ticket);
+                }
+            }
+            if (any_done)
                 S->cv_done.notify_all();
+            if (!done.empty())
+                S->cv_work.notify_one();
             if (rc) {
                 // a device error: fail everything still in the engine and stop
                 // using it; queued requests fail the same way, later submits too
@@ -182,7 +249,7 @@ int take(dic_server *S, uint64_t ticket, dic_result **out, std::unique_lock<std:
             *out = res;
         }
     } else {
-        set_error("request failed");
+        set_error(r->error.empty() ? std::string("request failed") : r->error);
     }
     S->reqs.erase(it);
     return rc;
@@ -228,13 +295,13 @@ int dic_serve_submit(dic_server *S, dic_db *db, double minsup, uint64_t M, uint6
         set_error("dic_serve_submit: bad argument");
         return DIC_E_INVAL;
     }
-    const uint64_t bytes = job_bytes_bound(db_m(db));
+    const uint64_t bytes = job_bytes_bound(db_m(db), db_n(db), M, 1);
     std::lock_guard<std::mutex> g(S->mu);
     if (S->stopping) {
         set_error("dic_serve_submit: server is shutting down");
         return DIC_E_INVAL;
     }
-    if (bytes > S->budget) {
+    if (bytes + db_bytes(db) > S->budget) {
         set_error("dic_serve_submit: the request's memory bound exceeds the budget");
         return DIC_E_CAPACITY;
     }
@@ -327,6 +394,22 @@ int dic_serve_stats(dic_server *S, double *p50_ms, double *p99_ms, double *throu
                                       .count();
         *throughput_rps = secs > 0 ? (double)v.size() / secs : 0.0;
     }
+    return DIC_OK;
+}
+
+int dic_serve_usage(dic_server *S, uint64_t *used, uint64_t *peak, uint64_t *budget)
+{
+    if (!S) {
+        set_error("dic_serve_usage: server is NULL");
+        return DIC_E_INVAL;
+    }
+    std::lock_guard<std::mutex> g(S->mu);
+    if (used)
+        *used = S->used;
+    if (peak)
+        *peak = S->peak;
+    if (budget)
+        *budget = S->budget;
     return DIC_OK;
 }
 
