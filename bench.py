@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--cpu-rows", type=int, default=40_000)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the parallel CPU oracle on the whole headline workload "
+                         "(0: min(16, CPUs available); -1: skip it)")
     ap.add_argument("--no-layouts", action="store_true",
                     help="skip the profiled count-kernel passes (for counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -157,7 +160,7 @@ def headline(dic, args, c):
     value = tests * args.steps / dt / 1e9
     log(f"  timed {args.steps} steps: {dt / args.steps * 1e3:.2f} ms/step, {value:.1f} G tests/s")
     out = {"value": value, "ms_per_step": dt / args.steps * 1e3, "stats": st,
-           "workload": c, "db": db, "rows": rows}
+           "workload": c, "db": db, "rows": rows, "result": res[0]}
     if args.calibrate_copy:
         t = torch.from_numpy(rows.view(np.int64)).cuda()
         torch.cuda.synchronize()
@@ -200,7 +203,12 @@ def headline(dic, args, c):
     return out
 
 
-def cpu_baseline(c, rows_full, n_rows):
+def cpu_baseline(c, rows_full, n_rows, threads, gpu_result):
+    """The CPU oracle timed two ways on the host: the serial checker (-O2, one
+    thread) on a prefix of the headline rows, and the same source built -O3
+    -march=native -fopenmp, its count loop over the live candidates shared
+    among `threads` threads, on the whole headline workload (its result is
+    compared with the GPU's)."""
     import oracle
     rows = np.ascontiguousarray(rows_full[:n_rows])
     log(f"CPU oracle on the first {n_rows} rows ...")
@@ -209,21 +217,58 @@ def cpu_baseline(c, rows_full, n_rows):
     dt = time.perf_counter() - t0
     tests = r.stats["tests"] + n_rows * c["m"]
     log(f"  oracle {dt:.1f}s, {tests / dt / 1e9:.3f} G tests/s")
-    return {"value": tests / dt / 1e9, "unit": "G subset-tests/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_rows} rows of the n=1,000,000 m=1,000 workload, same minsup and "
-                      f"M; serial C oracle, {dt:.1f} s, {r.stats['tests']} block tests + "
-                      f"{n_rows * c['m']} first-pass tests",
-            "cpu": _cpu_model()}
+    out = {"value": tests / dt / 1e9, "unit": "G subset-tests/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {n_rows} rows of the n=1,000,000 m=1,000 workload, same minsup and "
+                     f"M (stop_max {r.stats['stop_max']}, not 100); serial C oracle built -O2, "
+                     f"{dt:.1f} s, {r.stats['tests']} block tests + {n_rows * c['m']} first-pass "
+                     "tests",
+           "cpu": _cpu_model(), "host_cpus": _host_cpus()}
+    if threads > 0:
+        n, m = rows_full.shape[0], c["m"]
+        log(f"CPU oracle, OpenMP build, {threads} threads, whole workload ...")
+        t0 = time.perf_counter()
+        rp, used = oracle.dic_parallel(rows_full, m, c["minsup"], c["M"], threads)
+        dtp = time.perf_counter() - t0
+        tp = rp.stats["tests"] + n * m
+        same = (np.array_equal(rp.masks, gpu_result.masks)
+                and np.array_equal(rp.counts, gpu_result.counts)
+                and np.array_equal(rp.trace, gpu_result.trace.astype(rp.trace.dtype)))
+        log(f"  oracle (OpenMP) {dtp:.1f}s on {used} threads, {tp / dtp / 1e9:.3f} G tests/s, "
+            f"equal to the GPU result: {same}")
+        out["parallel"] = {
+            "value": tp / dtp / 1e9, "unit": "G subset-tests/s", "cores": used,
+            "kind": "oracle, parallel count loop",
+            "sample": f"the whole n={n:,} m={m:,} workload (minsup {c['minsup']}, M {c['M']}); "
+                      "oracle source built -O3 -march=native -fopenmp, the count over live "
+                      f"candidates shared by {used} threads, {dtp:.1f} s",
+            "seconds": dtp, "threads": used, "cpu": _cpu_model(), "host_cpus": _host_cpus(),
+            "identical_to_gpu_result": bool(same)}
+    return out
+
+
+def _host_cpus():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count()
 
 
 def _cpu_model():
+    """The host CPU as /proc/cpuinfo names it, with its family, model and
+    stepping numbers (a virtual machine may show a short model name)."""
+    info = {}
     try:
         for ln in open("/proc/cpuinfo"):
-            if ln.startswith("model name"):
-                return ln.split(":", 1)[1].strip()
+            if ":" in ln:
+                k, v = (x.strip() for x in ln.split(":", 1))
+                if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                    info[k] = v
+            elif info:
+                break
     except OSError:
-        pass
-    return "unknown"
+        return "unknown"
+    return (f"{info.get('model name', 'unknown')} (family {info.get('cpu family', '?')}, "
+            f"model {info.get('model', '?')}, stepping {info.get('stepping', '?')})")
 
 
 def other_configs(dic, inputs):
@@ -410,7 +455,9 @@ def main():
     }
     if not args.only_headline:
         if not args.no_cpu:
-            line["cpu_baseline"] = cpu_baseline(c, h["rows"], args.cpu_rows)
+            threads = args.cpu_threads if args.cpu_threads else min(16, _host_cpus())
+            line["cpu_baseline"] = cpu_baseline(c, h["rows"], args.cpu_rows, max(threads, 0),
+                                                h["result"])
         log("other single-database workloads ...")
         line["workloads"] = other_configs(dic, others)
         log("association rules ...")
