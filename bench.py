@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--cpu-rows", type=int, default=40_000)
@@ -58,6 +58,10 @@ def parse():
                          "(0: min(16, CPUs available); -1: skip it)")
     ap.add_argument("--no-layouts", action="store_true",
                     help="skip the profiled count-kernel passes (for counter runs)")
+    ap.add_argument("--layouts", default="1,0",
+                    help="counting layouts of the profiled passes (1 item bitsets, 0 rows)")
+    ap.add_argument("--layout", type=int, default=1, choices=(0, 1),
+                    help="counting layout of the timed headline steps (default 1)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also copy the headline rows device to device once (a copy of known "
                          "size for scaling memory counters)")
@@ -99,12 +103,12 @@ def count_work(results, W, n_frequent_items, layout):
     return byt, ops, ms, launches
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_stepx_quest_zipf_n1M_m1000_pmc.txt")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_stop_quest_zipf_n1M_m1000_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1812_10959_amd", "csrc", "dic_kernels.hip")
 
 
 def measured_traffic():
-    """HBM bytes per k_stepx launch from the committed rocprofv3 counter
+    """HBM bytes per k_stop launch from the committed rocprofv3 counter
     runs (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None
     when the kernel source changed since the counters were taken."""
     import hashlib
@@ -116,7 +120,7 @@ def measured_traffic():
     if sha not in txt:
         return None
     for ln in txt.splitlines():
-        if ln.startswith("k_stepx traffic_bytes_per_launch:"):
+        if ln.startswith("k_stop traffic_bytes_per_launch:"):
             return float(ln.split(":")[1])
     return None
 
@@ -125,7 +129,7 @@ def roofline_entry(byt, ops, ms, launches):
     achieved_tops = ops / (ms * 1e-3) / 1e12 if ms else 0.0
     achieved_gbs = byt / (ms * 1e-3) / 1e9 if ms else 0.0
     return {
-        "kernel": "k_stepx", "bound": "alu", "achieved": achieved_tops,
+        "kernel": "k_stop", "bound": "alu", "achieved": achieved_tops,
         "peak": ALU_PEAK_TOPS, "unit": "Tops/s (int32 VALU lane-ops)",
         "frac": achieved_tops / ALU_PEAK_TOPS, "traffic": None,
         "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -141,6 +145,7 @@ def headline(dic, args, c):
     n, W = rows.shape
     db = dic.dic_load_db(rows, m)
     dic.dic_set_option("profile", 0)
+    dic.dic_set_option("layout", args.layout)
     import torch
     for i in range(args.warmup):
         r = dic.dic_mine(db, c["minsup"], c["M"])
@@ -170,7 +175,8 @@ def headline(dic, args, c):
     # every CountSupport launch (profiled runs launch directly, not as graphs).
     n_freq_items = int((np.bitwise_count(res[0].masks).sum(axis=1) == 1).sum())
     layouts = {}
-    for layout in (() if args.no_layouts else (1, 0)):
+    first_pass = {}
+    for layout in (() if args.no_layouts else [int(x) for x in args.layouts.split(",") if x]):
         dic.dic_set_option("layout", layout)
         dic.dic_set_option("profile", 1)
         prof = []
@@ -182,9 +188,10 @@ def headline(dic, args, c):
         dic.dic_set_option("profile", 0)
         byt, ops, cms, launches = count_work(prof, W, n_freq_items, layout)
         entry = roofline_entry(byt, ops, cms, launches)
-        # the timed launches: k_stepx (MakeCandidates + bitset CountSupport);
+        # the timed launches: k_stop (one stop: MakeCandidates, CountSupport
+        # and Prune of new and surviving candidates, then the serial part);
         # with row bitmaps k_count runs first, between the same events
-        entry["kernel"] = "k_stepx" if layout == 1 else "k_count + k_stepx"
+        entry["kernel"] = "k_stop" if layout == 1 else "k_count + k_stop"
         entry["count_ms_per_step"] = cms / reps
         entry["mine_ms_per_step_profiled"] = pdt * 1e3
         entry["count_G_tests_per_s"] = st["tests"] / (cms / reps * 1e-3) / 1e9 if cms else 0.0
@@ -194,6 +201,9 @@ def headline(dic, args, c):
         log(f"  layout {layout}: count {cms / reps:.2f} ms/step over {launches // reps} launches,"
             f" {entry['achieved']:.3f} Tops/s ({100 * entry['frac']:.2f}% ALU), "
             f"{entry['hbm']['achieved']:.1f} GB/s, mine {pdt * 1e3:.1f} ms profiled")
+        first_pass[layout] = [r.stats["first_pass_ms"] for r in prof]
+    if first_pass:
+        out["first_pass"] = first_pass_entry(dic, db, c, first_pass, args.steps)
     dic.dic_set_option("layout", 1)
     if "item_bitsets" in layouts:
         layouts["item_bitsets"]["traffic"] = measured_traffic()
@@ -201,6 +211,78 @@ def headline(dic, args, c):
     out["roofline"] = layouts.get("item_bitsets")
     out["layouts"] = layouts
     return out
+
+
+def _flush_caches(torch, buf):
+    """Evict the L2s and the 256 MB Infinity Cache: write 1 GiB."""
+    buf.fill_(1)
+    torch.cuda.synchronize()
+
+
+def first_pass_entry(dic, db, c, warm, reps):
+    """FirstPass against the HBM roof: every item's bitset (m * ceil(n/64)
+    words) or every row (n * W words) is read once per mine.  Warm: the
+    profiled mines above, the database resident in the Infinity Cache from
+    the previous mine.  Cold: each mine after 1 GiB of writes."""
+    import torch
+    rows = c["rows"]
+    n, W = rows.shape
+    m = c["m"]
+    nw = (n + 63) // 64
+    buf = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
+    out = {}
+    for layout, name, byt, kernel in ((1, "item_bitsets", m * nw * 8, "k_first_pass_vert"),
+                                      (0, "row_bitmaps", n * W * 8, "k_first_pass")):
+        if layout not in warm:
+            continue
+        dic.dic_set_option("layout", layout)
+        dic.dic_set_option("profile", 1)
+        cold = []
+        for _ in range(max(3, min(reps, 5)) if layout == 1 else 2):
+            _flush_caches(torch, buf)
+            cold.append(dic.dic_mine(db, c["minsup"], c["M"]).stats["first_pass_ms"])
+        dic.dic_set_option("profile", 0)
+        w_ms, c_ms = float(np.median(warm[layout])), float(np.median(cold))
+        e = {"kernel": kernel, "bound": "hbm", "algorithmic_bytes_per_launch": byt,
+             "unit": "GB/s", "peak": HBM_PEAK_GBS,
+             "cold": {"ms": c_ms, "achieved": byt / (c_ms * 1e-3) / 1e9,
+                      "frac": byt / (c_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "runs": len(cold)},
+             "warm": {"ms": w_ms, "achieved": byt / (w_ms * 1e-3) / 1e9,
+                      "frac": byt / (w_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "runs": len(warm[layout])}}
+        out[name] = e
+        log(f"  first pass ({name}): cold {c_ms * 1e3:.1f} us = {e['cold']['achieved']:.0f} GB/s "
+            f"({100 * e['cold']['frac']:.1f}% HBM), warm {w_ms * 1e3:.1f} us = "
+            f"{e['warm']['achieved']:.0f} GB/s")
+    del buf
+    return out
+
+
+def load_entry(dic, c):
+    """dic_load_db from rows already on the device: one device copy of the
+    rows (n * W words read and written), the padding check (read) and the
+    transposition into item bitsets (rows read, m * ceil(n/64) words
+    written)."""
+    import torch
+    rows = c["rows"]
+    n, W = rows.shape
+    nw = (n + 63) // 64
+    t = torch.from_numpy(rows.view(np.int64)).cuda()
+    torch.cuda.synchronize()
+    dic.dic_free_db(dic.dic_load_db(t, c["m"]))
+    times = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        db = dic.dic_load_db(t, c["m"])
+        times.append(time.perf_counter() - t0)
+        dic.dic_free_db(db)
+    ms = float(np.median(times)) * 1e3
+    byt = 4 * n * W * 8 + c["m"] * nw * 8
+    log(f"  load from device rows: {ms:.3f} ms ({byt / (ms * 1e-3) / 1e9:.0f} GB/s of copy, "
+        "check and transposition bytes)")
+    return {"ms": ms, "bytes": byt, "GB_per_s": byt / (ms * 1e-3) / 1e9,
+            "note": "wall time of dic_load_db on a device tensor: copy + padding check + "
+                    "k_transpose; the kernel alone is in the committed rocprofv3 trace"}
 
 
 def cpu_baseline(c, rows_full, n_rows, threads, gpu_result):
@@ -447,12 +529,17 @@ def main():
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "quest_zipf_n1M_m1000", "n": int(h["rows"].shape[0]), "m": c["m"],
                    "minsup": c["minsup"], "M": c["M"], "seed": c["meta"]["seed"],
-                   "path": "dic_mine (plain, one database)"},
+                   "path": "dic_mine (plain, one database)",
+                   "layout": "item_bitsets" if args.layout == 1 else "row_bitmaps"},
         "roofline": h["roofline"],
         "stats": {k: h["stats"][k] for k in ("tau", "stops", "tests", "peak_live", "n_frequent",
                                               "k_max", "known", "restarts")},
         "layouts": h["layouts"],
     }
+    if "first_pass" in h:
+        line["first_pass"] = h["first_pass"]
+    if not args.only_headline:
+        line["load_db"] = load_entry(dic, c)
     if not args.only_headline:
         if not args.no_cpu:
             threads = args.cpu_threads if args.cpu_threads else min(16, _host_cpus())

@@ -79,7 +79,8 @@ typedef struct dic_stop_trace {
     uint32_t words;      /* nonzero 32-bit words over the live candidates' masks:
                             the AND work per transaction at this stop      */
     uint32_t items;      /* items over the live candidates (sum of sizes)   */
-    uint32_t reserved;
+    uint32_t launch_ns;  /* with the "profile" option: the stop's launch time in
+                            ns (HIP events; in a batch the launch is shared) */
 } dic_stop_trace;
 
 typedef struct dic_stats {
@@ -97,6 +98,8 @@ typedef struct dic_stats {
     double count_ms;     /* CountSupport kernel time (HIP events; 0 unless the
                             "profile" option is on)                           */
     uint64_t count_launches; /* CountSupport launches timed into count_ms      */
+    double first_pass_ms; /* FirstPass kernel time (HIP events; 0 unless the
+                             "profile" option is on; a batch's jobs share it) */
 } dic_stats;
 
 /*

@@ -68,14 +68,15 @@ class DicError(RuntimeError):
 class dic_stop_trace(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint32) for f in (
         "stop", "rows", "live", "promoted", "pruned", "generated", "solidified", "words", "items",
-        "reserved")]
+        "launch_ns")]
 
 
 class dic_stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in (
         "tau", "block", "stop_max", "stops", "tests", "peak_live", "n_frequent", "k_max",
         "known", "restarts")] + [("mine_ms", ctypes.c_double), ("count_ms", ctypes.c_double),
-                                 ("count_launches", ctypes.c_uint64)]
+                                 ("count_launches", ctypes.c_uint64),
+                                 ("first_pass_ms", ctypes.c_double)]
 
 
 class dic_rules_stats(ctypes.Structure):
@@ -232,6 +233,7 @@ class Result:
     trace: np.ndarray | None = None  # uint32[stops, 7] in TRACE_FIELDS order
     words: np.ndarray | None = None  # uint32[stops]: nonzero 32-bit words of the live masks
     items: np.ndarray | None = None  # uint32[stops]: items over the live candidates
+    launch_ns: np.ndarray | None = None  # uint32[stops]: launch time (profile option)
 
 
 def _take_result(h: int) -> Result:
@@ -255,14 +257,15 @@ def _take_result(h: int) -> Result:
                  for f, _ in dic_stats._fields_}
         ns = _u64()
         tp = _lib.dic_result_trace(h, ctypes.byref(ns))
-        trace = words = items = None
+        trace = words = items = launch = None
         if ns.value:
             raw = np.ctypeslib.as_array(ctypes.cast(tp, ctypes.POINTER(ctypes.c_uint32)),
                                         shape=(ns.value * 10,)).reshape(ns.value, 10)
             trace = raw[:, :7].copy()
             words = raw[:, 7].copy()
             items = raw[:, 8].copy()
-        return Result(masks, counts, stats, trace, words, items)
+            launch = raw[:, 9].copy()
+        return Result(masks, counts, stats, trace, words, items, launch)
     finally:
         _lib.dic_result_free(h)
 
@@ -475,13 +478,18 @@ def dic_set_option(name: str, value: int) -> None:
 
 
 def _apply_tuning():
-    """Apply the autotuner's saved choice (tuning.json beside this file)."""
+    """Apply the autotuner's saved choice (tuning.json beside this file): the
+    global knobs, then the per-shape cells (all others cleared)."""
     path = os.path.join(_HERE, "tuning.json")
+    _lib.dic_set_option(b"cells_clear", 1)
     if os.path.exists(path):
         import json
         with open(path) as f:
-            for k, v in json.load(f).get("settings", {}).items():
-                _lib.dic_set_option(k.encode(), int(v))
+            doc = json.load(f)
+        for k, v in doc.get("settings", {}).items():
+            _lib.dic_set_option(k.encode(), int(v))
+        for key, (mode, target) in doc.get("cells", {}).items():
+            _lib.dic_set_option(f"cell:{key}".encode(), int(mode) * 65536 + int(target))
 
 
 _apply_tuning()

@@ -16,7 +16,9 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <iterator>
 #include <mutex>
 #include <numeric>
 
@@ -91,7 +93,22 @@ int set_knob(const char *name, int64_t v)
         g_knobs.count_grid = (uint32_t)v;
     else if (n == "count_target" && v >= 64 && v <= 65536)
         g_knobs.count_target = (uint32_t)v;
-    else
+    else if (n == "cells_clear" && v == 1) {
+        std::fill(std::begin(g_knobs.cell_mode), std::end(g_knobs.cell_mode), (uint16_t)0);
+        std::fill(std::begin(g_knobs.cell_target), std::end(g_knobs.cell_target), (uint16_t)0);
+    } else if (n.compare(0, 5, "cell:") == 0) {
+        // "cell:<block band>:<survivor band>": mode * 65536 + target
+        unsigned b = 0, k = 0;
+        char tail = 0;
+        if (std::sscanf(n.c_str() + 5, "%u:%u%c", &b, &k, &tail) != 2 || b >= TUNE_BB ||
+            k >= TUNE_KB)
+            return DIC_E_INVAL;
+        const int64_t mode = v >> 16, target = v & 0xFFFF;
+        if (v < 0 || mode > 2 || (target != 0 && (target < 64 || target > 65535)))
+            return DIC_E_INVAL;
+        g_knobs.cell_mode[b * TUNE_KB + k] = (uint16_t)mode;
+        g_knobs.cell_target[b * TUNE_KB + k] = (uint16_t)target;
+    } else
         return DIC_E_INVAL;
     return DIC_OK;
 }
@@ -164,6 +181,8 @@ struct ActiveJob {
     bool in_loop = false;   // first candidates written, taking part in stops
     double count_ms = 0;
     uint64_t count_launches = 0;
+    double first_pass_ms = 0;
+    std::vector<uint32_t> stop_ns;  // per stop: its launch's duration (profiled runs)
     std::chrono::steady_clock::time_point t0;
 
     void release()
@@ -224,6 +243,7 @@ int Engine::launch_steps(uint32_t S, bool rows, bool vert, bool prof, double *co
                          uint32_t *steps_done)
 {
     *count_ms = 0;
+    launch_ms_.clear();
     if (prof) {
         const uint32_t need = 2 * std::max(S, GRAPH_STEPS);
         while (events_.size() < need) {
@@ -237,6 +257,7 @@ int Engine::launch_steps(uint32_t S, bool rows, bool vert, bool prof, double *co
             float t = 0;
             HIP_TRY(hipEventElapsedTime(&t, events_[2 * k], events_[2 * k + 1]));
             *count_ms += t;
+            launch_ms_.push_back(t);
         }
         return DIC_OK;
     };
@@ -467,14 +488,31 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
     HIP_TRY(hipMemcpyAsync(d_plan_aux_, &plan_aux_, sizeof(Plan), hipMemcpyHostToDevice, s_));
     HIP_TRY(hipMemcpyAsync(plan_aux_.pre_fp, pre_host_.data(), 8ull * (nf + 1),
                            hipMemcpyHostToDevice, s_));
+    const bool prof = profiling();
+    if (prof) {
+        while (events_.size() < 2) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            events_.push_back(e);
+        }
+        HIP_TRY(hipEventRecord(events_[0], s_));
+    }
     if (vert)
         launch_first_pass_vert((const Job *)table_aux_, d_plan_aux_, pre_host_[nf], s_);
     else
         launch_first_pass((const Job *)table_aux_, d_plan_aux_, pre_host_[nf], s_);
+    if (prof)
+        HIP_TRY(hipEventRecord(events_[1], s_));
     launch_l1_and_pairs_prepare((const Job *)table_aux_, d_plan_aux_, nf, s_);
     HIP_TRY(hipGetLastError());
     if ((rc = read_states()))
         return rc;
+    if (prof) {
+        float t = 0;
+        HIP_TRY(hipEventElapsedTime(&t, events_[0], events_[1]));
+        for (ActiveJob *a : fresh)
+            a->first_pass_ms = t;
+    }
 
     // ---- candidate pools sized from the frequent-item count
     for (uint32_t i = 0; i < nf; ++i) {
@@ -547,7 +585,9 @@ bool Engine::knobs_changed() const
     const Knobs k = knobs();
     return k.vt_target != plan_step_.vt_target || k.vt_wave_k != plan_step_.vt_wave_k ||
            k.vt_tile_words != plan_step_.vt_tile_words ||
-           k.count_target != plan_step_.count_target;
+           k.count_target != plan_step_.count_target ||
+           std::memcmp(k.cell_mode, plan_step_.cell_mode, sizeof(k.cell_mode)) != 0 ||
+           std::memcmp(k.cell_target, plan_step_.cell_target, sizeof(k.cell_target)) != 0;
 }
 
 int Engine::upload_table()
@@ -557,6 +597,8 @@ int Engine::upload_table()
     plan_step_.vt_wave_k = k.vt_wave_k;
     plan_step_.vt_tile_words = k.vt_tile_words;
     plan_step_.count_target = k.count_target;
+    std::memcpy(plan_step_.cell_mode, k.cell_mode, sizeof(k.cell_mode));
+    std::memcpy(plan_step_.cell_target, k.cell_target, sizeof(k.cell_target));
     table_host_.clear();
     for (ActiveJob *a : jobs_)
         if (a->in_loop)
@@ -638,11 +680,30 @@ int Engine::advance(uint32_t max_steps)
     }
     double ms = 0;
     uint32_t done = 0;
+    // trace index of each job's stop at the chunk's first launch (a pending
+    // job begins its first stop in it)
+    std::vector<uint32_t> first_idx;
+    if (prof)
+        for (ActiveJob *a : jobs_) {
+            const JobState &s = st_[a->slot];
+            first_idx.push_back(s.pending ? 0u : (s.epoch ? s.epoch - 1u : 0u));
+        }
     if ((rc = launch_steps(S, any_rows, any_vert, prof, &ms, &done)))
         return rc;
     if ((rc = read_states()))
         return rc;
     if (prof) {
+        for (size_t i = 0; i < jobs_.size(); ++i) {
+            ActiveJob *a = jobs_[i];
+            if (!a->in_loop)
+                continue;
+            for (size_t k = 0; k < launch_ms_.size(); ++k) {
+                const size_t e = first_idx[i] + k;
+                if (e >= a->stop_ns.size())
+                    a->stop_ns.resize(e + 1, 0u);
+                a->stop_ns[e] = (uint32_t)std::min(4.0e9, launch_ms_[k] * 1e6);
+            }
+        }
         for (ActiveJob *a : jobs_)
             if (a->in_loop) {
                 a->count_ms += ms;
@@ -744,6 +805,8 @@ int Engine::collect(std::vector<ActiveJob *> &fin,
         const uint32_t *ic = (const uint32_t *)(pin + P.icnt);
         o.trace.assign((const dic_stop_trace *)(pin + P.trace),
                        (const dic_stop_trace *)(pin + P.trace) + P.ntr);
+        for (size_t e = 0; e < o.trace.size() && e < a->stop_ns.size(); ++e)
+            o.trace[e].launch_ns = a->stop_ns[e];
         // L = the frequent items (src < 0) and the collected boxes (src >= 0),
         // in canonical order: by key, then in full where keys tie
         struct Entry {
@@ -836,6 +899,7 @@ int Engine::collect(std::vector<ActiveJob *> &fin,
         S.mine_ms = std::chrono::duration<double, std::milli>(now - a->t0).count();
         S.count_ms = a->count_ms;
         S.count_launches = a->count_launches;
+        S.first_pass_ms = a->first_pass_ms;
         o.status = s.asserts ? DIC_E_DEVICE : DIC_OK;
         if (s.stops > a->trace_cap) {
             o.status = DIC_E_DEVICE;

@@ -53,12 +53,29 @@ __host__ __device__ inline uint32_t vert_tile_words(uint32_t nL1, uint32_t max_w
 
 // Tuning knobs of the count planning and launch (set by dic_set_option or
 // the autotuner; every setting gives the same results).
+// Per-shape planning of the bitset count: a cell per (band of the block's
+// 64-row words, band of the survivors counted at the stop).  A cell's mode
+// is 0 (fall back to vt_wave_k / vt_target), 1 (one wave per candidate) or
+// 2 (LDS tiles with `target` workgroups aimed at; 0: vt_target).
+constexpr uint32_t TUNE_BB = 5;  // block words: <= 4, <= 16, <= 64, <= 256, more
+constexpr uint32_t TUNE_KB = 5;  // survivors: < 256, < 1024, < 4096, < 16384, more
+constexpr uint32_t TUNE_CELLS = TUNE_BB * TUNE_KB;
+__host__ __device__ inline uint32_t tune_cell(uint32_t block_words, uint32_t K)
+{
+    const uint32_t b = block_words <= 4u ? 0u : block_words <= 16u ? 1u : block_words <= 64u ? 2u
+                       : block_words <= 256u ? 3u : 4u;
+    const uint32_t k = K < 256u ? 0u : K < 1024u ? 1u : K < 4096u ? 2u : K < 16384u ? 3u : 4u;
+    return b * TUNE_KB + k;
+}
+
 struct Knobs {
     uint32_t vt_target = 768;      // bitset count: workgroups aimed at per job per stop
     uint32_t vt_wave_k = 2048;     // bitset count: one wave per candidate below this
     uint32_t vt_tile_words = 16;   // bitset count: 64-row words per LDS tile at most
     uint32_t count_grid = 2048;    // workgroups launched for the count kernels
     uint32_t count_target = 2048;  // row-bitmap count: work items aimed at per job
+    uint16_t cell_mode[TUNE_CELLS] = {};    // per-shape cells (see tune_cell)
+    uint16_t cell_target[TUNE_CELLS] = {};
 };
 Knobs knobs();
 int set_knob(const char *name, int64_t value);
@@ -308,6 +325,7 @@ struct Plan {
     unsigned long long *pre_fp;  // first pass row chunks
     uint32_t vt_target, vt_wave_k, vt_tile_words, count_target;  // see Knobs
     uint32_t *tickets;  // arrival counters of candidate generation (zero between launches)
+    uint16_t cell_mode[TUNE_CELLS], cell_target[TUNE_CELLS];  // see Knobs
 };
 // arrival counters: a root and TICKET_GROUPS group counters, TICKET_STRIDE
 // words apart so that no two share a cache line
@@ -494,6 +512,7 @@ class Engine {
     bool table_dirty_ = true;
     bool requeue_ = false;
     std::vector<hipEvent_t> events_;
+    std::vector<float> launch_ms_;  // per launch of the last profiled chunk
 };
 
 }  // namespace dic

@@ -27,6 +27,7 @@ namespace {
 
 constexpr uint32_t FP_ROWS = 4096;       // first pass rows per workgroup item
 constexpr uint32_t FPV_WORDS = 4096;     // first pass (bitsets): words per work item
+static_assert(FPV_WORDS % WG == 0, "first-pass chunks are whole loads per thread");
 constexpr int VT_CPT = 4;                // bitset count: candidates per thread at most
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 constexpr int ZP = 2;                    // row-bitmap survivors pruned per thread
@@ -304,30 +305,82 @@ __device__ __forceinline__ void block_reduce(uint32_t (&v)[NS + 1], uint32_t *sh
 
 // ---------------------------------------------------------------------------
 // Item bitsets from rows: bit r of vert[i * nw + g] is set when row 64g + r
-// holds item i.  One wave per 64-row word: lane r holds row 64g + r, a ballot
-// over the lanes yields one item's word, and the lane whose index is that
-// item's bit position keeps it, so each lane stores one word per row word.
+// holds item i.
+//
+// 64 x 64 bit transposition in one wave: lane r holds a 64-bit row, and after
+// six exchange steps lane c holds column c.  The step of width j swaps the
+// off-diagonal j x j blocks of every 2j x 2j block: lane r trades with lane
+// r ^ j, the lower lane taking its partner's low-column half into its high
+// columns and the upper lane the partner's high half into its low columns
+// (a transpose is a block swap at every scale).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t transpose64(uint64_t x, uint32_t lane)
+{
+    constexpr uint64_t HI[6] = {0xFFFFFFFF00000000ull, 0xFFFF0000FFFF0000ull,
+                                0xFF00FF00FF00FF00ull, 0xF0F0F0F0F0F0F0F0ull,
+                                0xCCCCCCCCCCCCCCCCull, 0xAAAAAAAAAAAAAAAAull};
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const int j = 32 >> s;
+        const uint64_t y = __shfl_xor(x, j, 64);
+        x = (lane & (uint32_t)j) ? ((x & HI[s]) | ((y >> j) & ~HI[s]))
+                                 : ((x & ~HI[s]) | ((y << j) & HI[s]));
+    }
+    return x;
+}
+
+// A workgroup transposes one tile: TR_G consecutive row words (64 rows each)
+// by the 64 * TR_W items of TR_W row-bitmap words.  Per row word, each wave
+// loads the tile's words of its 64 rows (lane r: row 64g + r), transposes
+// each 64 x 64 block and puts item i's word for g in LDS at (i, g).  The tile
+// then leaves as runs of TR_G consecutive words per item (128 contiguous
+// bytes), not one scattered word per lane.
+//
+// XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so the
+// k-th workgroup of XCD x takes unit x * P + k of the (tile, word chunk)
+// units, chunk fastest: each XCD walks a contiguous range of rows, and the
+// workgroups that read the same rows (one per chunk) share its L2.
+constexpr uint32_t TR_G = 16;               // row words per tile
+constexpr uint32_t TR_W = 8;                // row-bitmap words per tile (x 64 items)
+constexpr uint32_t TR_STRIDE = TR_G + 1;    // LDS words per item (odd: spreads banks)
+constexpr uint32_t N_XCD = 8;
+
 __global__ __launch_bounds__(WG) void k_transpose(const uint64_t *__restrict__ rows, uint64_t n,
                                                   uint32_t m, uint32_t W, uint64_t *vert,
-                                                  uint32_t nw)
+                                                  uint32_t nw, uint32_t per_xcd)
 {
-    const uint32_t lane = lane_id();
-    const uint64_t waves = (uint64_t)gridDim.x * (WG / 64);
-    for (uint64_t g = (uint64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6); g < nw; g += waves) {
-        const uint64_t r = g * 64 + lane;
-        for (uint32_t w = 0; w < W; ++w) {
-            const uint64_t x = r < n ? rows[r * W + w] : 0ull;
-            uint64_t keep = 0;
-            for (uint32_t b = 0; b < 64; ++b) {
-                const uint64_t msk = __ballot((x >> b) & 1ull);
-                if (lane == b)
-                    keep = msk;
-            }
-            const uint32_t item = w * 64u + lane;
-            if (item < m)
-                vert[(uint64_t)item * nw + g] = keep;
-        }
+    __shared__ uint64_t T[TR_W * 64 * TR_STRIDE];
+    const uint32_t chunks = (W + TR_W - 1u) / TR_W;
+    const uint32_t tiles = (nw + TR_G - 1u) / TR_G;
+    const uint64_t units = (uint64_t)tiles * chunks;
+    const uint64_t u = (uint64_t)(blockIdx.x % N_XCD) * per_xcd + blockIdx.x / N_XCD;
+    if (blockIdx.x / N_XCD >= per_xcd || u >= units)
+        return;
+    const uint32_t tile = (uint32_t)(u / chunks), c = (uint32_t)(u - (uint64_t)tile * chunks);
+    const uint32_t g0 = tile * TR_G, w0 = c * TR_W;
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    constexpr uint32_t PER_WAVE = TR_G / (WG / 64);
+    // every load of the wave's row words before the first exchange
+    uint64_t x[PER_WAVE][TR_W];
+#pragma unroll
+    for (uint32_t t = 0; t < PER_WAVE; ++t) {
+        const uint64_t r = (uint64_t)(g0 + wave + t * (WG / 64)) * 64u + lane;
+#pragma unroll
+        for (uint32_t i = 0; i < TR_W; ++i)
+            x[t][i] = r < n && w0 + i < W ? rows[r * W + w0 + i] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t t = 0; t < PER_WAVE; ++t)
+#pragma unroll
+        for (uint32_t i = 0; i < TR_W; ++i)
+            T[(i * 64u + lane) * TR_STRIDE + wave + t * (WG / 64)] = transpose64(x[t][i], lane);
+    __syncthreads();
+    const uint32_t gl = threadIdx.x % TR_G;
+    const uint32_t g = g0 + gl;
+    for (uint32_t it = threadIdx.x / TR_G; it < TR_W * 64u; it += WG / TR_G) {
+        const uint32_t item = w0 * 64u + it;
+        if (item < m && g < nw)
+            vert[(uint64_t)item * nw + g] = T[it * TR_STRIDE + gl];
     }
 }
 
@@ -347,9 +400,18 @@ __global__ __launch_bounds__(WG) void k_first_pass_vert(const Job *__restrict__ 
         const uint32_t w0 = ch * FPV_WORDS;
         const uint32_t w1 = w0 + FPV_WORDS < J->nw ? w0 + FPV_WORDS : J->nw;
         const uint64_t *v = J->vert + (uint64_t)item * J->nw;
+        // all of the thread's words in flight at once (FPV_WORDS / WG loads)
+        constexpr uint32_t PER = FPV_WORDS / WG;
+        uint64_t x[PER];
+#pragma unroll
+        for (uint32_t k = 0; k < PER; ++k) {
+            const uint32_t w = w0 + threadIdx.x + k * WG;
+            x[k] = v[w < w1 ? w : w0];
+        }
         uint32_t c = 0;
-        for (uint32_t w = w0 + threadIdx.x; w < w1; w += WG)
-            c += (uint32_t)__popcll(v[w]);
+#pragma unroll
+        for (uint32_t k = 0; k < PER; ++k)
+            c += w0 + threadIdx.x + k * WG < w1 ? (uint32_t)__popcll(x[k]) : 0u;
         c = block_sum(c, sh);
         if (threadIdx.x == 0 && c)
             atomicAdd(&J->item_cnt[item], c);
@@ -560,7 +622,11 @@ __device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const Plan 
     if (K == 0)
         return;
     const uint32_t rows = s.last - s.first;
-    if (J->layout == LAYOUT_VERTICAL && K < plan->vt_wave_k) {
+    // per-shape cell of this stop, else the global choice
+    const uint32_t cell = tune_cell(s.lw - s.fw + 1u, K);
+    const uint32_t cmode = plan->cell_mode[cell];
+    const bool wave = cmode ? cmode == 1u : K < plan->vt_wave_k;
+    if (J->layout == LAYOUT_VERTICAL && wave) {
         // few candidates: one wave per candidate, no tile
         s.cmode = 1;
         *items_stop = (K + WG / 64 - 1u) / (WG / 64);
@@ -571,7 +637,8 @@ __device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const Plan 
         const uint32_t ntile = (s.lw - s.fw + tw) / tw;
         // candidates per thread: spend the parallelism beyond vt_target
         // workgroups on fewer tile loads
-        const uint64_t vt_target = plan->vt_target;
+        const uint64_t vt_target = plan->cell_target[cell] ? plan->cell_target[cell]
+                                                           : plan->vt_target;
         uint64_t cpt = ((uint64_t)K * ntile + (uint64_t)WG * vt_target - 1u) /
                        ((uint64_t)WG * vt_target);
         cpt = cpt < 1u ? 1u : (cpt > (uint64_t)VT_CPT ? (uint64_t)VT_CPT : cpt);
@@ -1970,8 +2037,13 @@ void launch_first_pass_vert(const Job *jobs, const Plan *plan, unsigned long lon
 void launch_transpose(const uint64_t *rows, uint64_t n, uint32_t m, uint64_t *vert, uint32_t nw,
                       hipStream_t s)
 {
-    hipLaunchKernelGGL(k_transpose, dim3(grid_for(nw, WG / 64, 16384)), dim3(WG), 0, s, rows, n,
-                       m, (m + 63u) / 64u, vert, nw);
+    const uint32_t W = (m + 63u) / 64u;
+    const uint64_t units = (uint64_t)((nw + TR_G - 1u) / TR_G) * ((W + TR_W - 1u) / TR_W);
+    const uint32_t per_xcd = (uint32_t)((units + N_XCD - 1) / N_XCD);
+    if (units == 0)
+        return;
+    hipLaunchKernelGGL(k_transpose, dim3(per_xcd * N_XCD), dim3(WG), 0, s, rows, n, m, W, vert,
+                       nw, per_xcd);
 }
 
 void launch_l1_and_pairs_prepare(const Job *jobs, const Plan *, uint32_t njobs, hipStream_t s)

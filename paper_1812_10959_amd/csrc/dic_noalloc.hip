@@ -252,6 +252,8 @@ int mine_once(char *base, hipStream_t s, const MineRequest &req, uint32_t layout
     R.step.vt_wave_k = k.vt_wave_k;
     R.step.vt_tile_words = k.vt_tile_words;
     R.step.count_target = k.count_target;
+    std::memcpy(R.step.cell_mode, k.cell_mode, sizeof(k.cell_mode));
+    std::memcpy(R.step.cell_target, k.cell_target, sizeof(k.cell_target));
     R.step.tickets = tickets;
     NA_TRY(hipMemcpyAsync(d_step, &R.step, sizeof(Plan), hipMemcpyHostToDevice, s));
     NA_TRY(hipGetLastError());

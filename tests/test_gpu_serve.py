@@ -201,11 +201,25 @@ def test_planning_knobs_do_not_change_results(dic, orc):
     variants = [dict(vt_wave_k=0), dict(vt_wave_k=1 << 20), dict(vt_tile_words=1),
                 dict(vt_tile_words=5), dict(vt_target=64), dict(vt_target=8192),
                 dict(count_grid=64), dict(count_grid=5000)]
+    # per-shape cells: all wave, all tiles at a small and a large target,
+    # and a checkerboard of both
+    cells = [{(b, k): (1, 0) for b in range(5) for k in range(5)},
+             {(b, k): (2, 64) for b in range(5) for k in range(5)},
+             {(b, k): (2, 4096) for b in range(5) for k in range(5)},
+             {(b, k): ((1, 0) if (b + k) % 2 else (2, 300)) for b in range(5) for k in range(5)}]
     try:
-        for v in variants:
-            for k, x in {**base, **v}.items():
-                dic.dic_set_option(k, x)
+        dic.dic_set_option("cells_clear", 1)
+        for v in variants + cells:
+            if v in cells:
+                for k, x in base.items():
+                    dic.dic_set_option(k, x)
+                for (b, k), (mode, target) in v.items():
+                    dic.dic_set_option(f"cell:{b}:{k}", mode * 65536 + target)
+            else:
+                for k, x in {**base, **v}.items():
+                    dic.dic_set_option(k, x)
             g = dic.dic_mine(db, 0.006, 700)
+            dic.dic_set_option("cells_clear", 1)
             assert np.array_equal(g.masks, ref.masks) and np.array_equal(g.counts, ref.counts), v
             assert np.array_equal(g.trace.astype(np.uint64), ref.trace), v
         dic.dic_set_option("layout", 0)
@@ -221,3 +235,7 @@ def test_planning_knobs_do_not_change_results(dic, orc):
         paper_1812_10959_amd._apply_tuning()
     with pytest.raises(dic.DicError):
         dic.dic_set_option("vt_tile_words", 17)
+    for bad in (("cell:5:0", 65536), ("cell:0:5", 65536), ("cell:0:0", 3 * 65536),
+                ("cell:0:0", 2 * 65536 + 10), ("cell:0", 65536), ("cell:0:0:1", 65536)):
+        with pytest.raises(dic.DicError):
+            dic.dic_set_option(*bad)
