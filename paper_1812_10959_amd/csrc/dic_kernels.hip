@@ -606,12 +606,37 @@ __device__ __forceinline__ void begin_stop(const Job *J, JobState *st)
     }
 }
 
+// The planning knobs, copied from the Plan into LDS by the serial part of a
+// launch before any job is planned, so that a job's plan reads its cell
+// without a dependent global load.
+struct PlanTune {
+    uint32_t cell[TUNE_CELLS];  // mode << 16 | target
+    uint32_t vt_target, vt_wave_k, vt_tile_words, count_target;
+};
+
+// Every thread calls; the caller's barrier makes the copy visible.
+__device__ __forceinline__ void load_tune(const Plan *plan, PlanTune *t)
+{
+    const uint32_t i = threadIdx.x;
+    if (i < TUNE_CELLS)
+        t->cell[i] = ((uint32_t)plan->cell_mode[i] << 16) | plan->cell_target[i];
+    else if (i == TUNE_CELLS)
+        t->vt_target = plan->vt_target;
+    else if (i == TUNE_CELLS + 1)
+        t->vt_wave_k = plan->vt_wave_k;
+    else if (i == TUNE_CELLS + 2)
+        t->vt_tile_words = plan->vt_tile_words;
+    else if (i == TUNE_CELLS + 3)
+        t->count_target = plan->count_target;
+}
+
 // Work of one job in the next launch, from its state s: chunks of
 // MakeCandidates (WG (new box, frequent item) pairs each), the survivors'
 // work items by layout, and the row-bitmap count's work items (k_count).
 // The count plan is stored in s.
-__device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const Plan *plan, uint32_t *items_rows,
-                          uint32_t *items_stop, unsigned long long *chunks)
+__device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const PlanTune *tune,
+                                          uint32_t *items_rows, uint32_t *items_stop,
+                                          unsigned long long *chunks)
 {
     *items_rows = *items_stop = 0;
     *chunks = 0;
@@ -623,9 +648,9 @@ __device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const Plan 
         return;
     const uint32_t rows = s.last - s.first;
     // per-shape cell of this stop, else the global choice
-    const uint32_t cell = tune_cell(s.lw - s.fw + 1u, K);
-    const uint32_t cmode = plan->cell_mode[cell];
-    const bool wave = cmode ? cmode == 1u : K < plan->vt_wave_k;
+    const uint32_t cell = tune->cell[tune_cell(s.lw - s.fw + 1u, K)];
+    const uint32_t cmode = cell >> 16, ctarget = cell & 0xFFFFu;
+    const bool wave = cmode ? cmode == 1u : K < tune->vt_wave_k;
     if (J->layout == LAYOUT_VERTICAL && wave) {
         // few candidates: one wave per candidate, no tile
         s.cmode = 1;
@@ -633,12 +658,11 @@ __device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const Plan 
     } else if (J->layout == LAYOUT_VERTICAL) {
         // (candidate groups of WG * cpt) x (chunks of tiles of tw words)
         s.cmode = 0;
-        const uint32_t tw = vert_tile_words(s.nL1, plan->vt_tile_words);
+        const uint32_t tw = vert_tile_words(s.nL1, tune->vt_tile_words);
         const uint32_t ntile = (s.lw - s.fw + tw) / tw;
         // candidates per thread: spend the parallelism beyond vt_target
         // workgroups on fewer tile loads
-        const uint64_t vt_target = plan->cell_target[cell] ? plan->cell_target[cell]
-                                                           : plan->vt_target;
+        const uint64_t vt_target = ctarget ? ctarget : tune->vt_target;
         uint64_t cpt = ((uint64_t)K * ntile + (uint64_t)WG * vt_target - 1u) /
                        ((uint64_t)WG * vt_target);
         cpt = cpt < 1u ? 1u : (cpt > (uint64_t)VT_CPT ? (uint64_t)VT_CPT : cpt);
@@ -658,7 +682,7 @@ __device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const Plan 
         const uint32_t rt = row_tile_rows(J->W);
         const uint32_t n_ct = (K + CAND_PER_WG - 1u) / CAND_PER_WG;
         const uint32_t tiles = (rows + rt - 1u) / rt;
-        uint32_t want = (plan->count_target + n_ct - 1u) / n_ct;
+        uint32_t want = (tune->count_target + n_ct - 1u) / n_ct;
         want = want < 1u ? 1u : (want > tiles ? tiles : want);
         const uint32_t rpi = ((tiles + want - 1u) / want) * rt;
         s.n_ct = n_ct;
@@ -678,20 +702,41 @@ __device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const Plan 
 // and either ends the run or begins stop e+1.  Counters that other
 // workgroups of the launch updated with atomics are read with device-scope
 // atomic loads.
-__device__ __forceinline__ void settle_job(const Job *J, bool finish, bool begin, const Plan *plan,
-                           uint32_t *items_rows, uint32_t *items_stop, unsigned long long *chunks)
+// What settle_job reads from memory: the state, and the counters other
+// workgroups of the launch updated with atomics (device-scope atomic loads).
+// Loaded ahead of the knobs' copy, so that both are in flight together.
+struct SettleIn {
+    JobState s;
+    uint32_t pn, mr, asserts;
+    unsigned long long kn_nn;
+};
+
+__device__ __forceinline__ void settle_load(const Job *J, bool finish, SettleIn &in)
 {
     JobState *stp = J->st;
-    JobState s;
-    __builtin_memcpy(&s, stp, sizeof(JobState));
+    __builtin_memcpy(&in.s, stp, sizeof(JobState));
+    if (finish) {
+        in.pn = __hip_atomic_load(&stp->pool_n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        in.kn_nn = __hip_atomic_load((unsigned long long *)&stp->k_next, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        in.mr = __hip_atomic_load(&stp->max_rem, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        in.asserts = __hip_atomic_load(&stp->asserts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ __forceinline__ void settle_job(const Job *J, const SettleIn &in, bool finish,
+                                           bool begin, const PlanTune *tune, uint32_t *items_rows,
+                                           uint32_t *items_stop, unsigned long long *chunks)
+{
+    JobState *stp = J->st;
+    JobState s = in.s;
     bool write = false;
     if (finish && !s.done && !s.overflow && !s.pending) {
         write = true;
-        const uint32_t pn = __hip_atomic_load(&stp->pool_n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long kn_nn = __hip_atomic_load((unsigned long long *)&stp->k_next,
-                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t mr = __hip_atomic_load(&stp->max_rem, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s.asserts = __hip_atomic_load(&stp->asserts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t pn = in.pn;
+        const unsigned long long kn_nn = in.kn_nn;
+        const uint32_t mr = in.mr;
+        s.asserts = in.asserts;
         const uint32_t kn = (uint32_t)kn_nn, nn = (uint32_t)(kn_nn >> 32);
         const uint32_t E = s.epoch;
         s.pool_n = pn;
@@ -754,7 +799,7 @@ __device__ __forceinline__ void settle_job(const Job *J, bool finish, bool begin
         s.pending = 0;
         begin_stop(J, &s);
     }
-    plan_stop(J, s, plan, items_rows, items_stop, chunks);
+    plan_stop(J, s, tune, items_rows, items_stop, chunks);
     if (write || (!s.done && !s.overflow && !s.pending))
         __builtin_memcpy(stp, &s, sizeof(JobState));
 }
@@ -797,24 +842,65 @@ __device__ __forceinline__ bool arrive_last(uint32_t *tickets, uint32_t n)
 // The serial part of a launch for every job (one workgroup, every thread
 // calls): settle_job per job, then per-job prefix sums of the next launch's
 // work (row-bitmap count items, stop-kernel survivor items, MakeCandidates
-// chunks) and their totals.  sh holds 2 * (WG/64) words.
+// chunks) and their totals.  sh holds 2 * (WG/64) words.  Up to 64 jobs
+// the sums are one wave's (no barrier); more use the workgroup's scans.
 __device__ __forceinline__ void settle_and_plan(const Job *__restrict__ jobs, Plan *plan, bool finish, bool begin,
-                                uint32_t *sh, unsigned long long *shc)
+                                uint32_t *sh, unsigned long long *shc, PlanTune *tune)
 {
     const uint32_t njobs = plan->njobs;
-    uint32_t carry_c = 0, carry_v = 0;
-    unsigned long long carry_g = 0;
     if (threadIdx.x == 0) {
         plan->pre_count[0] = 0;
         plan->pre_countv[0] = 0;
         plan->pre_cg[0] = 0;
     }
+    if (njobs <= 64u) {
+        SettleIn in;
+        const uint32_t j = threadIdx.x;
+        if (j < njobs)
+            settle_load(jobs + j, finish, in);
+        load_tune(plan, tune);
+        __syncthreads();
+        if (threadIdx.x >= 64u)
+            return;
+        uint32_t items = 0, itemsv = 0;
+        unsigned long long chunks = 0;
+        if (j < njobs)
+            settle_job(jobs + j, in, finish, begin, tune, &items, &itemsv, &chunks);
+        // inclusive sums over the wave's lanes
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t a = __shfl_up(items, off, 64), b = __shfl_up(itemsv, off, 64);
+            const unsigned long long c = __shfl_up(chunks, off, 64);
+            if ((int)j >= off) {
+                items += a;
+                itemsv += b;
+                chunks += c;
+            }
+        }
+        if (j < njobs) {
+            plan->pre_count[j + 1] = items;
+            plan->pre_countv[j + 1] = itemsv;
+            plan->pre_cg[j + 1] = chunks;
+        }
+        if (j == njobs - 1u) {
+            plan->total_v = itemsv;
+            plan->total_cg = chunks;
+        }
+        return;
+    }
+    load_tune(plan, tune);
+    __syncthreads();
+    uint32_t carry_c = 0, carry_v = 0;
+    unsigned long long carry_g = 0;
     for (uint32_t b = 0; b < njobs; b += WG) {
         const uint32_t j = b + threadIdx.x;
         uint32_t items = 0, itemsv = 0;
         unsigned long long chunks = 0;
-        if (j < njobs)
-            settle_job(jobs + j, finish, begin, plan, &items, &itemsv, &chunks);
+        if (j < njobs) {
+            SettleIn in;
+            settle_load(jobs + j, finish, in);
+            settle_job(jobs + j, in, finish, begin, tune, &items, &itemsv, &chunks);
+        }
         uint32_t v[2] = {items, itemsv}, t[2];
         block_scan_n<2>(v, sh, t);
         unsigned long long tg;
@@ -861,7 +947,8 @@ __global__ __launch_bounds__(WG) void k_begin(const Job *__restrict__ jobs, Plan
 {
     __shared__ uint32_t sh[2 * (WG / 64)];
     __shared__ unsigned long long shc[WG / 64];
-    settle_and_plan(jobs, plan, false, true, sh, shc);
+    __shared__ PlanTune tune;
+    settle_and_plan(jobs, plan, false, true, sh, shc, &tune);
 }
 
 // CountSupport (Algorithm 3) on row bitmaps, ahead of the stop kernel.  Work
@@ -1939,7 +2026,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
                                                               : gridDim.x);
     __syncthreads();
     if (sh_flag)
-        settle_and_plan(jobs, plan, true, false, (uint32_t *)tile, shc);
+        settle_and_plan(jobs, plan, true, false, (uint32_t *)tile, shc,
+                        (PlanTune *)(tile + VT_WORDS / 2));
 }
 
 // Gather solid boxes (the output L without its 1-itemsets), each with its
