@@ -204,6 +204,10 @@ int dic_set_option(const char *name, int64_t value)
         set_init_mode((uint32_t)value);
         return DIC_OK;
     }
+    if (name && std::strcmp(name, "poison") == 0 && value >= 0 && value <= 255) {
+        set_poison((int)value);
+        return DIC_OK;
+    }
     if (name && std::strcmp(name, "layout") == 0 && (value == 0 || value == 1)) {
         set_count_layout(value ? LAYOUT_VERTICAL : LAYOUT_ROWS);
         return DIC_OK;

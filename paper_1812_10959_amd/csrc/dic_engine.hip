@@ -60,6 +60,7 @@ std::atomic<int> g_profile{0};
 std::atomic<uint32_t> g_layout{LAYOUT_VERTICAL};
 std::atomic<uint32_t> g_init{0};  // 0: FirstPass, 1: classic DIC initialisation
 std::atomic<bool> g_graphs{true};
+std::atomic<int> g_poison{0};
 std::mutex g_knob_mu;
 Knobs g_knobs;
 constexpr uint32_t GRAPH_STEPS = 8;  // stops per captured step graph
@@ -72,6 +73,8 @@ uint32_t count_layout() { return g_layout.load(); }
 uint32_t init_mode() { return g_init.load(); }
 void set_init_mode(uint32_t mode) { g_init.store(mode); }
 bool use_graphs() { return g_graphs.load(); }
+int poison() { return g_poison.load(); }
+void set_poison(int byte) { g_poison.store(byte); }
 
 Knobs knobs()
 {
@@ -439,6 +442,9 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         if (!a->small || !a->trace) {
             rc = DIC_E_NOMEM;
             set_error("device allocation failed (job records)");
+        } else if (const int pb = poison()) {
+            HIP_TRY(hipMemsetAsync(a->small, pb, 12ull * r.m + 768, s_));
+            HIP_TRY(hipMemsetAsync(a->trace, pb, sizeof(dic_stop_trace) * a->trace_cap, s_));
         }
     }
     if (rc)
@@ -531,6 +537,8 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
             set_error("device allocation failed (candidate pool)");
             return DIC_E_NOMEM;
         }
+        if (const int pb = poison())
+            HIP_TRY(hipMemsetAsync(a->pool, pb, L.bytes, s_));
         pool_assign(J, L, (char *)a->pool, a->cap);
         // the counts read item rows by frequent-item index: gather those rows
         // unless every item is frequent (classic start: all items, in order)
@@ -542,6 +550,8 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
                 set_error("device allocation failed (frequent-item bitsets)");
                 return DIC_E_NOMEM;
             }
+            if (const int pb = poison())
+                HIP_TRY(hipMemsetAsync(a->fvert, pb, 8ull * a->nL1 * J.nw, s_));
             J.fvert = (uint64_t *)a->fvert;
         }
         HIP_TRY(hipMemsetAsync(J.slots, 0xFF, L.hslots * 8, s_));
@@ -635,6 +645,8 @@ int Engine::ensure_trace(uint32_t steps)
             set_error("device allocation failed (trace)");
             return DIC_E_NOMEM;
         }
+        if (const int pb = poison())
+            HIP_TRY(hipMemsetAsync(nb, pb, sizeof(dic_stop_trace) * nc, s_));
         HIP_TRY(hipMemcpyAsync(nb, a->trace, sizeof(dic_stop_trace) * a->trace_cap,
                                hipMemcpyDeviceToDevice, s_));
         HIP_TRY(hipStreamSynchronize(s_));

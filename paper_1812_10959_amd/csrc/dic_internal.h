@@ -423,6 +423,12 @@ int run_jobs(const std::vector<MineRequest> &reqs, std::vector<MineOutput> &outs
              hipStream_t stream);
 bool use_graphs();
 void set_use_graphs(bool on);
+// Test aid: when nonzero, every job buffer (pool, per-item records,
+// frequent-item bitsets, trace) is filled with this byte value on
+// allocation, so that a read of memory the run has not written yet gives a
+// value from the fill instead of from whatever a previous job left there.
+int poison();
+void set_poison(int byte);
 
 // Bytes the library's allocator sets aside for a request of b bytes.
 inline uint64_t alloc_bytes(uint64_t b)
