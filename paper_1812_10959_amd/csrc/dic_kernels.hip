@@ -591,7 +591,8 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
 // first block after the last), the next epoch and its zeroed trace entry.
 __device__ __forceinline__ void begin_stop(const Job *J, JobState *st)
 {
-    const uint32_t stop = st->stop % J->stop_max + 1u;
+    // the next block, rewinding after the last (stop is 0 before the first)
+    const uint32_t stop = st->stop >= J->stop_max ? 1u : st->stop + 1u;
     st->stop = stop;
     const uint64_t first = (uint64_t)(stop - 1u) * J->Mp;
     const uint64_t end = (uint64_t)stop * J->Mp;
@@ -663,8 +664,11 @@ __device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const PlanT
         // candidates per thread: spend the parallelism beyond vt_target
         // workgroups on fewer tile loads
         const uint64_t vt_target = ctarget ? ctarget : tune->vt_target;
-        uint64_t cpt = ((uint64_t)K * ntile + (uint64_t)WG * vt_target - 1u) /
-                       ((uint64_t)WG * vt_target);
+        // (32-bit division when the work fits: a 64-bit one is far longer)
+        const uint64_t work = (uint64_t)K * ntile, per = (uint64_t)WG * vt_target;
+        uint64_t cpt = work + per <= 0xFFFFFFFFull
+                           ? (uint64_t)(((uint32_t)work + (uint32_t)per - 1u) / (uint32_t)per)
+                           : (work + per - 1u) / per;
         cpt = cpt < 1u ? 1u : (cpt > (uint64_t)VT_CPT ? (uint64_t)VT_CPT : cpt);
         s.cpt = (uint32_t)cpt;
         const uint32_t n_cg = (K + WG * (uint32_t)cpt - 1u) / (WG * (uint32_t)cpt);
@@ -852,7 +856,13 @@ __device__ __forceinline__ void settle_and_plan(const Job *__restrict__ jobs, Pl
         plan->pre_count[0] = 0;
         plan->pre_countv[0] = 0;
         plan->pre_cg[0] = 0;
+        if (njobs == 0u) {
+            plan->total_v = 0;
+            plan->total_cg = 0;
+        }
     }
+    if (njobs == 0u)
+        return;
     if (njobs <= 64u) {
         SettleIn in;
         const uint32_t j = threadIdx.x;
@@ -866,6 +876,16 @@ __device__ __forceinline__ void settle_and_plan(const Job *__restrict__ jobs, Pl
         unsigned long long chunks = 0;
         if (j < njobs)
             settle_job(jobs + j, in, finish, begin, tune, &items, &itemsv, &chunks);
+        if (njobs == 1u) {  // one job: its own totals, no sums across lanes
+            if (j == 0) {
+                plan->pre_count[1] = items;
+                plan->pre_countv[1] = itemsv;
+                plan->pre_cg[1] = chunks;
+                plan->total_v = itemsv;
+                plan->total_cg = chunks;
+            }
+            return;
+        }
         // inclusive sums over the wave's lanes
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
