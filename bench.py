@@ -359,12 +359,14 @@ def other_configs(dic, inputs):
         rows, m = c["rows"], c["m"]
         n = rows.shape[0]
         db = dic.dic_load_db(rows, m)
-        dic.dic_mine(db, c["minsup"], c["M"])
-        t0 = time.perf_counter()
-        reps = 3
-        for _ in range(reps):
+        for _ in range(2):
+            dic.dic_mine(db, c["minsup"], c["M"])
+        times = []
+        for _ in range(7):  # median of seven: one slow call does not move it
+            t0 = time.perf_counter()
             r = dic.dic_mine(db, c["minsup"], c["M"])
-        dt = (time.perf_counter() - t0) / reps
+            times.append(time.perf_counter() - t0)
+        dt = float(np.median(times))
         st = r.stats
         out[c["name"]] = {
             "n": n, "m": m, "minsup": c["minsup"], "M": c["M"], "ms": dt * 1e3,
