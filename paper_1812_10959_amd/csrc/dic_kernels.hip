@@ -1853,8 +1853,9 @@ __device__ __forceinline__ void candgen_stop(const Job *J, unsigned long long ch
     for (int t = 0; t < KD / 2; ++t)
         sw[t] = 0u;
     if (valid) {
-        const uint32_t q = (uint32_t)(x / nL1);
-        a = (uint32_t)(x % nL1);  // the new item, as a frequent-item index
+        // (32-bit division whenever the index fits: a 64-bit one is far longer)
+        const uint32_t q = x <= 0xFFFFFFFFull ? (uint32_t)x / nL1 : (uint32_t)(x / nL1);
+        a = (uint32_t)x - q * nL1;  // the new item, as a frequent-item index
         p = nb_last[q];
         k = J->pk[p];
         const unsigned long long hS = J->phash[p];
@@ -2022,11 +2023,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     for (unsigned long long it = blockIdx.x; it < total; it += gridDim.x) {
         if (it < ncg) {
             const uint32_t j = find_job(plan->pre_cg, njobs, it);
-            candgen_stop(jobs + j, it - plan->pre_cg[j], tile, sh_app, sh_red, sh_cnt);
+            // job 0's prefix is 0: no load (and no wait for it) on a single job
+            candgen_stop(jobs + j, j ? it - plan->pre_cg[j] : it, tile, sh_app, sh_red, sh_cnt);
         } else {
             const uint32_t v = (uint32_t)(it - ncg);
             const uint32_t j = find_job(plan->pre_countv, njobs, v);
-            survivors_stop(jobs + j, v - plan->pre_countv[j], tile, sh_app, sh_red);
+            survivors_stop(jobs + j, j ? v - plan->pre_countv[j] : v, tile, sh_app, sh_red);
         }
     }
     // Everything the serial part reads from this launch's other workgroups
