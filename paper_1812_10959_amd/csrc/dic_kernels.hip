@@ -863,6 +863,30 @@ __device__ __forceinline__ void settle_and_plan(const Job *__restrict__ jobs, Pl
     }
     if (njobs == 0u)
         return;
+    if (njobs == 1u) {
+        // One job: its serial part runs wave-uniform in wave 0, so the
+        // compiler keeps it in scalar registers on the scalar ALU instead of
+        // one lane's chain of vector instructions.
+        const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        SettleIn in;
+        if (wave == 0u)
+            settle_load(jobs, finish, in);
+        load_tune(plan, tune);
+        __syncthreads();
+        if (wave != 0u)
+            return;
+        uint32_t items = 0, itemsv = 0;
+        unsigned long long chunks = 0;
+        settle_job(jobs, in, finish, begin, tune, &items, &itemsv, &chunks);
+        if (threadIdx.x == 0) {
+            plan->pre_count[1] = items;
+            plan->pre_countv[1] = itemsv;
+            plan->pre_cg[1] = chunks;
+            plan->total_v = itemsv;
+            plan->total_cg = chunks;
+        }
+        return;
+    }
     if (njobs <= 64u) {
         SettleIn in;
         const uint32_t j = threadIdx.x;
@@ -876,16 +900,6 @@ __device__ __forceinline__ void settle_and_plan(const Job *__restrict__ jobs, Pl
         unsigned long long chunks = 0;
         if (j < njobs)
             settle_job(jobs + j, in, finish, begin, tune, &items, &itemsv, &chunks);
-        if (njobs == 1u) {  // one job: its own totals, no sums across lanes
-            if (j == 0) {
-                plan->pre_count[1] = items;
-                plan->pre_countv[1] = itemsv;
-                plan->pre_cg[1] = chunks;
-                plan->total_v = itemsv;
-                plan->total_cg = chunks;
-            }
-            return;
-        }
         // inclusive sums over the wave's lanes
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
