@@ -11,7 +11,8 @@
 //               stops the live candidates certainly still need, so enqueued
 //               stops are not idle;
 //   harvest  -> solid boxes are gathered, sorted canonically and returned;
-//               a job whose pool overflowed is rerun with four times the room.
+//               a job whose pool overflowed is rerun with POOL_GROWTH times
+//               the room (or handed back to its server for that).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -40,7 +41,11 @@ namespace {
 constexpr uint32_t FP_ROWS = 4096;    // rows per first-pass work item (kernel side too)
 constexpr uint32_t FPV_WORDS = 4096;  // bitset words per first-pass work item (kernel side too)
 constexpr uint32_t TRACE_INIT = 512;
-constexpr uint32_t MAX_RESTARTS = 6;
+constexpr uint32_t MAX_RESTARTS = 4;
+// Pool growth after an overflow.  A restart repeats the run from its first
+// stop, so the larger step: a run that needs 256 times the first pool
+// restarts twice instead of four times.
+constexpr uint32_t POOL_GROWTH = 16;
 
 bool canon_less(const uint64_t *A, const uint64_t *B, uint32_t W, uint32_t ka, uint32_t kb)
 {
@@ -953,7 +958,7 @@ int Engine::harvest(std::vector<std::pair<uint64_t, MineOutput>> &done)
             delete a;
         return rc;
     }
-    // rerun overflowed jobs with four times the candidate room (requeue
+    // rerun overflowed jobs with POOL_GROWTH times the candidate room (requeue
     // mode: hand them back to be added again once the room is granted)
     std::vector<ActiveJob *> again;
     for (ActiveJob *a : over) {
@@ -962,7 +967,7 @@ int Engine::harvest(std::vector<std::pair<uint64_t, MineOutput>> &done)
             MineOutput o;
             o.requeue = true;
             o.again = a->req;
-            o.again.mult = a->mult * 4;
+            o.again.mult = a->mult * POOL_GROWTH;
             o.again.restarts = a->restarts + 1;
             o.again.count_ms = a->count_ms;
             o.again.count_launches = a->count_launches;
@@ -982,7 +987,7 @@ int Engine::harvest(std::vector<std::pair<uint64_t, MineOutput>> &done)
         b->id = a->id;
         b->req = a->req;
         b->t0 = a->t0;
-        b->mult = a->mult * 4;
+        b->mult = a->mult * POOL_GROWTH;
         b->layout = a->layout;
         b->classic = a->classic;
         b->restarts = a->restarts + 1;

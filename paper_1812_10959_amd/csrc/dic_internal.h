@@ -41,14 +41,19 @@ enum : uint32_t { LAYOUT_ROWS = 0, LAYOUT_VERTICAL = 1 };
 
 // Words per frequent item in a vertical tile (the tile holds every frequent
 // item's bitset over those words) and the odd row stride that spreads the
-// items' words over the LDS banks.
+// items' words over the LDS banks.  A power of two (16, 8, 4, 2 or 1): the
+// count reads 16-, 8- and 4-word rows whole, without a condition per word.
 __host__ __device__ inline uint32_t vert_tile_words(uint32_t nL1, uint32_t max_words,
                                                     uint32_t capacity = VT_WORDS)
 {
     uint32_t t = nL1 ? capacity / nL1 : (uint32_t)VT_MAXW + 1u;
     t = t > 1u ? t - 1u : 1u;
     const uint32_t cap = max_words < (uint32_t)VT_MAXW ? max_words : (uint32_t)VT_MAXW;
-    return t > cap ? cap : t;
+    t = t > cap ? cap : t;
+    uint32_t p = 1u;
+    while (2u * p <= t)
+        p *= 2u;
+    return p;
 }
 
 // Tuning knobs of the count planning and launch (set by dic_set_option or
@@ -463,7 +468,7 @@ struct ActiveJob;
 // step chunks (their first pass runs at once); every advance() runs up to
 // max_steps stops for all unfinished jobs with one launch per kernel per
 // stop; harvest() hands back finished jobs and releases their memory.  A
-// job whose candidate pool overflowed is restarted with four times the room
+// job whose candidate pool overflowed is restarted with 16 times the room
 // (or handed back for that, in requeue mode).
 // Not thread-safe: one owner thread.
 class Engine {

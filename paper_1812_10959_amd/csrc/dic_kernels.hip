@@ -1314,40 +1314,53 @@ __device__ __forceinline__ void stage_tile(const Job *J, const JobState *st, uin
 }
 
 // Transactions of a staged tile (tw words, words past the block zero) that
-// contain the candidate: the AND of its items' tile rows, popcounted.  With
-// full 16-word tiles and an item list, every word is read without a
-// per-word condition, so each row's loads are issued together.
+// contain the candidate: the AND of its items' tile rows, popcounted.
+// The whole-row form for NW = 16, 8 or 4 words: one item row per iteration
+// (the loop is not unrolled, so no row's loads are hoisted ahead of its
+// turn), its NW words read with no per-word condition and all in flight
+// together; the item list is a queue of 16-bit entries shifted by one item
+// per iteration.
+template <int NW>
+__device__ __forceinline__ uint32_t and_tile_rows(const CandItems &ci, const uint64_t *tile,
+                                                  uint32_t ts)
+{
+    uint64_t acc[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+        acc[w] = ~0ull;
+    uint32_t qv[KD / 2];
+#pragma unroll
+    for (int u = 0; u < KD / 2; ++u)
+        qv[u] = ci.pk32[u];
+#pragma unroll 1
+    for (uint32_t t = 0; t < ci.k; ++t) {
+        const uint64_t *row = tile + (qv[0] & 0xFFFFu) * ts;
+#pragma unroll
+        for (int u = 0; u < KD / 2; ++u)
+            qv[u] = (qv[u] >> 16) | (u + 1 < KD / 2 ? qv[u + 1] << 16 : 0u);
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            acc[w] &= row[w];
+    }
+    uint32_t sum = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+        sum += (uint32_t)__popcll(acc[w]);
+    return sum;
+}
+
+// Any tile: the whole-row forms when the candidate has an item list and the
+// tile a power-of-two width of at least 4 words; otherwise word by word.
 __device__ __forceinline__ uint32_t and_tile_items(const Job *J, const CandItems &ci,
                                                    const uint64_t *tile, uint32_t ts, uint32_t nwt)
 {
-    if (nwt == (uint32_t)VT_MAXW && ci.k <= (uint32_t)KD) {
-        // one item row per iteration (the loop is not unrolled, so no row's
-        // loads are hoisted ahead of its turn): its 16 words are read with no
-        // per-word condition and all in flight together; the item list is a
-        // queue of 16-bit entries shifted by one item per iteration
-        uint64_t acc[VT_MAXW];
-#pragma unroll
-        for (int w = 0; w < VT_MAXW; ++w)
-            acc[w] = ~0ull;
-        uint32_t qv[KD / 2];
-#pragma unroll
-        for (int u = 0; u < KD / 2; ++u)
-            qv[u] = ci.pk32[u];
-#pragma unroll 1
-        for (uint32_t t = 0; t < ci.k; ++t) {
-            const uint64_t *row = tile + (qv[0] & 0xFFFFu) * ts;
-#pragma unroll
-            for (int u = 0; u < KD / 2; ++u)
-                qv[u] = (qv[u] >> 16) | (u + 1 < KD / 2 ? qv[u + 1] << 16 : 0u);
-#pragma unroll
-            for (int w = 0; w < VT_MAXW; ++w)
-                acc[w] &= row[w];
-        }
-        uint32_t sum = 0;
-#pragma unroll
-        for (int w = 0; w < VT_MAXW; ++w)
-            sum += (uint32_t)__popcll(acc[w]);
-        return sum;
+    if (ci.k <= (uint32_t)KD) {
+        if (nwt == 16u)
+            return and_tile_rows<16>(ci, tile, ts);
+        if (nwt == 8u)
+            return and_tile_rows<8>(ci, tile, ts);
+        if (nwt == 4u)
+            return and_tile_rows<4>(ci, tile, ts);
     }
     uint64_t acc[VT_MAXW];
 #pragma unroll
