@@ -341,7 +341,7 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x, uint32_t lane)
 // units, chunk fastest: each XCD walks a contiguous range of rows, and the
 // workgroups that read the same rows (one per chunk) share its L2.
 constexpr uint32_t TR_G = 16;               // row words per tile
-constexpr uint32_t TR_W = 8;                // row-bitmap words per tile (x 64 items)
+constexpr uint32_t TR_W = 4;                // row-bitmap words per tile (x 64 items)
 constexpr uint32_t TR_STRIDE = TR_G + 1;    // LDS words per item (odd: spreads banks)
 constexpr uint32_t N_XCD = 8;
 
