@@ -326,3 +326,21 @@ def test_counts_match_numpy_recount(orc):
     keys = sorted(L)[:: max(1, len(L) // 150)]
     sup = np_support(c["rows"], c["m"], keys)
     assert sup.tolist() == [L[k] for k in keys]
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_openmp_build_matches_serial(orc, threads):
+    """The OpenMP build of the same source (the timed CPU baseline) shares
+    only the per-candidate count loop among threads: every result, statistic
+    and trace entry equals the serial build's."""
+    cases = [(synth.config(1), None)]
+    for seed in (3, 11):
+        rows = synth.uniform_random(1500, 70, 0.2, seed)
+        cases.append(({"rows": rows, "m": 70, "minsup": 0.03, "M": 200}, seed))
+    for c, _ in cases:
+        ref = orc.dic(c["rows"], c["m"], c["minsup"], c["M"])
+        got, used = orc.dic_parallel(c["rows"], c["m"], c["minsup"], c["M"], threads)
+        assert used == threads
+        assert np.array_equal(got.masks, ref.masks) and np.array_equal(got.counts, ref.counts)
+        assert np.array_equal(got.trace, ref.trace)
+        assert got.stats == ref.stats
