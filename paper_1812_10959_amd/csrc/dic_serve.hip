@@ -95,9 +95,11 @@ uint64_t need_of(dic_server *S, const Req *r)
 // Give an admitted request's memory back (called with S->mu held).
 void release(dic_server *S, Req *r)
 {
+    if (!r->admitted)
+        return;
     S->used -= r->bytes;
     auto it = S->resident.find(r->db);
-    if (--it->second == 0) {
+    if (it != S->resident.end() && --it->second == 0) {
         S->used -= db_bytes(r->db);
         S->resident.erase(it);
     }
