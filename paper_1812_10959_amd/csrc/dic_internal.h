@@ -156,7 +156,7 @@ struct JobState {
     uint32_t k_cur;     // survivors of the last stop: the current list, counted at this one
     uint32_t pool_n;    // itemsets in the pool (> cap: overflow)
     uint32_t nL1;       // frequent items
-    uint32_t max_rem;   // most stops a kept candidate still needs (atomic max)
+    uint32_t spare;
     uint32_t parity;    // 1: current list live1, last stop's new boxes newbox1; 0: the others
     uint32_t first;     // block [first, last) of this stop
     uint32_t last;
@@ -204,6 +204,23 @@ constexpr int KD = 16;  // frequent-item indices stored per candidate (larger: d
 // indices.  LREC uint4 words: {p, supp, sc, k | box << 16}, then the items.
 constexpr uint32_t LREC = 3;
 
+// A stop's statistics are summed by the workgroups of its launch into
+// CTR_LINES counter lines per job, 128 bytes apart, each workgroup into the
+// line of its index modulo CTR_LINES, so that no line takes the atomics of
+// every workgroup; the serial part of the launch adds the lines up and
+// clears them.  Words of a line:
+constexpr uint32_t CTR_LINES = 8;
+constexpr uint32_t CTR_STRIDE = 32;  // words between lines
+enum : uint32_t {
+    CTR_WORDS = 0,   // nonzero mask dwords of the counted candidates (row bitmaps)
+    CTR_ITEMS,       // items of the counted candidates
+    CTR_PROMOTED,    // dashed circles promoted to boxes
+    CTR_PRUNED,      // dashed circles erased by the upper bound
+    CTR_SOLID,       // candidates that finished a full pass
+    CTR_MAX_REM,     // most stops a kept candidate still needs (maximum)
+    CTR_FIELDS
+};
+
 // Random word of item a for the Zobrist hash of an itemset, the XOR of its
 // items' words (mining keys items by frequent-item index): output a + 1
 // of the SplitMix64 generator (Steele, Lea & Flood, in Vigna's 64-bit form)
@@ -246,6 +263,7 @@ struct Job {
     unsigned long long *slots;  // open addressing: idx<<32 | fp24<<8 | k8
     uint4 *live0, *live1;       // cap records each (LREC uint4 words per record)
     unsigned long long *pcnt;   // cap: count | arrivals << 32 of a split group (zero between stops)
+    uint32_t *ctrs;             // CTR_LINES * CTR_STRIDE: the stop's statistics (zero between stops)
     uint32_t *newbox0, *newbox1;  // cap each: boxes promoted at a stop (by parity)
     uint32_t *l1;               // m
     uint32_t *item_cnt;         // m
@@ -291,8 +309,8 @@ inline uint64_t pool_cap_for(uint32_t nL1, uint32_t mult)
 
 // Layout of a job's candidate pool buffer (byte offsets of its arrays).
 struct PoolLayout {
-    size_t mask, items, hash, nz, supp, state, k, slots, live0, live1, pcnt, newbox0, newbox1,
-        omask, ocnt, okey;
+    size_t mask, items, hash, nz, supp, state, k, slots, live0, live1, pcnt, ctrs, newbox0,
+        newbox1, omask, ocnt, okey;
     size_t bytes;
     uint64_t hslots;
     PoolLayout(uint64_t cap, uint32_t W)
@@ -310,6 +328,7 @@ struct PoolLayout {
         live0 = c.take(cap * LREC * 16);
         live1 = c.take(cap * LREC * 16);
         pcnt = c.take(cap * 8);
+        ctrs = c.take(CTR_LINES * CTR_STRIDE * 4);
         newbox0 = c.take(cap * 4);
         newbox1 = c.take(cap * 4);
         omask = c.take(cap * W * 8);
@@ -354,6 +373,7 @@ inline void pool_assign(Job &J, const PoolLayout &L, char *b, uint32_t cap)
     J.live0 = (uint4 *)(b + L.live0);
     J.live1 = (uint4 *)(b + L.live1);
     J.pcnt = (unsigned long long *)(b + L.pcnt);
+    J.ctrs = (uint32_t *)(b + L.ctrs);
     J.newbox0 = (uint32_t *)(b + L.newbox0);
     J.newbox1 = (uint32_t *)(b + L.newbox1);
     J.out_mask = (uint64_t *)(b + L.omask);

@@ -73,12 +73,6 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *ctr, bool pred, bool u
     return pred ? atomicAdd(ctr, 1u) : 0u;
 }
 
-__device__ __forceinline__ dic_stop_trace *trace_of(const Job *J, const JobState *st)
-{
-    uint32_t e = st->epoch;
-    return (e >= 1 && e - 1 < J->trace_cap) ? J->trace + (e - 1) : nullptr;
-}
-
 // A candidate's frequent-item indices (ascending, KD x u16) as 8 words.
 __device__ __forceinline__ void load_items(const uint16_t *pi, uint32_t w[KD / 2])
 {
@@ -472,7 +466,6 @@ __global__ __launch_bounds__(WG) void k_l1(const Job *__restrict__ jobs)
             st->pending = 1;
             st->pool_base = 0;
             st->pool_n = J->m;
-            st->max_rem = 0;
         }
         return;
     }
@@ -495,7 +488,6 @@ __global__ __launch_bounds__(WG) void k_l1(const Job *__restrict__ jobs)
         st->pending = 1;
         st->pool_base = 0;
         st->pool_n = (uint32_t)nC2;
-        st->max_rem = 0;
     }
 }
 
@@ -711,7 +703,8 @@ __device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const PlanT
 // Loaded ahead of the knobs' copy, so that both are in flight together.
 struct SettleIn {
     JobState s;
-    uint32_t pn, mr, asserts;
+    uint32_t pn, asserts;
+    uint32_t ctr[CTR_FIELDS];  // the counter lines added up (CTR_MAX_REM: their maximum)
     unsigned long long kn_nn;
 };
 
@@ -723,8 +716,22 @@ __device__ __forceinline__ void settle_load(const Job *J, bool finish, SettleIn 
         in.pn = __hip_atomic_load(&stp->pool_n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         in.kn_nn = __hip_atomic_load((unsigned long long *)&stp->k_next, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT);
-        in.mr = __hip_atomic_load(&stp->max_rem, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         in.asserts = __hip_atomic_load(&stp->asserts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t c[CTR_LINES][CTR_FIELDS];
+#pragma unroll
+        for (uint32_t l = 0; l < CTR_LINES; ++l)
+#pragma unroll
+            for (uint32_t f = 0; f < CTR_FIELDS; ++f)
+                c[l][f] = __hip_atomic_load(J->ctrs + l * CTR_STRIDE + f, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (uint32_t f = 0; f < CTR_FIELDS; ++f) {
+            uint32_t t = c[0][f];
+#pragma unroll
+            for (uint32_t l = 1; l < CTR_LINES; ++l)
+                t = f == CTR_MAX_REM ? (c[l][f] > t ? c[l][f] : t) : t + c[l][f];
+            in.ctr[f] = t;
+        }
     }
 }
 
@@ -739,8 +746,14 @@ __device__ __forceinline__ void settle_job(const Job *J, const SettleIn &in, boo
         write = true;
         const uint32_t pn = in.pn;
         const unsigned long long kn_nn = in.kn_nn;
-        const uint32_t mr = in.mr;
+        const uint32_t mr = in.ctr[CTR_MAX_REM];
         s.asserts = in.asserts;
+        // the counter lines start the next stop at zero (read by its launch)
+#pragma unroll
+        for (uint32_t l = 0; l < CTR_LINES; ++l)
+#pragma unroll
+            for (uint32_t f = 0; f < CTR_FIELDS; ++f)
+                J->ctrs[l * CTR_STRIDE + f] = 0u;
         const uint32_t kn = (uint32_t)kn_nn, nn = (uint32_t)(kn_nn >> 32);
         const uint32_t E = s.epoch;
         s.pool_n = pn;
@@ -766,6 +779,11 @@ __device__ __forceinline__ void settle_job(const Job *J, const SettleIn &in, boo
                     t->stop = s.stop;
                     t->rows = rows;
                     t->live = live;
+                    t->words = in.ctr[CTR_WORDS];
+                    t->items = in.ctr[CTR_ITEMS];
+                    t->promoted = in.ctr[CTR_PROMOTED];
+                    t->pruned = in.ctr[CTR_PRUNED];
+                    t->solidified = in.ctr[CTR_SOLID];
                 }
                 if (kn == 0u && nn == 0u) {  // no survivor and no new box: DASHED stays empty
                     s.done = 1;
@@ -784,7 +802,6 @@ __device__ __forceinline__ void settle_job(const Job *J, const SettleIn &in, boo
         }
         s.k_next = 0;
         s.n_new = 0;
-        s.max_rem = 0;
     } else if (begin && s.pending && !s.done && !s.overflow) {
         // first stop: the first candidates (pool entries 0..pn-1, already in
         // live1) are the current list, counted like survivors
@@ -794,7 +811,6 @@ __device__ __forceinline__ void settle_job(const Job *J, const SettleIn &in, boo
         s.n_prev = 0;
         s.k_next = 0;
         s.n_new = 0;
-        s.max_rem = 0;
         s.pool_base = pn;
         s.parity = 1;
         s.stop = 0;
@@ -1315,37 +1331,50 @@ __device__ __forceinline__ void stage_tile(const Job *J, const JobState *st, uin
 
 // Transactions of a staged tile (tw words, words past the block zero) that
 // contain the candidate: the AND of its items' tile rows, popcounted.
-// The whole-row form for NW = 16, 8 or 4 words: one item row per iteration
-// (the loop is not unrolled, so no row's loads are hoisted ahead of its
-// turn), its NW words read with no per-word condition and all in flight
-// together; the item list is a queue of 16-bit entries shifted by one item
-// per iteration.
+// The whole-row form for NW = 16, 8 or 4 words, in passes of at most eight
+// words: the first item's words start the AND, and each further item's
+// eight words are read together (all in flight, one wait) before they are
+// ANDed.  (One accumulator per word of the whole row left room for only one
+// read in flight, and a row cost eight LDS round trips.)  The item loop is
+// not unrolled; the item list is a queue of 16-bit entries shifted by one
+// item per iteration.
 template <int NW>
 __device__ __forceinline__ uint32_t and_tile_rows(const CandItems &ci, const uint64_t *tile,
                                                   uint32_t ts)
 {
-    uint64_t acc[NW];
-#pragma unroll
-    for (int w = 0; w < NW; ++w)
-        acc[w] = ~0ull;
-    uint32_t qv[KD / 2];
-#pragma unroll
-    for (int u = 0; u < KD / 2; ++u)
-        qv[u] = ci.pk32[u];
-#pragma unroll 1
-    for (uint32_t t = 0; t < ci.k; ++t) {
-        const uint64_t *row = tile + (qv[0] & 0xFFFFu) * ts;
-#pragma unroll
-        for (int u = 0; u < KD / 2; ++u)
-            qv[u] = (qv[u] >> 16) | (u + 1 < KD / 2 ? qv[u + 1] << 16 : 0u);
-#pragma unroll
-        for (int w = 0; w < NW; ++w)
-            acc[w] &= row[w];
-    }
+    constexpr int H = NW < 8 ? NW : 8;
     uint32_t sum = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w)
-        sum += (uint32_t)__popcll(acc[w]);
+    for (int h = 0; h < NW; h += H) {
+        uint32_t qv[KD / 2];
+#pragma unroll
+        for (int u = 0; u < KD / 2; ++u)
+            qv[u] = ci.pk32[u];
+        uint64_t acc[H];
+        {
+            const uint64_t *row = tile + (qv[0] & 0xFFFFu) * ts + h;
+#pragma unroll
+            for (int w = 0; w < H; ++w)
+                acc[w] = row[w];
+        }
+#pragma unroll 1
+        for (uint32_t t = 1; t < ci.k; ++t) {
+#pragma unroll
+            for (int u = 0; u < KD / 2; ++u)
+                qv[u] = (qv[u] >> 16) | (u + 1 < KD / 2 ? qv[u + 1] << 16 : 0u);
+            const uint64_t *row = tile + (qv[0] & 0xFFFFu) * ts + h;
+            uint64_t v[H];
+#pragma unroll
+            for (int w = 0; w < H; ++w)
+                v[w] = row[w];
+#pragma unroll
+            for (int w = 0; w < H; ++w)
+                acc[w] &= v[w];
+        }
+#pragma unroll
+        for (int w = 0; w < H; ++w)
+            sum += (uint32_t)__popcll(acc[w]);
+    }
     return sum;
 }
 
@@ -1501,24 +1530,16 @@ __device__ __forceinline__ void prune_core(const Job *J, JobState *st, LRec (&r)
         if (promoted[q])
             nbox[npos[q]] = r[q].p;
     }
-    uint32_t v[6] = {nwords, nitems, npro, npru, nsol, rem};
+    uint32_t v[6] = {nwords, nitems, npro, npru, nsol, rem};  // in CTR_* order
     block_reduce<5>(v, sh_red);
     if (threadIdx.x == 0) {
-        dic_stop_trace *tr = trace_of(J, st);
-        if (tr) {
-            if (v[0])
-                atomicAdd(&tr->words, v[0]);
-            if (v[1])
-                atomicAdd(&tr->items, v[1]);
-            if (v[2])
-                atomicAdd(&tr->promoted, v[2]);
-            if (v[3])
-                atomicAdd(&tr->pruned, v[3]);
-            if (v[4])
-                atomicAdd(&tr->solidified, v[4]);
-        }
+        uint32_t *c = J->ctrs + (blockIdx.x & (CTR_LINES - 1u)) * CTR_STRIDE;
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            if (v[i])
+                atomicAdd(c + i, v[i]);
         if (v[5])
-            atomicMax(&st->max_rem, v[5]);
+            atomicMax(c + CTR_MAX_REM, v[5]);
     }
 }
 
@@ -2059,10 +2080,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         }
     }
     // Everything the serial part reads from this launch's other workgroups
-    // is a device-scope atomic (pool_n, k_next/n_new, max_rem, asserts) and
-    // is read with device-scope atomic loads.  The returning ones have
-    // completed before their results were used; the no-return ones (max_rem,
-    // asserts) are waited for here, in every wave, so that all of this
+    // is a device-scope atomic (pool_n, k_next/n_new, asserts, the counter
+    // lines) and is read with device-scope atomic loads.  The returning ones
+    // have completed before their results were used; the no-return ones (the
+    // counter lines, asserts) are waited for here, in every wave, so that all of this
     // workgroup's updates are done before its arrival is counted (a
     // workgroup barrier alone does not wait for memory operations).  Plain
     // stores of this launch (records, standings, counts) are read only by
