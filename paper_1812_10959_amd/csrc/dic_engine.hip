@@ -561,7 +561,7 @@ int Engine::add_impl(std::vector<ActiveJob *> &fresh)
         }
         HIP_TRY(hipMemsetAsync(J.slots, 0xFF, L.hslots * 8, s_));
         HIP_TRY(hipMemsetAsync(J.pcnt, 0, (size_t)cap * 8, s_));
-        HIP_TRY(hipMemsetAsync(J.ctrs, 0, CTR_LINES * CTR_STRIDE * 4, s_));
+        HIP_TRY(hipMemsetAsync(J.ctrs, 0, CTR_TOTAL * 4, s_));
         aux_host_[i] = J;
     }
     // first candidates: pairs of frequent items (nL1 x nL1 work), or every

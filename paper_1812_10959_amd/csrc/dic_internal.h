@@ -149,12 +149,9 @@ struct JobState {
     uint32_t overflow;  // candidate pool capacity exceeded
     uint32_t stop;      // block index 1..stop_max of the current stop (0 before the first)
     uint32_t epoch;     // index of the current stop (from 1); promotions are tagged with it
-    // survivors appended to the next live list and boxes promoted at this
-    // stop: one 64-bit word so that a workgroup reserves both with one atomic
-    uint32_t k_next;
-    uint32_t n_new;
+    uint32_t spare0, spare1;
     uint32_t k_cur;     // survivors of the last stop: the current list, counted at this one
-    uint32_t pool_n;    // itemsets in the pool (> cap: overflow)
+    uint32_t pool_n;    // itemsets in the pool after the last stop (> cap: overflow)
     uint32_t nL1;       // frequent items
     uint32_t spare;
     uint32_t parity;    // 1: current list live1, last stop's new boxes newbox1; 0: the others
@@ -179,7 +176,6 @@ struct JobState {
     uint32_t pad[2];
 };
 static_assert(sizeof(JobState) == 128, "JobState is read back as 128-byte records");
-static_assert(offsetof(JobState, k_next) % 8 == 0, "k_next/n_new form one 64-bit word");
 
 // Between chunks of stops a job is either pending (added, its first stop
 // not begun; it runs if it has first candidates) or begun on its next stop.
@@ -204,13 +200,23 @@ constexpr int KD = 16;  // frequent-item indices stored per candidate (larger: d
 // indices.  LREC uint4 words: {p, supp, sc, k | box << 16}, then the items.
 constexpr uint32_t LREC = 3;
 
-// A stop's statistics are summed by the workgroups of its launch into
-// CTR_LINES counter lines per job, 128 bytes apart, each workgroup into the
-// line of its index modulo CTR_LINES, so that no line takes the atomics of
-// every workgroup; the serial part of the launch adds the lines up and
-// clears them.  Words of a line:
+// The counters that the workgroups of a stop's launch update with atomics
+// live in lines of their own, 128 bytes apart, away from the job state that
+// every work item reads (an atomic on a line holds up the reads of that
+// line).  The stop's statistics are summed into CTR_LINES lines, each
+// workgroup into the line of its index modulo CTR_LINES, so that no line
+// takes the atomics of every workgroup; two more lines hold the list
+// appends and the pool growth.  The serial part of the launch reads and
+// clears them all.  Words of a statistics line:
 constexpr uint32_t CTR_LINES = 8;
 constexpr uint32_t CTR_STRIDE = 32;  // words between lines
+// records appended to the next live list (low word) and to the next
+// new-box list (high word) at this stop: one 64-bit word, so that a
+// workgroup reserves both with one atomic
+constexpr uint32_t CTR_APPEND = CTR_LINES * CTR_STRIDE;
+// pool entries made at this stop (they follow pool_base)
+constexpr uint32_t CTR_GEN = (CTR_LINES + 1) * CTR_STRIDE;
+constexpr uint32_t CTR_TOTAL = (CTR_LINES + 2) * CTR_STRIDE;  // words
 enum : uint32_t {
     CTR_WORDS = 0,   // nonzero mask dwords of the counted candidates (row bitmaps)
     CTR_ITEMS,       // items of the counted candidates
@@ -263,7 +269,7 @@ struct Job {
     unsigned long long *slots;  // open addressing: idx<<32 | fp24<<8 | k8
     uint4 *live0, *live1;       // cap records each (LREC uint4 words per record)
     unsigned long long *pcnt;   // cap: count | arrivals << 32 of a split group (zero between stops)
-    uint32_t *ctrs;             // CTR_LINES * CTR_STRIDE: the stop's statistics (zero between stops)
+    uint32_t *ctrs;             // CTR_TOTAL: the stop's counters (zero between stops)
     uint32_t *newbox0, *newbox1;  // cap each: boxes promoted at a stop (by parity)
     uint32_t *l1;               // m
     uint32_t *item_cnt;         // m
@@ -328,7 +334,7 @@ struct PoolLayout {
         live0 = c.take(cap * LREC * 16);
         live1 = c.take(cap * LREC * 16);
         pcnt = c.take(cap * 8);
-        ctrs = c.take(CTR_LINES * CTR_STRIDE * 4);
+        ctrs = c.take(CTR_TOTAL * 4);
         newbox0 = c.take(cap * 4);
         newbox1 = c.take(cap * 4);
         omask = c.take(cap * W * 8);

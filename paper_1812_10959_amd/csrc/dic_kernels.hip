@@ -689,6 +689,11 @@ __device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const PlanT
     }
 }
 
+// s_waitcnt operand (gfx9 encoding) that waits for every outstanding vector
+// memory operation of the wave -- loads, stores and atomics -- and for
+// nothing else: vmcnt 0, expcnt 7, lgkmcnt 15.
+constexpr int WAIT_VM0 = 0x0F70;
+
 // One job's turn in the serial part of a launch: complete stop e (finish:
 // after every work item of the stop kernel) or begin the first stop of a
 // job added since the last chunk (begin: in k_begin), then plan the next
@@ -705,6 +710,7 @@ struct SettleIn {
     JobState s;
     uint32_t pn, asserts;
     uint32_t ctr[CTR_FIELDS];  // the counter lines added up (CTR_MAX_REM: their maximum)
+    bool lines_done;           // the lines are cleared already
     unsigned long long kn_nn;
 };
 
@@ -712,10 +718,12 @@ __device__ __forceinline__ void settle_load(const Job *J, bool finish, SettleIn 
 {
     JobState *stp = J->st;
     __builtin_memcpy(&in.s, stp, sizeof(JobState));
+    in.lines_done = false;
     if (finish) {
-        in.pn = __hip_atomic_load(&stp->pool_n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        in.kn_nn = __hip_atomic_load((unsigned long long *)&stp->k_next, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
+        in.pn = in.s.pool_base + __hip_atomic_load(J->ctrs + CTR_GEN, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        in.kn_nn = __hip_atomic_load((const unsigned long long *)(J->ctrs + CTR_APPEND),
+                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         in.asserts = __hip_atomic_load(&stp->asserts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t c[CTR_LINES][CTR_FIELDS];
 #pragma unroll
@@ -735,6 +743,53 @@ __device__ __forceinline__ void settle_load(const Job *J, bool finish, SettleIn 
     }
 }
 
+// The finishing form of settle_load for one job, by every lane of one wave:
+// lane l < CTR_LINES reads statistics line l and clears it, and the lines
+// are added up with shuffles.
+__device__ __forceinline__ void settle_load_wave(const Job *J, SettleIn &in)
+{
+    JobState *stp = J->st;
+    __builtin_memcpy(&in.s, stp, sizeof(JobState));
+    in.pn = in.s.pool_base + __hip_atomic_load(J->ctrs + CTR_GEN, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    in.kn_nn = __hip_atomic_load((const unsigned long long *)(J->ctrs + CTR_APPEND),
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    in.asserts = __hip_atomic_load(&stp->asserts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t lane = lane_id();
+    uint32_t v[CTR_FIELDS];
+#pragma unroll
+    for (uint32_t f = 0; f < CTR_FIELDS; ++f)
+        v[f] = 0u;
+    if (lane < CTR_LINES) {
+#pragma unroll
+        for (uint32_t f = 0; f < CTR_FIELDS; ++f)
+            v[f] = __hip_atomic_load(J->ctrs + lane * CTR_STRIDE + f, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // every counter starts the next stop at zero (read by its launch); the
+    // loads above have returned before the lines are cleared
+    __builtin_amdgcn_s_waitcnt(WAIT_VM0);
+    if (lane < CTR_LINES) {
+        uint4 *line = (uint4 *)(J->ctrs + lane * CTR_STRIDE);
+        line[0] = line[1] = make_uint4(0u, 0u, 0u, 0u);  // words 0..7
+    } else if (lane == CTR_LINES) {
+        *(unsigned long long *)(J->ctrs + CTR_APPEND) = 0ull;
+        J->ctrs[CTR_GEN] = 0u;
+    }
+    // totals over lanes 0..CTR_LINES-1 (the other lanes hold zeros)
+#pragma unroll
+    for (int off = 1; off < (int)CTR_LINES; off <<= 1)
+#pragma unroll
+        for (uint32_t f = 0; f < CTR_FIELDS; ++f) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)v[f], off);
+            v[f] = f == CTR_MAX_REM ? (o > v[f] ? o : v[f]) : v[f] + o;
+        }
+#pragma unroll
+    for (uint32_t f = 0; f < CTR_FIELDS; ++f)
+        in.ctr[f] = __builtin_amdgcn_readfirstlane(v[f]);
+    in.lines_done = true;
+}
+
 __device__ __forceinline__ void settle_job(const Job *J, const SettleIn &in, bool finish,
                                            bool begin, const PlanTune *tune, uint32_t *items_rows,
                                            uint32_t *items_stop, unsigned long long *chunks)
@@ -748,12 +803,16 @@ __device__ __forceinline__ void settle_job(const Job *J, const SettleIn &in, boo
         const unsigned long long kn_nn = in.kn_nn;
         const uint32_t mr = in.ctr[CTR_MAX_REM];
         s.asserts = in.asserts;
-        // the counter lines start the next stop at zero (read by its launch)
+        if (!in.lines_done) {
+            // the counters start the next stop at zero (read by its launch)
 #pragma unroll
-        for (uint32_t l = 0; l < CTR_LINES; ++l)
+            for (uint32_t l = 0; l < CTR_LINES; ++l)
 #pragma unroll
-            for (uint32_t f = 0; f < CTR_FIELDS; ++f)
-                J->ctrs[l * CTR_STRIDE + f] = 0u;
+                for (uint32_t f = 0; f < CTR_FIELDS; ++f)
+                    J->ctrs[l * CTR_STRIDE + f] = 0u;
+            *(unsigned long long *)(J->ctrs + CTR_APPEND) = 0ull;
+            J->ctrs[CTR_GEN] = 0u;
+        }
         const uint32_t kn = (uint32_t)kn_nn, nn = (uint32_t)(kn_nn >> 32);
         const uint32_t E = s.epoch;
         s.pool_n = pn;
@@ -800,8 +859,6 @@ __device__ __forceinline__ void settle_job(const Job *J, const SettleIn &in, boo
                 }
             }
         }
-        s.k_next = 0;
-        s.n_new = 0;
     } else if (begin && s.pending && !s.done && !s.overflow) {
         // first stop: the first candidates (pool entries 0..pn-1, already in
         // live1) are the current list, counted like survivors
@@ -809,8 +866,6 @@ __device__ __forceinline__ void settle_job(const Job *J, const SettleIn &in, boo
         const uint32_t pn = s.pool_n < J->cap ? s.pool_n : J->cap;
         s.k_cur = pn;
         s.n_prev = 0;
-        s.k_next = 0;
-        s.n_new = 0;
         s.pool_base = pn;
         s.parity = 1;
         s.stop = 0;
@@ -823,11 +878,6 @@ __device__ __forceinline__ void settle_job(const Job *J, const SettleIn &in, boo
     if (write || (!s.done && !s.overflow && !s.pending))
         __builtin_memcpy(stp, &s, sizeof(JobState));
 }
-
-// s_waitcnt operand (gfx9 encoding) that waits for every outstanding vector
-// memory operation of the wave -- loads, stores and atomics -- and for
-// nothing else: vmcnt 0, expcnt 7, lgkmcnt 15.
-constexpr int WAIT_VM0 = 0x0F70;
 
 // Arrival counter of a launch, called by one thread per workgroup after the
 // workgroup's work: true for the workgroup that arrives last.  Only the
@@ -885,8 +935,12 @@ __device__ __forceinline__ void settle_and_plan(const Job *__restrict__ jobs, Pl
         // one lane's chain of vector instructions.
         const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         SettleIn in;
-        if (wave == 0u)
-            settle_load(jobs, finish, in);
+        if (wave == 0u) {
+            if (finish)
+                settle_load_wave(jobs, in);
+            else
+                settle_load(jobs, false, in);
+        }
         load_tune(plan, tune);
         __syncthreads();
         if (wave != 0u)
@@ -1522,7 +1576,7 @@ __device__ __forceinline__ void prune_core(const Job *J, JobState *st, LRec (&r)
     uint4 *next = st->parity ? J->live0 : J->live1;
     uint32_t *nbox = st->parity ? J->newbox0 : J->newbox1;
     uint32_t pos[NQ], npos[NQ];
-    block_append2_rounds<NQ>(&st->k_next, keep, promoted, sh_app, pos, npos);
+    block_append2_rounds<NQ>(J->ctrs + CTR_APPEND, keep, promoted, sh_app, pos, npos);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         if (keep[q])
@@ -1942,11 +1996,13 @@ __device__ __forceinline__ void candgen_stop(const Job *J, unsigned long long ch
             gen = subsets_are_boxes_wide(J, p, k, a, hC, base, E);
         }
     }
-    // New entries are pool slots [pool_base, pool_n).  Lookups in this
-    // launch never read them (see probe_list), so no fence is needed before
-    // publishing them in the hash table.
+    // New entries are pool slots from pool_base on, counted in the stop's
+    // pool-growth counter.  Lookups in this launch never read them (see
+    // probe_list), so no fence is needed before publishing them in the hash
+    // table.
     uint32_t wg_base, rank, g;
-    block_append_rank(&st->pool_n, gen, sh_app, &wg_base, &rank, &g);
+    block_append_rank(J->ctrs + CTR_GEN, gen, sh_app, &wg_base, &rank, &g);
+    wg_base += base;
     const uint32_t np = wg_base + rank;
     const bool stored = gen && np < J->cap;
     const uint32_t kc = k + 1u;
@@ -2080,8 +2136,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         }
     }
     // Everything the serial part reads from this launch's other workgroups
-    // is a device-scope atomic (pool_n, k_next/n_new, asserts, the counter
-    // lines) and is read with device-scope atomic loads.  The returning ones
+    // is a device-scope atomic (the counter lines: pool growth, list
+    // appends, statistics; asserts) and is read with device-scope atomic
+    // loads.  The returning ones
     // have completed before their results were used; the no-return ones (the
     // counter lines, asserts) are waited for here, in every wave, so that all of this
     // workgroup's updates are done before its arrival is counted (a

@@ -230,7 +230,7 @@ int mine_once(char *base, hipStream_t s, const MineRequest &req, uint32_t layout
         J.fvert = (uint64_t *)(base + o_fvert);
     launch_fill32((uint32_t *)J.slots, 0xFFFFFFFFu, 2 * L.hslots, s);
     launch_fill32((uint32_t *)J.pcnt, 0u, 2 * cap, s);
-    launch_fill32(J.ctrs, 0u, CTR_LINES * CTR_STRIDE, s);
+    launch_fill32(J.ctrs, 0u, CTR_TOTAL, s);
     NA_TRY(hipMemcpyAsync(d_job, &J, sizeof(Job), hipMemcpyHostToDevice, s));
     R.pre_cg[0] = 0;
     R.pre_cg[1] = classic ? (unsigned long long)nL1 : (unsigned long long)nL1 * nL1;
