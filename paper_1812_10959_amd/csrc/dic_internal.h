@@ -196,9 +196,11 @@ constexpr int KD = 16;  // frequent-item indices stored per candidate (larger: d
 // A live candidate travels between stops as a record in the live lists, so
 // that a stop reads everything it needs of a candidate with one load: its
 // pool entry, its support and the stops it has been counted on so far, its
-// size and whether it is a box already, and (size <= KD) its frequent-item
-// indices.  LREC uint4 words: {p, supp, sc, k | box << 16}, then the items.
-constexpr uint32_t LREC = 3;
+// size and whether it is a box already, and (size <= KR) its frequent-item
+// indices (larger itemsets' lists are read from the pool).  LREC uint4
+// words: {p, supp, sc, k | box << 16}, then KR 16-bit items.
+constexpr uint32_t LREC = 2;
+constexpr int KR = 8;
 
 // The counters that the workgroups of a stop's launch update with atomics
 // live in lines of their own, 128 bytes apart, away from the job state that

@@ -521,7 +521,6 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
             uint4 *r = J->live1 + (uint64_t)a * LREC;  // the first stop's current list
             r[0] = make_uint4(a, 0u, 0u, 1u);
             r[1] = make_uint4(a, 0u, 0u, 0u);
-            r[2] = make_uint4(0u, 0u, 0u, 0u);
             hash_insert(J, zob(a), 1, a);
             continue;
         }
@@ -547,7 +546,6 @@ __global__ __launch_bounds__(WG) void k_init_pairs(const Job *__restrict__ jobs,
         uint4 *r = J->live1 + (uint64_t)p * LREC;  // the first stop's current list
         r[0] = make_uint4(p, 0u, 0u, 2u);
         r[1] = make_uint4(a | (b << 16), 0u, 0u, 0u);
-        r[2] = make_uint4(0u, 0u, 0u, 0u);
         // no hash entry: outside the classic start a pair is only ever looked
         // up by its index (MakeCandidates' 2-subsets); larger itemsets and
         // the classic start's pairs go through the hash table
@@ -1194,17 +1192,16 @@ __device__ __forceinline__ CandItems cand_items(const Job *J, uint32_t p)
 // A live record (see LREC) in registers.
 struct LRec {
     uint32_t p, supp, sc, kb;  // kb: size | box << 16
-    uint32_t it[KD / 2];
+    uint32_t it[KR / 2];
 };
 
 __device__ __forceinline__ LRec load_rec(const uint4 *list, uint32_t c)
 {
     const uint4 *r = list + (uint64_t)c * LREC;
-    const uint4 a = r[0], b = r[1], d = r[2];
+    const uint4 a = r[0], b = r[1];
     LRec x;
     x.p = a.x; x.supp = a.y; x.sc = a.z; x.kb = a.w;
     x.it[0] = b.x; x.it[1] = b.y; x.it[2] = b.z; x.it[3] = b.w;
-    x.it[4] = d.x; x.it[5] = d.y; x.it[6] = d.z; x.it[7] = d.w;
     return x;
 }
 
@@ -1213,10 +1210,11 @@ __device__ __forceinline__ void store_rec(uint4 *list, uint32_t c, const LRec &x
     uint4 *r = list + (uint64_t)c * LREC;
     r[0] = make_uint4(x.p, x.supp, x.sc, x.kb);
     r[1] = make_uint4(x.it[0], x.it[1], x.it[2], x.it[3]);
-    r[2] = make_uint4(x.it[4], x.it[5], x.it[6], x.it[7]);
 }
 
-__device__ __forceinline__ CandItems rec_items(const LRec &x)
+// A record's item list: from the record up to KR items, from the pool up
+// to KD, none (the mask is decoded instead) above.
+__device__ __forceinline__ CandItems rec_items(const Job *J, const LRec &x)
 {
     CandItems ci;
     ci.k = x.kb & 0xFFFFu;
@@ -1224,7 +1222,13 @@ __device__ __forceinline__ CandItems rec_items(const LRec &x)
     ci.extra = NONE;
 #pragma unroll
     for (int t = 0; t < KD / 2; ++t)
-        ci.pk32[t] = x.it[t];
+        ci.pk32[t] = t < KR / 2 ? x.it[t] : 0u;
+    if (ci.k > (uint32_t)KR && ci.k <= (uint32_t)KD) {
+        const uint4 *ip = (const uint4 *)(J->pitems + (uint64_t)x.p * KD);
+        const uint4 h0 = ip[0], h1 = ip[1];
+        ci.pk32[0] = h0.x; ci.pk32[1] = h0.y; ci.pk32[2] = h0.z; ci.pk32[3] = h0.w;
+        ci.pk32[4] = h1.x; ci.pk32[5] = h1.y; ci.pk32[6] = h1.z; ci.pk32[7] = h1.w;
+    }
     return ci;
 }
 
@@ -1641,7 +1645,7 @@ __device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uin
         r[0] = LRec{};
         if (c < K) {
             r[0] = load_rec(cur, __builtin_amdgcn_readfirstlane(c));
-            const uint32_t cnt = count_wave_bitsets(J, st, rec_items(r[0]));
+            const uint32_t cnt = count_wave_bitsets(J, st, rec_items(J, r[0]));
             r[0].supp += cnt;
             r[0].sc += 1u;
             valid[0] = (threadIdx.x & 63u) == 0u;  // the wave's first lane prunes it
@@ -1678,7 +1682,7 @@ __device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uin
 #pragma unroll 1
         for (int q = 0; q < VT_CPT; ++q) {
             if (valid[0])
-                cnt[0] += and_tile_items(J, rec_items(r[0]), tile, ts, tw);
+                cnt[0] += and_tile_items(J, rec_items(J, r[0]), tile, ts, tw);
             const LRec r0 = r[0];
             const bool v0 = valid[0];
             const uint32_t c0 = cnt[0];
@@ -2098,8 +2102,8 @@ __device__ __forceinline__ void candgen_stop(const Job *J, unsigned long long ch
     r[0].sc = 1u;
     r[0].kb = kc;
 #pragma unroll
-    for (int u = 0; u < KD / 2; ++u)
-        r[0].it[u] = cw[u];
+    for (int u = 0; u < KR / 2; ++u)
+        r[0].it[u] = cw[u];  // larger itemsets' lists are read from the pool
     bool ok[1] = {stored};
     uint32_t words[1] = {stored && !vert ? mask_dwords(J, p, J->l1[a]) : 0u};
     if (stored && !vert)
