@@ -162,6 +162,19 @@ def test_edge_cases(dic, orc):
         mine_both(dic, orc, rows, m, 0.2, 17, f"m={m}")
 
 
+def test_itemsets_of_every_record_form(dic, orc):
+    """A live record carries up to 8 items; lists of 9 to 16 items are read
+    from the pool and larger itemsets are counted from their masks.  Every
+    subset of a 17-item pattern is frequent here (131,071 itemsets, sizes 1
+    to 17), so all three forms are counted and pruned at many stops."""
+    rows = pack([list(range(17))] * 4 + [[0, 1], [2, 3, 4], [17, 18]], 20)
+    g = mine_both(dic, orc, rows, 20, 0.5, 2, "17-item pattern")
+    assert g.stats["k_max"] == 17 and len(g.counts) == 131071
+    rows = pack([list(range(3, 23))] * 3 + [[1, 2]] * 2, 30)
+    g = mine_both(dic, orc, rows, 30, 0.6, 1, "20-item pattern, M=1")
+    assert g.stats["k_max"] == 20
+
+
 def test_load_paths_agree(dic, orc):
     rows = synth.uniform_random(500, 150, 0.07, 21)
     items, offs = synth.bitmap_to_csr(rows, 150)
