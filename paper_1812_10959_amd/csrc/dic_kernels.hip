@@ -218,15 +218,29 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh)
 }
 
 // NQ rounds of two workgroup-aggregated appends (ctr points at a pair of
-// adjacent u32 counters, low word first; pa / pb receive the slots of threads
-// whose a / b is true), in round order, with one 64-bit atomic for the
-// workgroup.  sh holds 2 * NQ * (WG/64) + 2 words.
-template <int NQ>
-__device__ __forceinline__ void block_append2_rounds(uint32_t *ctr, const bool (&a)[NQ], const bool (&b)[NQ],
-                                     uint32_t *sh, uint32_t (&pa)[NQ], uint32_t (&pb)[NQ])
+// adjacent u32 counters, low word first; pa / pb receive the slots of
+// threads whose a / b is true), in round order, with one 64-bit atomic for
+// the workgroup; and, in the same exchange, the workgroup's sums of NS
+// statistics and maximum of one more (st, per thread), which thread 0 adds
+// to counter line `line` right after the append atomic.  Each wave reduces
+// its statistics with shuffles before the one barrier that the appends
+// need anyway (a separate reduction cost a barrier and an LDS pass more).
+// sh holds 2 * NQ * (WG/64) + 2 + (NS + 1) * (WG/64) words.
+template <int NQ, int NS>
+__device__ __forceinline__ void block_append2_stats(uint32_t *ctr, const bool (&a)[NQ],
+                                                    const bool (&b)[NQ], uint32_t (&st)[NS + 1],
+                                                    uint32_t *line, uint32_t *sh,
+                                                    uint32_t (&pa)[NQ], uint32_t (&pb)[NQ])
 {
     constexpr int NW = WG / 64;
+    uint32_t *shs = sh + 2 * NQ * NW + 2;
     const uint32_t wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i <= NS; ++i)
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)st[i], off);
+            st[i] = i < NS ? st[i] + o : (o > st[i] ? o : st[i]);
+        }
     unsigned long long ba[NQ], bb[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -236,6 +250,11 @@ __device__ __forceinline__ void block_append2_rounds(uint32_t *ctr, const bool (
             sh[q * NW + wave] = (uint32_t)__popcll(ba[q]);
             sh[(NQ + q) * NW + wave] = (uint32_t)__popcll(bb[q]);
         }
+    }
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int i = 0; i <= NS; ++i)
+            shs[i * NW + wave] = st[i];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -253,6 +272,16 @@ __device__ __forceinline__ void block_append2_rounds(uint32_t *ctr, const bool (
                             ((unsigned long long)tb << 32) | (unsigned long long)ta);
         sh[2 * NQ * NW] = (uint32_t)old;
         sh[2 * NQ * NW + 1] = (uint32_t)(old >> 32);
+#pragma unroll
+        for (int i = 0; i <= NS; ++i) {
+            uint32_t x = shs[i * NW];
+            for (int w = 1; w < NW; ++w) {
+                const uint32_t o = shs[i * NW + w];
+                x = i < NS ? x + o : (o > x ? o : x);
+            }
+            if (x)
+                i < NS ? (void)atomicAdd(line + i, x) : (void)atomicMax(line + i, x);
+        }
     }
     __syncthreads();
     const unsigned long long lt = lanemask_lt();
@@ -260,37 +289,6 @@ __device__ __forceinline__ void block_append2_rounds(uint32_t *ctr, const bool (
     for (int q = 0; q < NQ; ++q) {
         pa[q] = sh[2 * NQ * NW] + sh[q * NW + wave] + (uint32_t)__popcll(ba[q] & lt);
         pb[q] = sh[2 * NQ * NW + 1] + sh[(NQ + q) * NW + wave] + (uint32_t)__popcll(bb[q] & lt);
-    }
-    __syncthreads();
-}
-
-// Workgroup sums of NS values and maximum of one more; results valid in
-// thread 0.  sh holds (NS + 1) * WG/64 words.
-template <int NS>
-__device__ __forceinline__ void block_reduce(uint32_t (&v)[NS + 1], uint32_t *sh)
-{
-    const uint32_t wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i <= NS; ++i) {
-        uint32_t x = v[i];
-        for (int off = 32; off > 0; off >>= 1) {
-            const uint32_t o = (uint32_t)__shfl_xor((int)x, off);
-            x = i < NS ? x + o : (o > x ? o : x);
-        }
-        if (lane_id() == 0)
-            sh[i * (WG / 64) + wave] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i <= NS; ++i) {
-            uint32_t x = sh[i * (WG / 64)];
-            for (int w = 1; w < WG / 64; ++w) {
-                const uint32_t o = sh[i * (WG / 64) + w];
-                x = i < NS ? x + o : (o > x ? o : x);
-            }
-            v[i] = x;
-        }
     }
     __syncthreads();
 }
@@ -1534,7 +1532,7 @@ __device__ __forceinline__ uint32_t mask_dwords(const Job *J, uint32_t p, uint32
 template <int NQ>
 __device__ __forceinline__ void prune_core(const Job *J, JobState *st, LRec (&r)[NQ],
                                            const bool (&valid)[NQ], const uint32_t (&words)[NQ],
-                                           uint32_t *sh_app, uint32_t *sh_red)
+                                           uint32_t *sh_app)
 {
     const uint32_t E = st->epoch;
     bool keep[NQ], promoted[NQ];
@@ -1580,24 +1578,16 @@ __device__ __forceinline__ void prune_core(const Job *J, JobState *st, LRec (&r)
     uint4 *next = st->parity ? J->live0 : J->live1;
     uint32_t *nbox = st->parity ? J->newbox0 : J->newbox1;
     uint32_t pos[NQ], npos[NQ];
-    block_append2_rounds<NQ>(J->ctrs + CTR_APPEND, keep, promoted, sh_app, pos, npos);
+    uint32_t v[6] = {nwords, nitems, npro, npru, nsol, rem};  // in CTR_* order
+    block_append2_stats<NQ, 5>(J->ctrs + CTR_APPEND, keep, promoted, v,
+                               J->ctrs + (blockIdx.x & (CTR_LINES - 1u)) * CTR_STRIDE, sh_app,
+                               pos, npos);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         if (keep[q])
             store_rec(next, pos[q], r[q]);
         if (promoted[q])
             nbox[npos[q]] = r[q].p;
-    }
-    uint32_t v[6] = {nwords, nitems, npro, npru, nsol, rem};  // in CTR_* order
-    block_reduce<5>(v, sh_red);
-    if (threadIdx.x == 0) {
-        uint32_t *c = J->ctrs + (blockIdx.x & (CTR_LINES - 1u)) * CTR_STRIDE;
-#pragma unroll
-        for (int i = 0; i < 5; ++i)
-            if (v[i])
-                atomicAdd(c + i, v[i]);
-        if (v[5])
-            atomicMax(c + CTR_MAX_REM, v[5]);
     }
 }
 
@@ -1613,7 +1603,7 @@ __device__ __forceinline__ void prune_core(const Job *J, JobState *st, LRec (&r)
 // candidate with the total.  Row bitmaps: k_count has added the block's
 // counts to the pool; ZP * WG survivors are pruned.  Every thread calls.
 __device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uint64_t *tile,
-                                               uint32_t *sh_app, uint32_t *sh_red)
+                                               uint32_t *sh_app)
 {
     JobState *st = J->st;
     const uint4 *cur = st->parity ? J->live1 : J->live0;
@@ -1634,7 +1624,7 @@ __device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uin
             r[q].sc += 1u;
             words[q] = valid[q] ? mask_dwords(J, r[q].p, NONE) : 0u;
         }
-        prune_core<ZP>(J, st, r, valid, words, sh_app, sh_red);
+        prune_core<ZP>(J, st, r, valid, words, sh_app);
         return;
     }
     if (st->cmode == 1) {
@@ -1650,7 +1640,7 @@ __device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uin
             r[0].sc += 1u;
             valid[0] = (threadIdx.x & 63u) == 0u;  // the wave's first lane prunes it
         }
-        prune_core<1>(J, st, r, valid, words, sh_app, sh_red);
+        prune_core<1>(J, st, r, valid, words, sh_app);
         return;
     }
     const uint32_t n_cg = st->n_ct;
@@ -1725,7 +1715,7 @@ __device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uin
         r[q].sc += 1u;
     }
     const uint32_t words[VT_CPT] = {};  // a figure of the row-bitmap count only
-    prune_core<VT_CPT>(J, st, r, valid, words, sh_app, sh_red);
+    prune_core<VT_CPT>(J, st, r, valid, words, sh_app);
 }
 
 // Copy W 64-bit words (the loads of a group of eight are issued together).
@@ -1940,7 +1930,7 @@ constexpr uint32_t REC = 12;
 // threads over LDS tiles of the block (many), and pruned as a dashed circle
 // seen on one block.  Every thread of the workgroup calls.
 __device__ __forceinline__ void candgen_stop(const Job *J, unsigned long long chunk, uint64_t *lds, uint32_t *sh_app,
-                             uint32_t *sh_red, uint32_t *sh_cnt)
+                             uint32_t *sh_cnt)
 {
     JobState *st = J->st;
     const uint32_t W = J->W;
@@ -2108,7 +2098,7 @@ __device__ __forceinline__ void candgen_stop(const Job *J, unsigned long long ch
     uint32_t words[1] = {stored && !vert ? mask_dwords(J, p, J->l1[a]) : 0u};
     if (stored && !vert)
         J->psupp[np] = cnt;  // row bitmaps keep the running total in the pool
-    prune_core<1>(J, st, r, ok, words, sh_app, sh_red);
+    prune_core<1>(J, st, r, ok, words, sh_app);
 }
 
 // One stop for every job in the table: MakeCandidates chunks (with the new
@@ -2120,8 +2110,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     const Job *__restrict__ jobs, Plan *plan)
 {
     __shared__ uint64_t tile[VT_WORDS];
-    __shared__ uint32_t sh_app[2 * VT_CPT * (WG / 64) + 2];
-    __shared__ uint32_t sh_red[6 * (WG / 64)];
+    __shared__ uint32_t sh_app[2 * VT_CPT * (WG / 64) + 2 + 6 * (WG / 64)];
     __shared__ uint32_t sh_cnt[WG];
     __shared__ unsigned long long shc[WG / 64];
     __shared__ uint32_t sh_flag;
@@ -2132,11 +2121,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         if (it < ncg) {
             const uint32_t j = find_job(plan->pre_cg, njobs, it);
             // job 0's prefix is 0: no load (and no wait for it) on a single job
-            candgen_stop(jobs + j, j ? it - plan->pre_cg[j] : it, tile, sh_app, sh_red, sh_cnt);
+            candgen_stop(jobs + j, j ? it - plan->pre_cg[j] : it, tile, sh_app, sh_cnt);
         } else {
             const uint32_t v = (uint32_t)(it - ncg);
             const uint32_t j = find_job(plan->pre_countv, njobs, v);
-            survivors_stop(jobs + j, j ? v - plan->pre_countv[j] : v, tile, sh_app, sh_red);
+            survivors_stop(jobs + j, j ? v - plan->pre_countv[j] : v, tile, sh_app);
         }
     }
     // Everything the serial part reads from this launch's other workgroups
