@@ -32,6 +32,11 @@ constexpr int VT_CPT = 4;                // bitset count: candidates per thread 
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 constexpr int ZP = 2;                    // row-bitmap survivors pruned per thread
 
+// s_waitcnt operand (gfx9 encoding) that waits for every outstanding vector
+// memory operation of the wave -- loads, stores and atomics -- and for
+// nothing else: vmcnt 0, expcnt 7, lgkmcnt 15.
+constexpr int WAIT_VM0 = 0x0F70;
+
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
 __device__ __forceinline__ unsigned long long lanemask_lt()
@@ -266,12 +271,9 @@ __device__ __forceinline__ void block_append2_stats(uint32_t *ctr, const bool (&
             ta += ca;
             tb += cb;
         }
-        unsigned long long old = 0;
-        if (ta | tb)
-            old = atomicAdd((unsigned long long *)ctr,
-                            ((unsigned long long)tb << 32) | (unsigned long long)ta);
-        sh[2 * NQ * NW] = (uint32_t)old;
-        sh[2 * NQ * NW + 1] = (uint32_t)(old >> 32);
+        // the statistics, then the append; both are complete before the
+        // positions are handed out, so that the workgroup can arrive
+        // without waiting for its stores
 #pragma unroll
         for (int i = 0; i <= NS; ++i) {
             uint32_t x = shs[i * NW];
@@ -282,6 +284,13 @@ __device__ __forceinline__ void block_append2_stats(uint32_t *ctr, const bool (&
             if (x)
                 i < NS ? (void)atomicAdd(line + i, x) : (void)atomicMax(line + i, x);
         }
+        unsigned long long old = 0;
+        if (ta | tb)
+            old = atomicAdd((unsigned long long *)ctr,
+                            ((unsigned long long)tb << 32) | (unsigned long long)ta);
+        __builtin_amdgcn_s_waitcnt(WAIT_VM0);
+        sh[2 * NQ * NW] = (uint32_t)old;
+        sh[2 * NQ * NW + 1] = (uint32_t)(old >> 32);
     }
     __syncthreads();
     const unsigned long long lt = lanemask_lt();
@@ -684,11 +693,6 @@ __device__ __forceinline__ void plan_stop(const Job *J, JobState &s, const PlanT
         *items_stop = (K + ZP * WG - 1u) / (ZP * WG);
     }
 }
-
-// s_waitcnt operand (gfx9 encoding) that waits for every outstanding vector
-// memory operation of the wave -- loads, stores and atomics -- and for
-// nothing else: vmcnt 0, expcnt 7, lgkmcnt 15.
-constexpr int WAIT_VM0 = 0x0F70;
 
 // One job's turn in the serial part of a launch: complete stop e (finish:
 // after every work item of the stop kernel) or begin the first stop of a
@@ -1709,8 +1713,10 @@ __device__ __forceinline__ void survivors_stop(const Job *J, uint32_t local, uin
     }
 #pragma unroll
     for (int q = 0; q < VT_CPT; ++q) {
-        if (valid[q] && (uint64_t)r[q].supp + cnt[q] > J->n)  // a support never exceeds n
+        if (valid[q] && (uint64_t)r[q].supp + cnt[q] > J->n) {  // a support never exceeds n
             atomicAdd(&st->asserts, 1u);
+            __builtin_amdgcn_s_waitcnt(WAIT_VM0);  // complete before the arrival
+        }
         r[q].supp += cnt[q];
         r[q].sc += 1u;
     }
@@ -2131,15 +2137,15 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     // Everything the serial part reads from this launch's other workgroups
     // is a device-scope atomic (the counter lines: pool growth, list
     // appends, statistics; asserts) and is read with device-scope atomic
-    // loads.  The returning ones
-    // have completed before their results were used; the no-return ones (the
-    // counter lines, asserts) are waited for here, in every wave, so that all of this
-    // workgroup's updates are done before its arrival is counted (a
-    // workgroup barrier alone does not wait for memory operations).  Plain
-    // stores of this launch (records, standings, counts) are read only by
-    // later launches.  A full device-scope release would also write back
-    // this XCD's L2, which costs tens of microseconds per launch.
-    __builtin_amdgcn_s_waitcnt(WAIT_VM0);
+    // loads.  Each is complete before its workgroup passes the barrier below:
+    // the returning ones because their results were used, the no-return
+    // ones (Prune's statistics, asserts) because the thread that issued them
+    // waited for them (s_waitcnt vmcnt(0): a workgroup barrier alone does
+    // not wait for memory operations).  Plain stores of this launch
+    // (records, standings, counts) are read only by later launches, so the
+    // workgroup arrives without waiting for them.  A device-scope release
+    // would also write back this XCD's L2, which costs tens of microseconds
+    // per launch.
     __syncthreads();
     if (threadIdx.x == 0)
         sh_flag = arrive_last(plan->tickets, total < gridDim.x ? (total ? (uint32_t)total : 1u)
